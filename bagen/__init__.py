@@ -1,0 +1,415 @@
+"""Seeded synthetic bundle-adjustment windows.
+
+This module only *synthesises inputs*: keyframe poses, camera rigs, landmarks and
+noisy pixel observations shaped like the sliding-window local map of the paper's
+3D module (Sec. 2.2: the last N keyframe poses, the landmarks they see and the 2D
+observations o of landmark j by camera k at pose i).  It holds none of the
+solver's arithmetic.  To synthesise pixels it needs a pinhole projection; that
+is written here independently (``_project``) so that the oracle's own projection
+can be checked against it (noiseless ground truth must give zero residual).
+
+Conventions
+-----------
+* Camera frame: x right, y down, z forward.  Pinhole without distortion.
+* A pose is stored as a 3x4 ``[R | t]`` base-from-world transform (x_b = R x_w + t).
+* Extrinsics are 3x4 camera-from-base transforms (x_c = R_cb x_b + t_cb).
+* Every random draw comes from ``numpy.random.default_rng(seed)``; the default
+  seed of window ``w`` of workload ``cfg`` is ``1000 * cfg + w``.
+* Observations are emitted in a random order (not landmark-major), so that the
+  solver's own ordering is exercised.
+
+Workloads (sizes as stated for each):
+  1  mono, 5 keyframes 0.5 m apart along x, 200 landmarks tracked 3-5 frames
+  2  stereo, 20 keyframes, 5000 landmarks, ~60k observations, 2 % outliers
+  3  256 mono windows of uneven size (5-30 keyframes, 500-8000 landmarks)
+  4  32-camera rig, 10 rig poses on a circle, 20000 landmarks, ~300k observations
+  5  64 mono windows, 10 keyframes, 2000 landmarks, every visible frame observed
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+__all__ = ["Window", "make_window", "make_workload", "tiny_window", "WORKLOAD_NAMES"]
+
+WORKLOAD_NAMES = {
+    1: "mono-5kf-200lm",
+    2: "stereo-20kf-5000lm",
+    3: "batch-256-mono-uneven",
+    4: "rig-32cam-10pose-20000lm",
+    5: "adjoint-64x-mono-10kf-2000lm",
+}
+
+
+@dataclasses.dataclass
+class Window:
+    """One sliding-window bundle-adjustment problem (all arrays float64/int32)."""
+
+    intrinsics: np.ndarray      # (C, 4) fx, fy, cx, cy
+    extrinsics: np.ndarray      # (C, 3, 4) camera-from-base
+    image_size: np.ndarray      # (C, 2) width, height
+    poses_gt: np.ndarray        # (N, 3, 4) base-from-world
+    points_gt: np.ndarray       # (M, 3) world
+    poses_init: np.ndarray      # (N, 3, 4)
+    points_init: np.ndarray     # (M, 3)
+    obs_pose: np.ndarray        # (n_obs,) int32
+    obs_point: np.ndarray       # (n_obs,) int32
+    obs_cam: np.ndarray         # (n_obs,) int32
+    obs_uv: np.ndarray          # (n_obs, 2) pixels (noisy)
+    obs_w: np.ndarray           # (n_obs,) observation weights
+    outlier: np.ndarray         # (n_obs,) bool, True where the pixel was replaced
+    pose_fixed: np.ndarray      # (N,) uint8
+    max_iters: int = 10
+    huber_delta: float = 1.0
+    lambda_init: float = 1e-3
+    mixed: bool = False
+    name: str = ""
+
+    @property
+    def n_poses(self) -> int:
+        return int(self.poses_gt.shape[0])
+
+    @property
+    def n_points(self) -> int:
+        return int(self.points_gt.shape[0])
+
+    @property
+    def n_cams(self) -> int:
+        return int(self.intrinsics.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_pose.shape[0])
+
+    def copy(self) -> "Window":
+        return dataclasses.replace(self, **{f.name: (getattr(self, f.name).copy()
+                                                    if isinstance(getattr(self, f.name), np.ndarray)
+                                                    else getattr(self, f.name))
+                                           for f in dataclasses.fields(self)})
+
+
+# ---------------------------------------------------------------------------
+# generator-local geometry (independent of the solver and of the oracle)
+# ---------------------------------------------------------------------------
+
+def _rot_axis(axis: np.ndarray, angle: float) -> np.ndarray:
+    """Rotation about a unit axis (Rodrigues' formula, generator-local)."""
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(angle) * K + (1 - math.cos(angle)) * (K @ K)
+
+
+def _rot_y(angle: float) -> np.ndarray:
+    c, s = math.cos(angle), math.sin(angle)
+    return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+
+
+def _pose_from_cam_to_world(R_wc: np.ndarray, centre: np.ndarray) -> np.ndarray:
+    R = R_wc.T
+    t = -R @ centre
+    return np.concatenate([R, t[:, None]], axis=1)
+
+
+def _to_cam(pose: np.ndarray, ext: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """World points (..., 3) to camera coordinates through base pose and extrinsic."""
+    xb = pts @ pose[:, :3].T + pose[:, 3]
+    return xb @ ext[:, :3].T + ext[:, 3]
+
+
+def _project(K: np.ndarray, xc: np.ndarray) -> np.ndarray:
+    z = xc[..., 2]
+    return np.stack([K[0] * xc[..., 0] / z + K[2], K[1] * xc[..., 1] / z + K[3]], axis=-1)
+
+
+def _visible(K, size, xc, min_z=0.1):
+    uv = _project(K, np.where(xc[..., 2:3] > min_z, xc, 1.0))
+    return ((xc[..., 2] > min_z) & (uv[..., 0] >= 0) & (uv[..., 0] < size[0])
+            & (uv[..., 1] >= 0) & (uv[..., 1] < size[1]))
+
+
+def _random_unit(rng, n=None):
+    v = rng.normal(size=(3,) if n is None else (n, 3))
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _perturb_poses(rng, poses, fixed, rot=0.05, trans=0.05):
+    """Rotate each free pose by `rot` rad about a random axis and shift its
+    translation by `trans` m along a random direction."""
+    out = poses.copy()
+    for i in range(poses.shape[0]):
+        if fixed[i]:
+            continue
+        Rd = _rot_axis(_random_unit(rng), rot)
+        out[i, :, :3] = Rd @ poses[i, :, :3]
+        out[i, :, 3] = Rd @ poses[i, :, 3] + trans * _random_unit(rng)
+    return out
+
+
+def _assemble(rng, *, intr, ext, size, poses, points, tracks, sigma, outlier_frac,
+              fixed, max_iters, mixed, name, point_sigma=0.1, pose_rot=0.05,
+              pose_trans=0.05) -> Window:
+    """tracks: list of (point index, pose index, cam index) int arrays."""
+    op, oj, ok = (np.asarray(a, np.int32) for a in tracks)
+    uv = np.empty((op.shape[0], 2))
+    for k in range(intr.shape[0]):
+        for i in range(poses.shape[0]):
+            m = (ok == k) & (op == i)
+            if m.any():
+                uv[m] = _project(intr[k], _to_cam(poses[i], ext[k], points[oj[m]]))
+    uv += rng.normal(scale=sigma, size=uv.shape)
+    outl = np.zeros(op.shape[0], bool)
+    if outlier_frac > 0:
+        outl = rng.random(op.shape[0]) < outlier_frac
+        w = size[ok[outl], 0]
+        h = size[ok[outl], 1]
+        uv[outl, 0] = rng.random(outl.sum()) * w
+        uv[outl, 1] = rng.random(outl.sum()) * h
+    order = rng.permutation(op.shape[0])
+    fixed_arr = np.zeros(poses.shape[0], np.uint8)
+    fixed_arr[list(fixed)] = 1
+    return Window(
+        intrinsics=np.asarray(intr, float), extrinsics=np.asarray(ext, float),
+        image_size=np.asarray(size, float), poses_gt=poses, points_gt=points,
+        poses_init=_perturb_poses(rng, poses, fixed_arr, pose_rot, pose_trans),
+        points_init=points + rng.normal(scale=point_sigma, size=points.shape),
+        obs_pose=op[order], obs_point=oj[order], obs_cam=ok[order], obs_uv=uv[order],
+        obs_w=np.ones(op.shape[0]), outlier=outl[order], pose_fixed=fixed_arr,
+        max_iters=max_iters, mixed=mixed, name=name)
+
+
+# ---------------------------------------------------------------------------
+# mono windows (workloads 1, 3, 5)
+# ---------------------------------------------------------------------------
+
+_MONO_K = np.array([458.0, 458.0, 367.0, 248.0])
+_MONO_SIZE = np.array([752.0, 480.0])
+
+
+def _mono_window(rng, n_kf, n_lm, *, track, x_hi, min_vis, fixed, max_iters, mixed,
+                 name, sigma=0.5) -> Window:
+    """Keyframes 0.5 m apart along x with U(-5, 5) deg yaw; landmarks uniform in the
+    box x in [-4, x_hi], y in [-3, 3], z in [2, 20] m.
+
+    track: ("subset", lo, hi) -> random subset of U{lo..min(hi, #visible)} visible
+           frames; ("all",) -> every visible frame.
+    """
+    yaw = rng.uniform(-5.0, 5.0, n_kf) * math.pi / 180.0
+    poses = np.stack([_pose_from_cam_to_world(_rot_y(yaw[i]), np.array([0.5 * i, 0.0, 0.0]))
+                      for i in range(n_kf)])
+    ext = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)[None]
+    intr, size = _MONO_K[None], _MONO_SIZE[None]
+    pts, trk_p, trk_j = [], [], []
+    n_have = 0
+    while n_have < n_lm:
+        n_c = max(256, 2 * (n_lm - n_have))
+        cand = np.stack([rng.uniform(-4.0, x_hi, n_c), rng.uniform(-3.0, 3.0, n_c),
+                         rng.uniform(2.0, 20.0, n_c)], axis=1)
+        vis = np.stack([_visible(intr[0], size[0], _to_cam(poses[i], ext[0], cand))
+                        for i in range(n_kf)], axis=1)                     # (n_c, K)
+        nvis = vis.sum(1)
+        keep = np.nonzero(nvis >= min_vis)[0][: n_lm - n_have]
+        for c in keep:
+            frames = np.nonzero(vis[c])[0]
+            if track[0] == "subset":
+                L = int(rng.integers(track[1], min(track[2], frames.size) + 1))
+                frames = np.sort(rng.choice(frames, size=L, replace=False))
+            j = n_have
+            pts.append(cand[c])
+            trk_p.append(frames)
+            trk_j.append(np.full(frames.size, j))
+            n_have += 1
+    points = np.asarray(pts)
+    op = np.concatenate(trk_p)
+    oj = np.concatenate(trk_j)
+    ok = np.zeros_like(op)
+    return _assemble(rng, intr=intr, ext=ext, size=size, poses=poses, points=points,
+                     tracks=(op, oj, ok), sigma=sigma, outlier_frac=0.0, fixed=fixed,
+                     max_iters=max_iters, mixed=mixed, name=name)
+
+
+def _workload1(rng, w):
+    return _mono_window(rng, 5, 200, track=("subset", 3, 5), x_hi=6.0, min_vis=3,
+                        fixed=[0], max_iters=10, mixed=False, name=f"{WORKLOAD_NAMES[1]}")
+
+
+def _workload3(rng, w):
+    n_kf = int(rng.integers(5, 31))
+    n_lm = int(rng.integers(500, 8001))
+    return _mono_window(rng, n_kf, n_lm, track=("subset", 2, 10),
+                        x_hi=0.5 * (n_kf - 1) + 4.0, min_vis=2, fixed=[0], max_iters=15,
+                        mixed=True, name=f"{WORKLOAD_NAMES[3]}[{w}]")
+
+
+def _workload5(rng, w):
+    return _mono_window(rng, 10, 2000, track=("all",), x_hi=8.5, min_vis=3, fixed=[0, 1],
+                        max_iters=50, mixed=True, name=f"{WORKLOAD_NAMES[5]}[{w}]")
+
+
+# ---------------------------------------------------------------------------
+# stereo window (workload 2)
+# ---------------------------------------------------------------------------
+
+def _workload2(rng, w, n_kf=20, n_lm=5000, geom_p=0.14):
+    K = np.array([718.0, 718.0, 607.0, 185.0])
+    size = np.array([1241.0, 376.0])
+    intr = np.stack([K, K])
+    sizes = np.stack([size, size])
+    ext = np.zeros((2, 3, 4))
+    ext[0, :, :3] = np.eye(3)
+    ext[1, :, :3] = np.eye(3)
+    ext[1, :, 3] = [-0.54, 0.0, 0.0]
+    yaw = np.zeros(n_kf)
+    centres = np.zeros((n_kf, 3))
+    for i in range(1, n_kf):
+        yaw[i] = yaw[i - 1] + rng.uniform(-1.0, 1.0) * math.pi / 180.0
+        centres[i] = centres[i - 1] + _rot_y(yaw[i - 1]) @ np.array([0.0, 0.0, 1.0])
+    poses = np.stack([_pose_from_cam_to_world(_rot_y(yaw[i]), centres[i]) for i in range(n_kf)])
+    pts, op, oj, ok = [], [], [], []
+    while len(pts) < n_lm:
+        # track length 2 + Geom(p) (failures before the first success), at most 15
+        # frames; the anchor pixel and log-uniform depth are drawn in the track's
+        # last frame e, and the track runs back from e while both views see it.
+        L_want = min(2 + int(rng.geometric(geom_p)) - 1, 15, n_kf)
+        e = int(rng.integers(1, n_kf))
+        u = rng.uniform(0, size[0])
+        v = rng.uniform(0, size[1])
+        depth = math.exp(rng.uniform(math.log(3.0), math.log(60.0)))
+        xc = np.array([(u - K[2]) / K[0] * depth, (v - K[3]) / K[1] * depth, depth])
+        R = poses[e, :, :3]
+        p = R.T @ (xc - poses[e, :, 3])
+        L = 0
+        while L < L_want and e - L >= 0 and all(
+                _visible(K, size, _to_cam(poses[e - L], ext[k], p[None]))[0] for k in range(2)):
+            L += 1
+        if L < 2:
+            continue
+        j = len(pts)
+        pts.append(p)
+        for i in range(e - L + 1, e + 1):
+            for k in range(2):
+                op.append(i)
+                oj.append(j)
+                ok.append(k)
+    return _assemble(rng, intr=intr, ext=ext, size=sizes, poses=poses, points=np.asarray(pts),
+                     tracks=(op, oj, ok), sigma=0.7, outlier_frac=0.02, fixed=[0],
+                     max_iters=10, mixed=True, name=WORKLOAD_NAMES[2])
+
+
+# ---------------------------------------------------------------------------
+# 32-camera rig (workload 4)
+# ---------------------------------------------------------------------------
+
+def _workload4(rng, w, n_cam=32, n_pose=10, n_lm=20000, target_obs=300_000):
+    K = np.array([400.0, 400.0, 320.0, 240.0])
+    size = np.array([640.0, 480.0])
+    intr = np.tile(K, (n_cam, 1))
+    sizes = np.tile(size, (n_cam, 1))
+    ext = np.zeros((n_cam, 3, 4))
+    for k in range(n_cam):
+        z = _random_unit(rng)
+        a = _random_unit(rng)
+        x = np.cross(a, z)
+        x /= np.linalg.norm(x)
+        y = np.cross(z, x)
+        roll = rng.uniform(0, 2 * math.pi)
+        R_bc = np.stack([x, y, z], axis=1) @ _rot_axis(np.array([0.0, 0.0, 1.0]), roll)
+        R_cb = R_bc.T
+        ext[k, :, :3] = R_cb
+        ext[k, :, 3] = -R_cb @ (0.3 * z)
+    radius, step = 2.0, 0.4
+    poses = []
+    for i in range(n_pose):
+        th = i * step / radius
+        centre = np.array([radius * math.sin(th), 0.0, radius * math.cos(th)])
+        fwd = np.array([math.cos(th), 0.0, -math.sin(th)])       # tangent
+        down = np.array([0.0, 1.0, 0.0])
+        right = np.cross(down, fwd)
+        R_wb = np.stack([right, down, fwd], axis=1)
+        poses.append(_pose_from_cam_to_world(R_wb, centre))
+    poses = np.stack(poses)
+
+    def sample(n):
+        d = _random_unit(rng, n)
+        r = rng.uniform(12.0, 15.0, n)
+        p = d * r[:, None]
+        vis = np.zeros((n, n_pose, n_cam), bool)
+        for i in range(n_pose):
+            for k in range(n_cam):
+                vis[:, i, k] = _visible(K, size, _to_cam(poses[i], ext[k], p))
+        return p, vis
+
+    p0, v0 = sample(n_lm)
+    q = min(1.0, target_obs / max(1, int(v0.sum())))
+    pts, op, oj, ok = [], [], [], []
+    p, vis = p0, v0
+    while len(pts) < n_lm:
+        keep = vis & (rng.random(vis.shape) < q)
+        npose = keep.any(axis=2).sum(axis=1)
+        good = np.nonzero(npose >= 2)[0][: n_lm - len(pts)]
+        for c in good:
+            j = len(pts)
+            pts.append(p[c])
+            ii, kk = np.nonzero(keep[c])
+            op.extend(ii.tolist())
+            ok.extend(kk.tolist())
+            oj.extend([j] * ii.size)
+        if len(pts) < n_lm:
+            p, vis = sample(max(64, 2 * (n_lm - len(pts))))
+    return _assemble(rng, intr=intr, ext=ext, size=sizes, poses=poses, points=np.asarray(pts),
+                     tracks=(op, oj, ok), sigma=0.5, outlier_frac=0.0, fixed=[0],
+                     max_iters=10, mixed=True, name=WORKLOAD_NAMES[4])
+
+
+_MAKERS = {1: _workload1, 2: _workload2, 3: _workload3, 4: _workload4, 5: _workload5}
+_COUNTS = {1: 1, 2: 1, 3: 256, 4: 1, 5: 64}
+
+
+def make_window(cfg: int, index: int = 0, seed: Optional[int] = None) -> Window:
+    """Window `index` of workload `cfg` (seed defaults to 1000*cfg + index)."""
+    rng = np.random.default_rng(1000 * cfg + index if seed is None else seed)
+    return _MAKERS[cfg](rng, index)
+
+
+def make_workload(cfg: int, count: Optional[int] = None) -> List[Window]:
+    n = _COUNTS[cfg] if count is None else count
+    return [make_window(cfg, w) for w in range(n)]
+
+
+def tiny_window(seed: int = 0, n_kf: int = 3, n_lm: int = 12, stereo: bool = False,
+                noise: float = 0.5, fixed=(0,), outlier_frac: float = 0.0,
+                max_iters: int = 10) -> Window:
+    """A small window for brute-force checks: mono (or stereo, 0.3 m baseline)
+    keyframes 0.5 m apart, landmarks in a 3-8 m box, every visible frame observed."""
+    rng = np.random.default_rng(seed)
+    yaw = rng.uniform(-5.0, 5.0, n_kf) * math.pi / 180.0
+    poses = np.stack([_pose_from_cam_to_world(_rot_y(yaw[i]), np.array([0.5 * i, 0.0, 0.0]))
+                      for i in range(n_kf)])
+    n_cam = 2 if stereo else 1
+    ext = np.zeros((n_cam, 3, 4))
+    ext[:, :, :3] = np.eye(3)
+    if stereo:
+        ext[1, :, 3] = [-0.3, 0.0, 0.0]
+    intr = np.tile(_MONO_K, (n_cam, 1))
+    size = np.tile(_MONO_SIZE, (n_cam, 1))
+    pts, op, oj, ok = [], [], [], []
+    while len(pts) < n_lm:
+        p = np.array([rng.uniform(-1.0, 0.5 * n_kf + 1.0), rng.uniform(-1.5, 1.5),
+                      rng.uniform(3.0, 8.0)])
+        views = [(i, k) for i in range(n_kf) for k in range(n_cam)
+                 if _visible(intr[k], size[k], _to_cam(poses[i], ext[k], p[None]))[0]]
+        if len({v[0] for v in views}) < 2:
+            continue
+        j = len(pts)
+        pts.append(p)
+        for i, k in views:
+            op.append(i)
+            oj.append(j)
+            ok.append(k)
+    return _assemble(rng, intr=intr, ext=ext, size=size, poses=poses, points=np.asarray(pts),
+                     tracks=(op, oj, ok), sigma=noise, outlier_frac=outlier_frac,
+                     fixed=list(fixed), max_iters=max_iters, mixed=False,
+                     name=f"tiny-{n_kf}kf-{n_lm}lm{'-stereo' if stereo else ''}")
