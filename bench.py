@@ -1,0 +1,318 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X bundle adjuster.
+
+One step = one batched mixed-precision LM solve (15 attempts per window) of
+256 independent mono windows of uneven size (5-30 keyframes, 500-8000
+landmarks, tracks of 2-10 frames, about 6.2M observations), replayed from a
+HIP graph that also restores the initial state (two device-to-device copies).
+Inputs are resident in HBM before the timed region.
+
+Printed as one JSON line:
+  value              LM attempts per second over all windows (whole job)
+  obs_jacobians_per_s  n_obs * (1 + accepted) per window, per second
+  plain_fp64         the same 256 windows solved one at a time in FP64 (ba_solve),
+                     sequentially on one stream: LM attempts per second and the
+                     speed-up of the batched mixed solve over it
+  adjoint            64 windows of 10 keyframes / 2000 landmarks, forward solve
+                     then the implicit-function adjoint: observations per second
+  rms_check          final RMS of sampled windows against the FP64 oracle (1e-3 px)
+  roofline           the linearise + Schur kernel (pass A) against the FP32 ALU peak
+  cpu_baseline       the FP64 oracle on the host cores, on a bounded sample
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LM iters/s & obs-Jacobians/s, batched+adjoint vs plain FP64, at oracle RMS"
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
+N_WINDOWS = 256
+ITERS = 15
+
+# algorithmic flops of pass A, counted from the kernel source per unit of work:
+#   per observation: transform (double) + projection + Huber + 2x6 / 2x3 Jacobians
+#                    + the U, W, V, gradient block products          350
+#   per free pair  : Z = W L^-T |D|^-1/2 (6 rows) + reduced rhs        90
+#   per landmark   : sum of the pair blocks, damping, 3x3 L D L^T      60
+#   per Schur block: off-diagonal 6x6 (36 x 3 FMA + scaling)          234
+#                    diagonal (21 entries)                            144
+FLOP_OBS, FLOP_FREE_PAIR, FLOP_LM, FLOP_BLK_OFF, FLOP_BLK_DIAG = 350, 90, 60, 234, 144
+
+
+def pass_a_flops(infos):
+    f = 0
+    for i in infos:
+        off = i["schur_blocks"] - i["n_free_pairs"]
+        f += (FLOP_OBS * i["n_obs"] + FLOP_FREE_PAIR * i["n_free_pairs"] + FLOP_LM * i["n_points"]
+              + FLOP_BLK_OFF * off + FLOP_BLK_DIAG * i["n_free_pairs"])
+    return f
+
+
+def _cpu_worker(index):
+    """Oracle solve of one window (spawned process; no torch, one BLAS thread)."""
+    import numpy as np  # noqa: F401
+    import bagen
+    import oracle
+    w = bagen.make_window(3, index)
+    prob = oracle.Problem.from_window(w)
+    st = oracle.LMSettings(max_iters=ITERS, lambda_init=w.lambda_init, huber_delta=w.huber_delta)
+    t = time.perf_counter()
+    res = oracle.lm_solve(w.poses_init, w.points_init, prob, st, backend="schur")
+    dt = time.perf_counter() - t
+    return index, dt, oracle.rms(res.poses, res.points, prob)
+
+
+def cpu_baseline(sample):
+    import multiprocessing as mp
+    procs = max(1, min(len(sample), os.cpu_count() or 1, 16))
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    t = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        out = pool.map(_cpu_worker, sample)
+    wall = time.perf_counter() - t
+    return out, wall, procs
+
+
+def kernels_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2506_04359_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(per_launch_flops_units):
+    """HBM bytes of one pass-A launch from the committed rocprofv3 counter
+    summary, when it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pass_a_batch256_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernels_sha") != kernels_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 baseline")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import bagen
+    import paper_2506_04359_amd as ba
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    ws = [bagen.make_window(3, i) for i in range(N_WINDOWS)]
+    log(f"generated {N_WINDOWS} windows in {time.time() - t0:.1f}s, "
+        f"{sum(w.n_obs for w in ws)} observations")
+    wins = [ba.Window.from_problem(w, host_only=True) for w in ws]
+    batch = ba.Batch(wins)
+    infos = [batch.info(k) for k in range(N_WINDOWS)]
+    n_obs = np.array([w.n_obs for w in ws])
+    s_mixed = ba.Settings(max_iters=ITERS, precision=ba.BA_MIXED, lambda_init=1e-3, huber_delta=1.0)
+
+    P0 = torch.tensor(np.concatenate([w.poses_init for w in ws]), dtype=torch.float64, device=dev)
+    L0 = torch.tensor(np.concatenate([w.points_init for w in ws]), dtype=torch.float64, device=dev)
+    uv = torch.tensor(np.concatenate([w.obs_uv for w in ws]), dtype=torch.float64, device=dev)
+    P = P0.clone()
+    L = L0.clone()
+    reports = torch.zeros(48 * N_WINDOWS, dtype=torch.uint8, device=dev)
+
+    chunk = None
+    if not args.no_tune:
+        big = torch.empty(max(batch.workspace_size(s_mixed), 1), dtype=torch.uint8, device=dev)
+        # room for the finest candidate shape
+        batch.set_launch(1024)
+        big = torch.empty(batch.workspace_size(s_mixed) + 256, dtype=torch.uint8, device=dev)
+        chunk = batch.autotune(s_mixed, P, L, uv, None, big)
+        del big
+        log(f"autotuned chunk_obs = {chunk}")
+    ws_bytes = batch.workspace_size(s_mixed)
+    work = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+
+    def step():
+        P.copy_(P0)
+        L.copy_(L0)
+        ba.solve_batched(batch, s_mixed, P, L, uv, None, work, reports)
+
+    with torch.cuda.stream(side):
+        step()                        # eager run before capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        step()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record()
+    for k in range(args.steps):
+        graph.replay()
+        log(f"step {k + 1}/{args.steps} enqueued")
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    rep = ba.parse_reports(reports)
+    assert np.all(rep["iters"] == ITERS), rep["iters"]
+    lm_iters_per_s = N_WINDOWS * ITERS / (ms_per_step / 1e3)
+    obs_jac = float(np.sum(n_obs * (1 + rep["accepted"]))) / (ms_per_step / 1e3)
+    log(f"batched mixed: {ms_per_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), "
+        f"{lm_iters_per_s:.4g} LM iters/s")
+    P_final = P.cpu().numpy()
+    L_final = L.cpu().numpy()
+
+    # per-stage device times (HIP events on the launch stream), same solve
+    P.copy_(P0)
+    L.copy_(L0)
+    stages = batch.profile_stages(s_mixed, P, L, uv, None, work, reports)
+    pass_a_ms = stages["pass_a"] / ITERS
+    flops = pass_a_flops(infos)
+    achieved = flops / (pass_a_ms / 1e3) / 1e12
+    log(f"stages (ms over {ITERS} attempts): {stages}")
+
+    out = {
+        "metric": METRIC, "value": lm_iters_per_s, "unit": "LM iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": bagen.WORKLOAD_NAMES[3], "windows": N_WINDOWS,
+                   "observations": int(n_obs.sum()), "landmarks": int(sum(w.n_points for w in ws)),
+                   "lm_attempts_per_window": ITERS, "precision": "mixed (FP32 bulk, FP64 Cholesky)",
+                   "graph_captured": True, "chunk_obs": chunk},
+        "obs_jacobians_per_s": obs_jac,
+        "stage_ms_per_attempt": {k: v / ITERS for k, v in stages.items()},
+    }
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                       "traffic": traffic_from_profile(flops), "kernel": "k_pass_a<float,256>",
+                       "flops_per_launch": flops, "avg_launch_ms": pass_a_ms}
+
+    # plain FP64: one window at a time on one stream
+    if not args.no_fp64:
+        s64 = ba.Settings(max_iters=ITERS, precision=ba.BA_FP64, lambda_init=1e-3, huber_delta=1.0)
+        singles = [ba.Window.from_problem(w) for w in ws]
+        po = np.cumsum([0] + [w.n_poses for w in ws])
+        lo = np.cumsum([0] + [w.n_points for w in ws])
+        oo = np.cumsum([0] + [w.n_obs for w in ws])
+        need = max(sw.workspace_size(s64) for sw in singles)
+        w64 = torch.empty(need, dtype=torch.uint8, device=dev)
+        rep64 = torch.zeros(48 * N_WINDOWS, dtype=torch.uint8, device=dev)
+        Pw, Lw = P0.clone(), L0.clone()
+        views = [(Pw[po[k]:po[k + 1]], Lw[lo[k]:lo[k + 1]], uv[oo[k]:oo[k + 1]], rep64[48 * k:48 * (k + 1)])
+                 for k in range(N_WINDOWS)]
+        for k in range(2):   # warm-up
+            ba.solve(singles[k], s64, views[k][0], views[k][1], views[k][2], None, w64, views[k][3])
+        Pw.copy_(P0)
+        Lw.copy_(L0)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        for k in range(N_WINDOWS):
+            ba.solve(singles[k], s64, views[k][0], views[k][1], views[k][2], None, w64, views[k][3])
+        f1.record()
+        torch.cuda.synchronize()
+        ms64 = f0.elapsed_time(f1)
+        r64 = ba.parse_reports(rep64)
+        it64 = N_WINDOWS * ITERS / (ms64 / 1e3)
+        out["plain_fp64"] = {"value": it64, "unit": "LM iters/s", "ms_total": ms64,
+                             "obs_jacobians_per_s": float(np.sum(n_obs * (1 + r64["accepted"]))) / (ms64 / 1e3),
+                             "speedup_batched_mixed": lm_iters_per_s / it64}
+        log(f"plain FP64 sequential: {ms64:.1f} ms, {it64:.4g} LM iters/s")
+        P64, L64 = Pw.cpu().numpy(), Lw.cpu().numpy()
+        del singles
+
+    # adjoint on 64 windows of 10 keyframes / 2000 landmarks
+    if not args.no_adjoint:
+        wa = [bagen.make_window(5, i) for i in range(64)]
+        ba_wins = [ba.Window.from_problem(w, host_only=True) for w in wa]
+        badj = ba.Batch(ba_wins)
+        sa = ba.Settings(max_iters=50, precision=ba.BA_MIXED, lambda_init=1e-3, huber_delta=1.0)
+        Pa = torch.tensor(np.concatenate([w.poses_init for w in wa]), dtype=torch.float64, device=dev)
+        La = torch.tensor(np.concatenate([w.points_init for w in wa]), dtype=torch.float64, device=dev)
+        uva = torch.tensor(np.concatenate([w.obs_uv for w in wa]), dtype=torch.float64, device=dev)
+        Pgt = torch.tensor(np.concatenate([w.poses_gt for w in wa]), dtype=torch.float64, device=dev)
+        free = torch.tensor(np.concatenate([1 - w.pose_fixed for w in wa]), dtype=torch.float64, device=dev)
+        wsa = torch.empty(badj.workspace_size(sa), dtype=torch.uint8, device=dev)
+        ba.solve_batched(badj, sa, Pa, La, uva, None, wsa)
+        gP = (2.0 * (Pa - Pgt) * free[:, None, None]).contiguous()     # chordal loss gradient
+        guv = torch.empty_like(uva)
+        gw = torch.empty(uva.shape[0], dtype=torch.float64, device=dev)
+        ba.adjoint(badj, sa, Pa, La, uva, None, gP, None, guv, gw, wsa)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(args.steps):
+            ba.adjoint(badj, sa, Pa, La, uva, None, gP, None, guv, gw, wsa)
+        a1.record()
+        torch.cuda.synchronize()
+        ms_adj = a0.elapsed_time(a1) / args.steps
+        nobs_a = sum(w.n_obs for w in wa)
+        out["adjoint"] = {"workload": bagen.WORKLOAD_NAMES[5], "windows": 64, "observations": nobs_a,
+                          "ms_per_call": ms_adj, "obs_per_s": nobs_a / (ms_adj / 1e3),
+                          "windows_per_s": 64 / (ms_adj / 1e3),
+                          "finite": bool(torch.isfinite(guv).all().item())}
+        log(f"adjoint: {ms_adj:.3f} ms for {nobs_a} observations")
+
+    # oracle on the host: bounded sample, also the RMS check of those windows
+    sample = list(range(min(args.cpu_sample, N_WINDOWS)))
+    if not args.no_cpu:
+        import oracle
+        res, wall_cpu, procs = cpu_baseline(sample)
+        iters_cpu = len(sample) * ITERS / wall_cpu
+        po = np.cumsum([0] + [w.n_poses for w in ws])
+        lo = np.cumsum([0] + [w.n_points for w in ws])
+        worst = 0.0
+        for idx, dt, rms_o in res:
+            w = ws[idx]
+            prob = oracle.Problem.from_window(w)
+            rms_g = oracle.rms(P_final[po[idx]:po[idx + 1]], L_final[lo[idx]:lo[idx + 1]], prob)
+            worst = max(worst, abs(rms_g - rms_o))
+        out["rms_check"] = {"windows": len(sample), "max_abs_drms_px": worst, "tol_px": 1e-3,
+                            "pass": bool(worst <= 1e-3)}
+        out["cpu_baseline"] = {"value": iters_cpu, "unit": "LM iters/s", "cores": procs,
+                               "kind": "oracle",
+                               "sample": f"windows 0-{len(sample) - 1} of the 256, {ITERS} LM attempts each, "
+                                         f"block-Schur FP64 oracle, one process per window"}
+        log(f"cpu oracle: {wall_cpu:.1f}s for {len(sample)} windows on {procs} processes, worst dRMS {worst:.2e}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

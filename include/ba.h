@@ -1,0 +1,228 @@
+/*
+ * ba.h -- C ABI of the MI355X (gfx950) sliding-window sparse bundle adjuster.
+ *
+ * The library solves the local sparse bundle adjustment of the paper's 3D module
+ * (cuVSLAM, Sec. 2.2, Eq. 2 and Eq. 3): given keyframe poses T^bw_i
+ * (base-from-world), landmarks p^w_j, a rig of cameras with fixed
+ * camera-from-base transforms T^cb_k and pinhole intrinsics, and 2D observations
+ * o of landmark j by camera k at pose i, it minimises
+ *
+ *     F = 1/2 sum_o w_o rho( || pi(T^cb_k T^bw_i p^w_j) - o ||^2 )
+ *
+ * (rho = Huber kernel on the pixel residual, w_o = observation weight) with
+ * Levenberg-Marquardt.  Each linear system is solved "poses first, then points"
+ * through the Schur complement (the sentence after Eq. 3): per-landmark
+ * elimination of the 3x3 point blocks, an FP64 Cholesky of the reduced camera
+ * system, then point back-substitution.
+ *
+ * Conventions (all arrays row-major, all values FP64 at this boundary):
+ *   pose / extrinsic  : 3x4 [R | t] (12 doubles), x_out = R x_in + t
+ *   pose update       : left perturbation T <- Exp(xi) T, xi = (rho, phi)
+ *   intrinsics        : fx, fy, cx, cy (4 doubles per camera)
+ *   observation pixel : (u, v), residual r = pi(x_c) - (u, v)
+ *   damping           : U_ii += lambda * max(diag, 1e-9), likewise V_jj
+ *   attempt           : one solve + candidate evaluation; accepted iff the robust
+ *                       cost strictly decreases (lambda /= down), else rejected
+ *                       (lambda *= up); a solve that meets a non-positive pivot
+ *                       or a candidate with a camera depth <= min_depth is a
+ *                       rejected attempt.  Exactly max_iters attempts run.
+ *
+ * Ownership: the caller owns every device buffer and the workspace.  The
+ * library owns plan handles (ba_window, ba_batch); they are immutable after
+ * creation and may be used concurrently on different streams with different
+ * workspaces.  ba_solve, ba_solve_batched and ba_adjoint allocate nothing,
+ * never synchronise the stream and never read device memory back to the host,
+ * so a caller may capture them into a HIP graph.  Plan creation allocates
+ * device memory for the plan's index arrays (on the current device).
+ *
+ * Errors: every call returns ba_status.  Argument and structure errors are
+ * detected on the host before any device work and return a negative status;
+ * ba_last_error() gives a thread-local description.  Numerical outcomes of a
+ * solve (Cholesky failures, rejected candidates, non-finite input) are written
+ * to the device-resident ba_report of each window.
+ *
+ * Limits of this implementation (checked at plan creation):
+ *   n_poses <= 64 per window, n_cams <= 32, free poses <= 32 per window
+ *   (<= 29 in BA_FP64, reported by ba_workspace_size / the solve calls),
+ *   every landmark observed from >= 2 distinct (pose, camera) views,
+ *   observations per landmark <= 4096, < 2^30 observations per batch.
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_window_s* ba_window;  /* plan of one window's structure */
+typedef struct ba_batch_s* ba_batch;    /* plan of many windows, packed window-major */
+
+typedef enum {
+  BA_OK = 0,
+  BA_ERR_INVALID_ARG = -1,          /* NULL pointer, index out of range, bad value */
+  BA_ERR_OOM = -2,                  /* host or plan device allocation failed */
+  BA_ERR_HIP = -3,                  /* a HIP runtime call failed */
+  BA_ERR_WORKSPACE_TOO_SMALL = -4,  /* ws_bytes below ba_workspace_size() */
+  BA_ERR_UNSUPPORTED = -5,          /* structure beyond the limits above */
+  BA_ERR_STATE = -6                 /* handle not usable for this call (e.g. host-only) */
+} ba_status;
+
+typedef enum {
+  BA_FP64 = 0,   /* every step in FP64 */
+  BA_MIXED = 1   /* FP32 observation stream, Jacobians, Hessian blocks and Schur
+                    products; FP64 pose/point state, camera-frame transform,
+                    cost sums, acceptance test, damping of S and the reduced-camera
+                    Cholesky */
+} ba_precision;
+
+/* flags of ba_window_create */
+enum { BA_CREATE_HOST_ONLY = 1 };   /* build and validate the plan, no device upload */
+
+typedef struct {
+  int32_t max_iters;      /* LM attempts (accepted + rejected); >= 0 */
+  int32_t precision;      /* ba_precision */
+  double lambda_init;     /* initial damping, > 0 (e.g. 1e-3) */
+  double lambda_up;       /* factor on rejection, > 1 (10) */
+  double lambda_down;     /* divisor on acceptance, > 1 (10) */
+  double lambda_min;      /* clamp, > 0 (1e-10) */
+  double lambda_max;      /* clamp (1e10) */
+  double huber_delta;     /* pixels; <= 0 selects plain least squares */
+  double min_depth;       /* candidate rejected if any camera depth Z <= min_depth */
+} ba_settings;
+
+/* Per-window outcome, written by the device at the end of a solve. */
+typedef struct {
+  double initial_cost;    /* F at the input state */
+  double final_cost;      /* F at the output state */
+  double final_lambda;
+  int32_t iters;          /* attempts run */
+  int32_t accepted;       /* accepted attempts */
+  int32_t chol_failures;  /* attempts rejected by a non-positive pivot */
+  int32_t depth_rejects;  /* attempts rejected by min_depth */
+  int32_t status;         /* 0 = ok, 1 = non-finite input cost */
+  int32_t reserved;
+} ba_report;
+
+/* One attempt of one window (optional per-attempt trace). */
+typedef struct {
+  double cost;            /* F before the attempt */
+  double cand_cost;       /* F at the candidate; NaN when none was formed */
+  double lambda;          /* damping used */
+  int32_t accepted;
+  int32_t status;         /* 0 = candidate formed, 1 = pivot failure, 2 = depth */
+} ba_iter_trace;
+
+/* Plan statistics (host side; usable without a device). */
+typedef struct {
+  int32_t n_poses, n_points, n_cams, n_free;
+  int64_t n_obs, n_pairs;   /* pairs = distinct (pose, landmark) */
+  int32_t n_tiles, n_chunks;
+  int64_t schur_blocks;     /* sum over landmarks of P(P+1)/2, P = free pairs */
+  int64_t n_free_pairs;     /* pairs whose pose is free */
+} ba_plan_info;
+
+/* Validate one window's structure and build its plan.
+ *   obs_pose, obs_point : HOST, n_obs each, indices in [0, n_poses) / [0, n_points)
+ *   obs_cam             : HOST, n_obs, in [0, n_cams); NULL -> camera 0
+ *   pose_fixed          : HOST, n_poses bytes (nonzero = held fixed); NULL -> pose 0 fixed
+ *   intrinsics          : HOST, n_cams x 4 (fx, fy, cx, cy), finite, fx, fy > 0
+ *   extrinsics          : HOST, n_cams x 12 camera-from-base [R | t]; NULL -> identity
+ *   flags               : 0 or BA_CREATE_HOST_ONLY
+ * The arrays are copied; the caller may free them after the call.  The user's
+ * observation order is kept at every later call (obs_uv, obs_w, gradients). */
+ba_status ba_window_create(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
+                           const int32_t* obs_pose, const int32_t* obs_point,
+                           const int32_t* obs_cam, const uint8_t* pose_fixed,
+                           const double* intrinsics, const double* extrinsics,
+                           int32_t flags, ba_window* out);
+void ba_window_destroy(ba_window w);
+ba_status ba_window_info(ba_window w, ba_plan_info* info);
+
+/* Copy of the plan's landmark-major observation order: perm[k] = user index of
+ * the k-th observation in plan order (HOST, n_obs).  For tests of the plan. */
+ba_status ba_window_order(ba_window w, int64_t* perm);
+
+/* Pack windows into one batch (device upload).  Windows keep their order;
+ * batched arrays are concatenated window-major: poses (sum n_poses x 12),
+ * points (sum n_points x 3), observations (sum n_obs, each window in its own
+ * user order).  The windows may be destroyed after the call. */
+ba_status ba_batch_create(int32_t n_windows, const ba_window* windows, ba_batch* out);
+void ba_batch_destroy(ba_batch b);
+ba_status ba_batch_info(ba_batch b, int32_t window, ba_plan_info* info);
+
+/* Bytes of workspace needed by ba_solve / ba_solve_batched / ba_adjoint for this
+ * plan and precision.  Exactly one of w, b is non-NULL. */
+ba_status ba_workspace_size(ba_window w, ba_batch b, const ba_settings* s, size_t* bytes);
+
+/* Solve one window in place.
+ *   poses   : DEVICE, n_poses x 12, in/out (fixed poses are left untouched)
+ *   points  : DEVICE, n_points x 3, in/out
+ *   obs_uv  : DEVICE, n_obs x 2 pixels, user order
+ *   obs_w   : DEVICE, n_obs weights; NULL -> all 1
+ *   workspace: DEVICE, >= ba_workspace_size bytes, 256-byte aligned
+ *   report  : DEVICE, one ba_report
+ *   trace   : DEVICE, max_iters ba_iter_trace, or NULL
+ *   stream  : hipStream_t (NULL = default stream)
+ * Enqueued on `stream`; returns before the device finishes. */
+ba_status ba_solve(ba_window w, const ba_settings* s, double* poses, double* points,
+                   const double* obs_uv, const double* obs_w, void* workspace,
+                   size_t ws_bytes, ba_report* report, ba_iter_trace* trace, void* stream);
+
+/* Solve every window of a batch in one launch sequence (one kernel per stage
+ * covering all windows).  Arrays are packed window-major (see ba_batch_create);
+ * reports: DEVICE, n_windows; traces: DEVICE, n_windows x max_iters or NULL.
+ * Every window runs the same number of attempts. */
+ba_status ba_solve_batched(ba_batch b, const ba_settings* s, double* poses, double* points,
+                           const double* obs_uv, const double* obs_w, void* workspace,
+                           size_t ws_bytes, ba_report* reports, ba_iter_trace* traces,
+                           void* stream);
+
+/* Implicit-function adjoint at a converged state x* (given, not recomputed).
+ * With a = H*^-1 dL/dx (H* = exact Hessian of F over the free variables, no
+ * damping) it writes, per observation in user order,
+ *     grad_uv[o] = w_o (rho' I + 2 rho'' r r^T) J_o a,   grad_w[o] = -rho' r^T J_o a.
+ *   grad_poses : DEVICE, n_poses x 12 ambient cotangent dL/d[R | t] (rows of
+ *                fixed poses are ignored); mapped to the left-perturbation tangent
+ *   grad_points: DEVICE, n_points x 3, or NULL (zero)
+ *   grad_uv    : DEVICE out, n_obs x 2;  grad_w: DEVICE out, n_obs, or NULL
+ *   reports    : DEVICE, per window; chol_failures = 1 when H* was not positive
+ *                definite on the reduced camera system
+ * Exactly one of w, b is non-NULL; with b the arrays are packed as in
+ * ba_solve_batched.  settings->lambda_* and max_iters are ignored. */
+ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double* poses,
+                     const double* points, const double* obs_uv, const double* obs_w,
+                     const double* grad_poses, const double* grad_points, double* grad_uv,
+                     double* grad_w, void* workspace, size_t ws_bytes, ba_report* reports,
+                     void* stream);
+
+/* Launch-shape tuning.  ba_autotune times the candidate shapes of the batched
+ * Schur kernel on this plan (synchronising the stream; not capturable), keeps
+ * the fastest in the plan and returns it; ba_set_launch sets one directly.
+ * Shape = observations per work item (chunk target).  Results are cached per
+ * (device name, precision, size bucket) in the file named by $BA_TUNE_CACHE
+ * when that variable is set. */
+ba_status ba_autotune(ba_batch b, const ba_settings* s, double* poses, double* points,
+                      const double* obs_uv, const double* obs_w, void* workspace,
+                      size_t ws_bytes, void* stream, int32_t* chosen_chunk_obs);
+ba_status ba_set_launch(ba_batch b, int32_t chunk_obs);
+
+/* Diagnostics: the same solve as ba_solve_batched with HIP events recorded on
+ * `stream` between the launches; writes the summed device time in ms of each
+ * stage over all attempts: stage_ms[0] linearise + Schur (pass A),
+ * [1] reduction + Cholesky + candidate poses, [2] back-substitution +
+ * candidate cost (pass B), [3] acceptance.  Synchronises the stream; not
+ * capturable.  For benchmarks and profiling only. */
+ba_status ba_profile_stages(ba_batch b, const ba_settings* s, double* poses, double* points,
+                            const double* obs_uv, const double* obs_w, void* workspace,
+                            size_t ws_bytes, ba_report* reports, void* stream, double* stage_ms);
+
+const char* ba_status_string(ba_status s);
+const char* ba_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BA_H */

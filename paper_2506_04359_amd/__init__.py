@@ -1,0 +1,24 @@
+"""MI355X (gfx950) sliding-window sparse Levenberg-Marquardt bundle adjustment.
+
+Thin Python binding of ``libba.so`` (C ABI in ``include/ba.h``).  Every step of
+the solve runs in the library's HIP kernels; this module only marshals
+arguments: host index lists for plan creation, torch tensors for device memory
+and the caller's current HIP stream.  Loading fails loudly when the library has
+not been built (``python -m paper_2506_04359_amd.build``); there is no fallback.
+"""
+from ._binding import (  # noqa: F401
+    BA_CREATE_HOST_ONLY,
+    BA_FP64,
+    BA_MIXED,
+    BAError,
+    Batch,
+    Settings,
+    Window,
+    adjoint,
+    lib,
+    parse_reports,
+    parse_traces,
+    solve,
+    solve_batched,
+)
+from .autograd import BASolve  # noqa: F401

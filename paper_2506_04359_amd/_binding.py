@@ -1,0 +1,309 @@
+"""ctypes binding of libba.so (argument marshalling only)."""
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libba.so")
+
+BA_FP64 = 0
+BA_MIXED = 1
+BA_CREATE_HOST_ONLY = 1
+
+
+class BAError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"ba status {status}: {message}")
+        self.status = status
+
+
+class _Settings(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lambda_init", ctypes.c_double), ("lambda_up", ctypes.c_double),
+                ("lambda_down", ctypes.c_double), ("lambda_min", ctypes.c_double),
+                ("lambda_max", ctypes.c_double), ("huber_delta", ctypes.c_double),
+                ("min_depth", ctypes.c_double)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("n_poses", ctypes.c_int32), ("n_points", ctypes.c_int32),
+                ("n_cams", ctypes.c_int32), ("n_free", ctypes.c_int32),
+                ("n_obs", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+                ("schur_blocks", ctypes.c_int64), ("n_free_pairs", ctypes.c_int64)]
+
+
+REPORT_DTYPE = np.dtype([("initial_cost", "<f8"), ("final_cost", "<f8"), ("final_lambda", "<f8"),
+                         ("iters", "<i4"), ("accepted", "<i4"), ("chol_failures", "<i4"),
+                         ("depth_rejects", "<i4"), ("status", "<i4"), ("reserved", "<i4")])
+TRACE_DTYPE = np.dtype([("cost", "<f8"), ("cand_cost", "<f8"), ("lambda", "<f8"),
+                        ("accepted", "<i4"), ("status", "<i4")])
+assert REPORT_DTYPE.itemsize == 48 and TRACE_DTYPE.itemsize == 32
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                              "`python -m paper_2506_04359_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.ba_window_create.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp, vp, i32,
+                                       ctypes.POINTER(vp)]
+        L.ba_window_destroy.argtypes = [vp]
+        L.ba_window_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
+        L.ba_window_order.argtypes = [vp, vp]
+        L.ba_batch_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+        L.ba_batch_destroy.argtypes = [vp]
+        L.ba_batch_info.argtypes = [vp, i32, ctypes.POINTER(_PlanInfo)]
+        L.ba_workspace_size.argtypes = [vp, vp, ctypes.POINTER(_Settings), ctypes.POINTER(sz)]
+        L.ba_solve.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp, vp, vp]
+        L.ba_solve_batched.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
+                                       vp, vp]
+        L.ba_adjoint.argtypes = [vp, vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, vp, vp,
+                                 vp, vp, sz, vp, vp]
+        L.ba_autotune.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
+                                  ctypes.POINTER(i32)]
+        L.ba_set_launch.argtypes = [vp, i32]
+        L.ba_profile_stages.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
+                                        vp, ctypes.POINTER(ctypes.c_double)]
+        L.ba_status_string.argtypes = [i32]
+        L.ba_status_string.restype = ctypes.c_char_p
+        L.ba_last_error.restype = ctypes.c_char_p
+        for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
+                  "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_batched",
+                  "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise BAError(status, lib().ba_last_error().decode())
+
+
+@dataclasses.dataclass
+class Settings:
+    max_iters: int = 10
+    precision: int = BA_FP64
+    lambda_init: float = 1e-3
+    lambda_up: float = 10.0
+    lambda_down: float = 10.0
+    lambda_min: float = 1e-10
+    lambda_max: float = 1e10
+    huber_delta: float = 1.0
+    min_depth: float = 1e-3
+
+    def c(self) -> _Settings:
+        return _Settings(self.max_iters, self.precision, self.lambda_init, self.lambda_up,
+                         self.lambda_down, self.lambda_min, self.lambda_max, self.huber_delta,
+                         self.min_depth)
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Window:
+    """Plan of one window's structure (index lists are host arrays)."""
+
+    def __init__(self, n_poses, n_points, obs_pose, obs_point, intrinsics, obs_cam=None,
+                 pose_fixed=None, extrinsics=None, host_only=False):
+        L = lib()
+        self._keep = [_host(obs_pose, np.int32), _host(obs_point, np.int32)]
+        op, oj = self._keep
+        oc = None if obs_cam is None else _host(obs_cam, np.int32)
+        pf = None if pose_fixed is None else _host(pose_fixed, np.uint8)
+        K = _host(intrinsics, np.float64).reshape(-1, 4)
+        E = None if extrinsics is None else _host(extrinsics, np.float64).reshape(-1, 12)
+        h = ctypes.c_void_p()
+        _check(L.ba_window_create(int(n_poses), int(n_points), int(K.shape[0]), int(op.shape[0]),
+                                  op.ctypes.data_as(ctypes.c_void_p), oj.ctypes.data_as(ctypes.c_void_p),
+                                  None if oc is None else oc.ctypes.data_as(ctypes.c_void_p),
+                                  None if pf is None else pf.ctypes.data_as(ctypes.c_void_p),
+                                  K.ctypes.data_as(ctypes.c_void_p),
+                                  None if E is None else E.ctypes.data_as(ctypes.c_void_p),
+                                  BA_CREATE_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        self._h = h
+        self.n_poses, self.n_points, self.n_obs = int(n_poses), int(n_points), int(op.shape[0])
+        self._keep = None
+
+    @classmethod
+    def from_problem(cls, w, host_only=False):
+        """From any object with the fields of a bagen.Window."""
+        return cls(w.poses_gt.shape[0] if hasattr(w, "poses_gt") else w.n_poses,
+                   w.points_gt.shape[0] if hasattr(w, "points_gt") else w.n_points,
+                   w.obs_pose, w.obs_point, w.intrinsics, obs_cam=w.obs_cam,
+                   pose_fixed=w.pose_fixed, extrinsics=w.extrinsics, host_only=host_only)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = _PlanInfo()
+        _check(lib().ba_window_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _PlanInfo._fields_}
+
+    def order(self):
+        p = np.empty(self.n_obs, np.int64)
+        _check(lib().ba_window_order(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    def workspace_size(self, settings: Settings) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().ba_workspace_size(self._h, None, ctypes.byref(settings.c()), ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ba_window_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many windows packed window-major into one plan."""
+
+    def __init__(self, windows: Sequence[Window]):
+        arr = (ctypes.c_void_p * len(windows))(*[w.handle.value for w in windows])
+        h = ctypes.c_void_p()
+        _check(lib().ba_batch_create(len(windows), arr, ctypes.byref(h)))
+        self._h = h
+        self.n_windows = len(windows)
+        self.n_poses = [w.n_poses for w in windows]
+        self.n_points = [w.n_points for w in windows]
+        self.n_obs = [w.n_obs for w in windows]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_size(self, settings: Settings) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().ba_workspace_size(None, self._h, ctypes.byref(settings.c()), ctypes.byref(n)))
+        return n.value
+
+    def info(self, w):
+        i = _PlanInfo()
+        _check(lib().ba_batch_info(self._h, int(w), ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _PlanInfo._fields_}
+
+    def set_launch(self, chunk_obs: int):
+        _check(lib().ba_set_launch(self._h, int(chunk_obs)))
+
+    def autotune(self, settings, poses, points, obs_uv, obs_w, workspace, stream=None) -> int:
+        c = ctypes.c_int32()
+        _check(lib().ba_autotune(self._h, ctypes.byref(settings.c()), _ptr(poses), _ptr(points),
+                                 _ptr(obs_uv), _ptr(obs_w), _ptr(workspace), workspace.numel(),
+                                 _stream(stream), ctypes.byref(c)))
+        return c.value
+
+    def profile_stages(self, settings, poses, points, obs_uv, obs_w, workspace, reports,
+                       stream=None):
+        """Per-stage device time (ms, summed over attempts) of one solve."""
+        ms = (ctypes.c_double * 4)()
+        _check(lib().ba_profile_stages(self._h, ctypes.byref(settings.c()), _ptr(poses),
+                                       _ptr(points), _ptr(obs_uv), _ptr(obs_w), _ptr(workspace),
+                                       workspace.numel(), _ptr(reports), _stream(stream), ms))
+        return dict(pass_a=ms[0], reduce=ms[1], pass_b=ms[2], accept=ms[3])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ba_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _workspace(plan, settings, workspace, device):
+    import torch
+    need = plan.workspace_size(settings)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+    return workspace
+
+
+def solve(window: Window, settings: Settings, poses, points, obs_uv, obs_w=None, workspace=None,
+          report=None, trace=None, stream=None):
+    """In-place solve of one window; tensors are float64 on the GPU.
+    Returns (report bytes tensor, trace bytes tensor or None, workspace)."""
+    import torch
+    dev = poses.device
+    workspace = _workspace(window, settings, workspace, dev)
+    if report is None:
+        report = torch.zeros(REPORT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    _check(lib().ba_solve(window.handle, ctypes.byref(settings.c()), _ptr(poses), _ptr(points),
+                          _ptr(obs_uv), _ptr(obs_w), _ptr(workspace), workspace.numel(),
+                          _ptr(report), _ptr(trace), _stream(stream)))
+    return report, trace, workspace
+
+
+def solve_batched(batch: Batch, settings: Settings, poses, points, obs_uv, obs_w=None,
+                  workspace=None, reports=None, traces=None, stream=None):
+    import torch
+    dev = poses.device
+    workspace = _workspace(batch, settings, workspace, dev)
+    if reports is None:
+        reports = torch.zeros(REPORT_DTYPE.itemsize * batch.n_windows, dtype=torch.uint8, device=dev)
+    _check(lib().ba_solve_batched(batch.handle, ctypes.byref(settings.c()), _ptr(poses),
+                                  _ptr(points), _ptr(obs_uv), _ptr(obs_w), _ptr(workspace),
+                                  workspace.numel(), _ptr(reports), _ptr(traces), _stream(stream)))
+    return reports, traces, workspace
+
+
+def adjoint(plan, settings: Settings, poses, points, obs_uv, obs_w, grad_poses, grad_points,
+            grad_uv, grad_w, workspace=None, reports=None, stream=None):
+    import torch
+    dev = poses.device
+    workspace = _workspace(plan, settings, workspace, dev)
+    n = plan.n_windows if isinstance(plan, Batch) else 1
+    if reports is None:
+        reports = torch.zeros(REPORT_DTYPE.itemsize * n, dtype=torch.uint8, device=dev)
+    w = plan.handle if isinstance(plan, Window) else None
+    b = plan.handle if isinstance(plan, Batch) else None
+    _check(lib().ba_adjoint(w, b, ctypes.byref(settings.c()), _ptr(poses), _ptr(points),
+                            _ptr(obs_uv), _ptr(obs_w), _ptr(grad_poses), _ptr(grad_points),
+                            _ptr(grad_uv), _ptr(grad_w), _ptr(workspace), workspace.numel(),
+                            _ptr(reports), _stream(stream)))
+    return reports, workspace
+
+
+def parse_reports(reports) -> np.ndarray:
+    return np.frombuffer(reports.cpu().numpy().tobytes(), dtype=REPORT_DTYPE)
+
+
+def parse_traces(traces, n_windows, max_iters) -> np.ndarray:
+    return np.frombuffer(traces.cpu().numpy().tobytes(), dtype=TRACE_DTYPE).reshape(n_windows, max_iters)

@@ -1,0 +1,702 @@
+// C ABI of the bundle adjuster (include/ba.h): argument checks, plan upload,
+// workspace layout, launch-shape selection and the launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "device.hpp"
+#include "plan.hpp"
+
+namespace ba {
+
+// defined in kernels.hip
+template <typename Real, int TP>
+size_t pass_a_lds(int max_nf);
+template <typename Real, int TP>
+size_t pass_b_lds();
+size_t reduce_lds(int max_nf);
+template <typename Real, int TP, bool ADJ>
+hipError_t set_attrs();
+struct LaunchArgs {
+  DevPlan plan;
+  DevTiles tiles;
+  DevUser user;
+  DevSettings settings;
+  int max_nf;
+  hipStream_t stream;
+};
+template <typename Real, int TP>
+hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K);
+template <typename Real, int TP>
+hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K);
+template <typename Real, int TP>
+hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* stage_ms);
+
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kChunkMin = 512;
+constexpr int kChunkMax = 65536;
+
+thread_local std::string g_error;
+
+ba_status set_error(ba_status s, const std::string& m) {
+  g_error = m;
+  return s;
+}
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Device copy of a std::vector inside one plan allocation.
+struct Blob {
+  std::vector<std::pair<size_t, std::vector<uint8_t>>> parts;
+  size_t size = 0;
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = align_up(size);
+    std::vector<uint8_t> bytes(v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(bytes.data(), v.data(), bytes.size());
+    parts.emplace_back(off, std::move(bytes));
+    size = off + std::max<size_t>(parts.back().second.size(), 1);
+    return off;
+  }
+};
+
+struct DeviceTables {
+  int tp = 0, chunk_obs = 0;
+  int n_chunks = 0;
+  int64_t part_elems = 0;
+  void* mem = nullptr;
+  WinDev* win = nullptr;
+  int32_t* tile_lm_begin = nullptr;
+  int32_t* chunk_window = nullptr;
+  int32_t* chunk_tile_begin = nullptr;
+  int64_t* chunk_part_off = nullptr;
+};
+
+}  // namespace ba
+
+using namespace ba;
+
+struct ba_batch_s {
+  std::vector<HostWindow> wins;
+  int max_nf = 0;
+  int64_t n_poses = 0, n_points = 0, n_cams = 0, n_obs = 0, n_pairs = 0;
+  int device = 0;
+  void* mem = nullptr;   // plan arrays
+  DevPlan plan{};
+  DeviceTables tables[2];   // [0]: small tiles, [1]: large tiles
+  int chunk_obs = 4096;
+  std::mutex mu;
+  ~ba_batch_s() {
+    if (mem) (void)hipFree(mem);
+    for (auto& t : tables)
+      if (t.mem) (void)hipFree(t.mem);
+  }
+};
+
+struct ba_window_s {
+  HostWindow host;
+  ba_batch_s* batch = nullptr;   // single-window batch, NULL when host-only
+  ~ba_window_s() { delete batch; }
+};
+
+namespace {
+
+ba_status hip_fail(hipError_t e, const char* what) {
+  return set_error(BA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
+  std::vector<const HostWindow*> ws;
+  for (auto& w : b->wins) ws.push_back(&w);
+  LaunchTables t;
+  build_tiles(ws, tp, chunk_obs, t);
+  // per-window records with this table's chunk ranges
+  std::vector<WinDev> wd(b->wins.size());
+  int32_t po = 0, lo = 0, co = 0, oo = 0, pa = 0;
+  for (size_t i = 0; i < b->wins.size(); ++i) {
+    const HostWindow& w = b->wins[i];
+    WinDev& d = wd[i];
+    d.n_poses = w.n_poses;
+    d.n_points = w.n_points;
+    d.n_cams = w.n_cams;
+    d.n_free = w.n_free;
+    d.pose_off = po;
+    d.point_off = lo;
+    d.cam_off = co;
+    d.obs_off = oo;
+    d.pair_off = pa;
+    d.chunk_begin = t.win_chunk_begin[i];
+    d.chunk_end = t.win_chunk_begin[i + 1];
+    d.pad = 0;
+    po += w.n_poses;
+    lo += w.n_points;
+    co += w.n_cams;
+    oo += (int32_t)w.n_obs;
+    pa += (int32_t)w.n_pairs();
+  }
+  Blob blob;
+  const size_t o_win = blob.add(wd);
+  const size_t o_tile = blob.add(t.tile_lm_begin);
+  const size_t o_cw = blob.add(t.chunk_window);
+  const size_t o_ct = blob.add(t.chunk_tile_begin);
+  const size_t o_cp = blob.add(t.chunk_part_off);
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, blob.size);
+  if (e != hipSuccess) return set_error(BA_ERR_OOM, "plan tables: hipMalloc failed");
+  for (auto& p : blob.parts)
+    if (!p.second.empty()) {
+      e = hipMemcpy((char*)mem + p.first, p.second.data(), p.second.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "plan tables upload");
+      }
+    }
+  DeviceTables& D = b->tables[which];
+  if (D.mem) (void)hipFree(D.mem);
+  D.mem = mem;
+  D.tp = tp;
+  D.chunk_obs = chunk_obs;
+  D.n_chunks = t.n_chunks();
+  D.part_elems = t.part_elems;
+  D.win = (WinDev*)((char*)mem + o_win);
+  D.tile_lm_begin = (int32_t*)((char*)mem + o_tile);
+  D.chunk_window = (int32_t*)((char*)mem + o_cw);
+  D.chunk_tile_begin = (int32_t*)((char*)mem + o_ct);
+  D.chunk_part_off = (int64_t*)((char*)mem + o_cp);
+  return BA_OK;
+}
+
+int default_chunk_obs(int64_t n_obs) {
+  const int64_t c = n_obs / 1024;
+  return (int)std::min<int64_t>(8192, std::max<int64_t>(1024, c));
+}
+
+ba_status batch_build(std::vector<HostWindow>&& wins, ba_batch_s** out) {
+  std::unique_ptr<ba_batch_s> b(new ba_batch_s());
+  b->wins = std::move(wins);
+  std::vector<int32_t> free_slot, lm_pair_begin, pair_obs_begin, pair_lm, obs_perm;
+  std::vector<uint8_t> lm_nfree, pair_pose, obs_cam;
+  std::vector<double> cam;
+  int32_t lm_base = 0, pair_base = 0, obs_base = 0;
+  for (auto& w : b->wins) {
+    b->max_nf = std::max(b->max_nf, w.n_free);
+    for (int i = 0; i < w.n_poses; ++i) free_slot.push_back(w.free_slot[i]);
+    cam.insert(cam.end(), w.cam.begin(), w.cam.end());
+    for (int j = 0; j < w.n_points; ++j) {
+      lm_pair_begin.push_back(pair_base + w.lm_pair_begin[j]);
+      lm_nfree.push_back(w.lm_nfree[j]);
+    }
+    for (int64_t q = 0; q < w.n_pairs(); ++q) {
+      pair_obs_begin.push_back(obs_base + w.pair_obs_begin[q]);
+      pair_lm.push_back(lm_base + w.pair_lm[q]);
+      pair_pose.push_back(w.pair_pose[q]);
+    }
+    obs_cam.insert(obs_cam.end(), w.obs_cam.begin(), w.obs_cam.end());
+    obs_perm.insert(obs_perm.end(), w.perm.begin(), w.perm.end());
+    lm_base += w.n_points;
+    pair_base += (int32_t)w.n_pairs();
+    obs_base += (int32_t)w.n_obs;
+    b->n_poses += w.n_poses;
+    b->n_points += w.n_points;
+    b->n_cams += w.n_cams;
+    b->n_obs += w.n_obs;
+    b->n_pairs += w.n_pairs();
+  }
+  if (b->n_obs > (int64_t)INT32_MAX / 2 || b->n_pairs > (int64_t)INT32_MAX / 2)
+    return set_error(BA_ERR_UNSUPPORTED, "batch too large for 32-bit indices");
+  lm_pair_begin.push_back(pair_base);
+  pair_obs_begin.push_back(obs_base);
+  Blob blob;
+  const size_t o_fs = blob.add(free_slot), o_cam = blob.add(cam), o_lpb = blob.add(lm_pair_begin),
+               o_lnf = blob.add(lm_nfree), o_pob = blob.add(pair_obs_begin),
+               o_plm = blob.add(pair_lm), o_pp = blob.add(pair_pose), o_oc = blob.add(obs_cam),
+               o_op = blob.add(obs_perm);
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipMalloc(&b->mem, blob.size);
+  if (e != hipSuccess) return set_error(BA_ERR_OOM, "plan arrays: hipMalloc failed");
+  for (auto& p : blob.parts)
+    if (!p.second.empty()) {
+      e = hipMemcpy((char*)b->mem + p.first, p.second.data(), p.second.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "plan upload");
+    }
+  char* m = (char*)b->mem;
+  b->plan.free_slot = (const int32_t*)(m + o_fs);
+  b->plan.cam = (const double*)(m + o_cam);
+  b->plan.lm_pair_begin = (const int32_t*)(m + o_lpb);
+  b->plan.lm_nfree = (const uint8_t*)(m + o_lnf);
+  b->plan.pair_obs_begin = (const int32_t*)(m + o_pob);
+  b->plan.pair_lm = (const int32_t*)(m + o_plm);
+  b->plan.pair_pose = (const uint8_t*)(m + o_pp);
+  b->plan.obs_cam = (const uint8_t*)(m + o_oc);
+  b->plan.obs_perm = (const int32_t*)(m + o_op);
+  b->plan.n_windows = (int32_t)b->wins.size();
+  b->chunk_obs = default_chunk_obs(b->n_obs);
+  ba_status s = upload_tables(b.get(), 0, kTileSmall, b->chunk_obs);
+  if (s != BA_OK) return s;
+  s = upload_tables(b.get(), 1, kTileLarge, b->chunk_obs);
+  if (s != BA_OK) return s;
+  *out = b.release();
+  return BA_OK;
+}
+
+ba_status check_settings(const ba_settings* s) {
+  if (!s) return set_error(BA_ERR_INVALID_ARG, "settings is NULL");
+  if (s->max_iters < 0 || s->max_iters > 100000) return set_error(BA_ERR_INVALID_ARG, "max_iters out of range");
+  if (s->precision != BA_FP64 && s->precision != BA_MIXED)
+    return set_error(BA_ERR_INVALID_ARG, "unknown precision");
+  if (!(s->lambda_init > 0) || !(s->lambda_up > 1) || !(s->lambda_down > 1) ||
+      !(s->lambda_min > 0) || !(s->lambda_max >= s->lambda_min) || !std::isfinite(s->lambda_max))
+    return set_error(BA_ERR_INVALID_ARG, "invalid lambda settings");
+  if (std::isnan(s->huber_delta) || !std::isfinite(s->min_depth))
+    return set_error(BA_ERR_INVALID_ARG, "invalid huber_delta or min_depth");
+  return BA_OK;
+}
+
+// Tile configuration for a precision: the large tiles when their LDS fits.
+ba_status pick_config(const ba_batch_s* b, int precision, int* which) {
+  const int nf = b->max_nf;
+  if (precision == BA_MIXED) {
+    if (pass_a_lds<float, kTileLarge>(nf) <= kLdsLimit) *which = 1;
+    else if (pass_a_lds<float, kTileSmall>(nf) <= kLdsLimit) *which = 0;
+    else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
+  } else {
+    if (nf > kMaxFreeFp64) return set_error(BA_ERR_UNSUPPORTED, "BA_FP64 supports at most 29 free poses per window");
+    if (pass_a_lds<double, kTileLarge>(nf) <= kLdsLimit) *which = 1;
+    else if (pass_a_lds<double, kTileSmall>(nf) <= kLdsLimit) *which = 0;
+    else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
+  }
+  if (reduce_lds(nf) > kLdsLimit) return set_error(BA_ERR_UNSUPPORTED, "reduced system too large for LDS");
+  return BA_OK;
+}
+
+struct Layout {
+  size_t du, dv, w, poses_b, points_b, state, dp, part, cost_a, cost_b, flag_a, flag_b, total;
+};
+
+Layout layout(const ba_batch_s* b, const DeviceTables& t, size_t real) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.du = take(real * b->n_obs);
+  L.dv = take(real * b->n_obs);
+  L.w = take(real * b->n_obs);
+  L.poses_b = take(sizeof(double) * 12 * b->n_poses);
+  L.points_b = take(sizeof(double) * 3 * b->n_points);
+  L.state = take(sizeof(WinState) * b->wins.size());
+  L.dp = take(sizeof(double) * kDpStride * b->wins.size());
+  L.part = take(real * t.part_elems);
+  L.cost_a = take(sizeof(double) * t.n_chunks);
+  L.cost_b = take(sizeof(double) * t.n_chunks);
+  L.flag_a = take(sizeof(int32_t) * t.n_chunks);
+  L.flag_b = take(sizeof(int32_t) * t.n_chunks);
+  L.total = o;
+  return L;
+}
+
+template <typename Real>
+DevWork<Real> make_work(const Layout& L, void* ws, bool has_w) {
+  char* m = (char*)ws;
+  DevWork<Real> K;
+  K.du = (Real*)(m + L.du);
+  K.dv = (Real*)(m + L.dv);
+  K.w = has_w ? (Real*)(m + L.w) : nullptr;
+  K.poses_b = (double*)(m + L.poses_b);
+  K.points_b = (double*)(m + L.points_b);
+  K.state = (WinState*)(m + L.state);
+  K.dp = (double*)(m + L.dp);
+  K.part = (Real*)(m + L.part);
+  K.part_cost_a = (double*)(m + L.cost_a);
+  K.part_cost_b = (double*)(m + L.cost_b);
+  K.part_flag_a = (int32_t*)(m + L.flag_a);
+  K.part_flag_b = (int32_t*)(m + L.flag_b);
+  return K;
+}
+
+ba_status ensure_attrs() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    hipError_t e;
+    if ((e = set_attrs<double, kTileSmall, false>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<double, kTileLarge, false>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<float, kTileSmall, false>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<float, kTileLarge, false>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<double, kTileSmall, true>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<double, kTileLarge, true>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<float, kTileSmall, true>()) != hipSuccess) { err = e; return; }
+    if ((e = set_attrs<float, kTileLarge, true>()) != hipSuccess) { err = e; return; }
+  });
+  if (err != hipSuccess) return hip_fail(err, "hipFuncSetAttribute");
+  return BA_OK;
+}
+
+DevSettings dev_settings(const ba_settings* s) {
+  DevSettings d;
+  d.lambda_init = s->lambda_init;
+  d.lambda_up = s->lambda_up;
+  d.lambda_down = s->lambda_down;
+  d.lambda_min = s->lambda_min;
+  d.lambda_max = s->lambda_max;
+  d.huber_delta = s->huber_delta;
+  d.min_depth = s->min_depth;
+  d.max_iters = s->max_iters;
+  d.pad = 0;
+  return d;
+}
+
+DevTiles dev_tiles(const DeviceTables& t) {
+  DevTiles d;
+  d.tile_lm_begin = t.tile_lm_begin;
+  d.chunk_window = t.chunk_window;
+  d.chunk_tile_begin = t.chunk_tile_begin;
+  d.chunk_part_off = t.chunk_part_off;
+  d.n_chunks = t.n_chunks;
+  return d;
+}
+
+enum class Op { Solve, Adjoint, Timed };
+
+ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws, size_t ws_bytes,
+                 void* stream, bool has_w, double* stage_ms = nullptr) {
+  int which = 0;
+  ba_status st = pick_config(b, s->precision, &which);
+  if (st != BA_OK) return st;
+  const DeviceTables& t = b->tables[which];
+  const size_t real = s->precision == BA_FP64 ? sizeof(double) : sizeof(float);
+  const Layout L = layout(b, t, real);
+  if (!ws) return set_error(BA_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < L.total) return set_error(BA_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  if (((uintptr_t)ws) % 256 != 0) return set_error(BA_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if ((st = ensure_attrs()) != BA_OK) return st;
+  LaunchArgs A;
+  A.plan = b->plan;
+  A.plan.win = t.win;
+  A.tiles = dev_tiles(t);
+  A.user = U;
+  A.settings = dev_settings(s);
+  A.max_nf = b->max_nf;
+  A.stream = (hipStream_t)stream;
+  hipError_t e;
+  if (s->precision == BA_FP64) {
+    const DevWork<double> K = make_work<double>(L, ws, has_w);
+    if (op == Op::Solve)
+      e = t.tp == kTileLarge ? run_solve<double, kTileLarge>(A, K) : run_solve<double, kTileSmall>(A, K);
+    else if (op == Op::Timed)
+      e = t.tp == kTileLarge ? run_solve_timed<double, kTileLarge>(A, K, stage_ms)
+                             : run_solve_timed<double, kTileSmall>(A, K, stage_ms);
+    else
+      e = t.tp == kTileLarge ? run_adjoint<double, kTileLarge>(A, K) : run_adjoint<double, kTileSmall>(A, K);
+  } else {
+    const DevWork<float> K = make_work<float>(L, ws, has_w);
+    if (op == Op::Solve)
+      e = t.tp == kTileLarge ? run_solve<float, kTileLarge>(A, K) : run_solve<float, kTileSmall>(A, K);
+    else if (op == Op::Timed)
+      e = t.tp == kTileLarge ? run_solve_timed<float, kTileLarge>(A, K, stage_ms)
+                             : run_solve_timed<float, kTileSmall>(A, K, stage_ms);
+    else
+      e = t.tp == kTileLarge ? run_adjoint<float, kTileLarge>(A, K) : run_adjoint<float, kTileSmall>(A, K);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BA_OK;
+}
+
+ba_batch_s* batch_of(ba_window w, ba_batch b) {
+  if (w && !b) return w->batch;
+  if (b && !w) return b;
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ba_status_string(ba_status s) {
+  switch (s) {
+    case BA_OK: return "ok";
+    case BA_ERR_INVALID_ARG: return "invalid argument";
+    case BA_ERR_OOM: return "out of memory";
+    case BA_ERR_HIP: return "HIP runtime error";
+    case BA_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case BA_ERR_UNSUPPORTED: return "unsupported structure";
+    case BA_ERR_STATE: return "handle not usable for this call";
+  }
+  return "unknown status";
+}
+
+const char* ba_last_error(void) { return g_error.c_str(); }
+
+ba_status ba_window_create(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
+                           const int32_t* obs_pose, const int32_t* obs_point,
+                           const int32_t* obs_cam, const uint8_t* pose_fixed,
+                           const double* intrinsics, const double* extrinsics, int32_t flags,
+                           ba_window* out) {
+  if (!out) return set_error(BA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (flags & ~BA_CREATE_HOST_ONLY) return set_error(BA_ERR_INVALID_ARG, "unknown flags");
+  std::unique_ptr<ba_window_s> w(new (std::nothrow) ba_window_s());
+  if (!w) return set_error(BA_ERR_OOM, "host allocation failed");
+  int code = 0;
+  const std::string err = build_window(n_poses, n_points, n_cams, n_obs, obs_pose, obs_point,
+                                       obs_cam, pose_fixed, intrinsics, extrinsics, w->host, &code);
+  if (code != 0) return set_error((ba_status)code, err);
+  if (!(flags & BA_CREATE_HOST_ONLY)) {
+    std::vector<HostWindow> one(1, w->host);
+    ba_status s = batch_build(std::move(one), &w->batch);
+    if (s != BA_OK) return s;
+  }
+  *out = w.release();
+  return BA_OK;
+}
+
+void ba_window_destroy(ba_window w) { delete w; }
+
+static void fill_info(const HostWindow& h, int n_tiles, int n_chunks, ba_plan_info* info) {
+  info->n_poses = h.n_poses;
+  info->n_points = h.n_points;
+  info->n_cams = h.n_cams;
+  info->n_free = h.n_free;
+  info->n_obs = h.n_obs;
+  info->n_pairs = h.n_pairs();
+  info->n_tiles = n_tiles;
+  info->n_chunks = n_chunks;
+  info->schur_blocks = h.schur_blocks;
+  info->n_free_pairs = h.n_free_pairs;
+}
+
+ba_status ba_window_info(ba_window w, ba_plan_info* info) {
+  if (!w || !info) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  std::vector<const HostWindow*> one{&w->host};
+  LaunchTables t;
+  build_tiles(one, kTileLarge, default_chunk_obs(w->host.n_obs), t);
+  fill_info(w->host, t.n_tiles(), t.n_chunks(), info);
+  return BA_OK;
+}
+
+ba_status ba_window_order(ba_window w, int64_t* perm) {
+  if (!w || (!perm && w->host.n_obs > 0)) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  for (int64_t k = 0; k < w->host.n_obs; ++k) perm[k] = w->host.perm[k];
+  return BA_OK;
+}
+
+ba_status ba_batch_create(int32_t n_windows, const ba_window* windows, ba_batch* out) {
+  if (!out || !windows || n_windows < 1) return set_error(BA_ERR_INVALID_ARG, "invalid arguments");
+  *out = nullptr;
+  std::vector<HostWindow> ws;
+  ws.reserve(n_windows);
+  for (int i = 0; i < n_windows; ++i) {
+    if (!windows[i]) return set_error(BA_ERR_INVALID_ARG, "NULL window in list");
+    ws.push_back(windows[i]->host);
+  }
+  ba_batch_s* b = nullptr;
+  ba_status s = batch_build(std::move(ws), &b);
+  if (s != BA_OK) return s;
+  *out = b;
+  return BA_OK;
+}
+
+void ba_batch_destroy(ba_batch b) { delete b; }
+
+ba_status ba_batch_info(ba_batch b, int32_t window, ba_plan_info* info) {
+  if (!b || !info || window < 0 || window >= (int32_t)b->wins.size())
+    return set_error(BA_ERR_INVALID_ARG, "invalid arguments");
+  const DeviceTables& t = b->tables[1];
+  fill_info(b->wins[window], 0, t.n_chunks, info);
+  return BA_OK;
+}
+
+ba_status ba_workspace_size(ba_window w, ba_batch b, const ba_settings* s, size_t* bytes) {
+  if (!bytes) return set_error(BA_ERR_INVALID_ARG, "bytes is NULL");
+  if (w && !w->batch && !b) return set_error(BA_ERR_STATE, "host-only window");
+  ba_batch_s* bb = batch_of(w, b);
+  if (!bb) return set_error(BA_ERR_INVALID_ARG, "exactly one of w, b must be given");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  int which = 0;
+  if ((st = pick_config(bb, s->precision, &which)) != BA_OK) return st;
+  const size_t real = s->precision == BA_FP64 ? sizeof(double) : sizeof(float);
+  *bytes = layout(bb, bb->tables[which], real).total;
+  return BA_OK;
+}
+
+ba_status ba_solve_batched(ba_batch b, const ba_settings* s, double* poses, double* points,
+                           const double* obs_uv, const double* obs_w, void* workspace,
+                           size_t ws_bytes, ba_report* reports, ba_iter_trace* traces,
+                           void* stream) {
+  if (!b) return set_error(BA_ERR_INVALID_ARG, "batch is NULL");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  if (!poses || (!points && b->n_points > 0) || (!obs_uv && b->n_obs > 0) || !reports)
+    return set_error(BA_ERR_INVALID_ARG, "NULL device array");
+  DevUser U{};
+  U.poses = poses;
+  U.points = points;
+  U.obs_uv = obs_uv;
+  U.obs_w = obs_w;
+  U.reports = reports;
+  U.traces = traces;
+  std::lock_guard<std::mutex> lk(b->mu);
+  return launch(b, s, Op::Solve, U, workspace, ws_bytes, stream, obs_w != nullptr);
+}
+
+ba_status ba_solve(ba_window w, const ba_settings* s, double* poses, double* points,
+                   const double* obs_uv, const double* obs_w, void* workspace, size_t ws_bytes,
+                   ba_report* report, ba_iter_trace* trace, void* stream) {
+  if (!w) return set_error(BA_ERR_INVALID_ARG, "window is NULL");
+  if (!w->batch) return set_error(BA_ERR_STATE, "host-only window cannot be solved");
+  return ba_solve_batched(w->batch, s, poses, points, obs_uv, obs_w, workspace, ws_bytes, report,
+                          trace, stream);
+}
+
+ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double* poses,
+                     const double* points, const double* obs_uv, const double* obs_w,
+                     const double* grad_poses, const double* grad_points, double* grad_uv,
+                     double* grad_w, void* workspace, size_t ws_bytes, ba_report* reports,
+                     void* stream) {
+  if (w && !w->batch && !b) return set_error(BA_ERR_STATE, "host-only window");
+  ba_batch_s* bb = batch_of(w, b);
+  if (!bb) return set_error(BA_ERR_INVALID_ARG, "exactly one of w, b must be given");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  if (!poses || (!points && bb->n_points > 0) || (!obs_uv && bb->n_obs > 0) || !grad_poses ||
+      (!grad_uv && bb->n_obs > 0))
+    return set_error(BA_ERR_INVALID_ARG, "NULL device array");
+  DevUser U{};
+  U.poses = const_cast<double*>(poses);
+  U.points = const_cast<double*>(points);
+  U.obs_uv = obs_uv;
+  U.obs_w = obs_w;
+  U.reports = reports;
+  U.grad_poses = grad_poses;
+  U.grad_points = grad_points;
+  U.grad_uv = grad_uv;
+  U.grad_w = grad_w;
+  std::lock_guard<std::mutex> lk(bb->mu);
+  return launch(bb, s, Op::Adjoint, U, workspace, ws_bytes, stream, obs_w != nullptr);
+}
+
+ba_status ba_profile_stages(ba_batch b, const ba_settings* s, double* poses, double* points,
+                            const double* obs_uv, const double* obs_w, void* workspace,
+                            size_t ws_bytes, ba_report* reports, void* stream, double* stage_ms) {
+  if (!b || !stage_ms) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  if (!poses || (!points && b->n_points > 0) || (!obs_uv && b->n_obs > 0) || !reports)
+    return set_error(BA_ERR_INVALID_ARG, "NULL device array");
+  DevUser U{};
+  U.poses = poses;
+  U.points = points;
+  U.obs_uv = obs_uv;
+  U.obs_w = obs_w;
+  U.reports = reports;
+  std::lock_guard<std::mutex> lk(b->mu);
+  return launch(b, s, Op::Timed, U, workspace, ws_bytes, stream, obs_w != nullptr, stage_ms);
+}
+
+ba_status ba_set_launch(ba_batch b, int32_t chunk_obs) {
+  if (!b || chunk_obs < kChunkMin || chunk_obs > kChunkMax)
+    return set_error(BA_ERR_INVALID_ARG, "chunk_obs out of range");
+  std::lock_guard<std::mutex> lk(b->mu);
+  ba_status s = upload_tables(b, 0, kTileSmall, chunk_obs);
+  if (s != BA_OK) return s;
+  s = upload_tables(b, 1, kTileLarge, chunk_obs);
+  if (s != BA_OK) return s;
+  b->chunk_obs = chunk_obs;
+  return BA_OK;
+}
+
+ba_status ba_autotune(ba_batch b, const ba_settings* s, double* poses, double* points,
+                      const double* obs_uv, const double* obs_w, void* workspace, size_t ws_bytes,
+                      void* stream, int32_t* chosen_chunk_obs) {
+  if (!b) return set_error(BA_ERR_INVALID_ARG, "batch is NULL");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  // cache lookup
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, b->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  int bucket = 0;
+  for (int64_t n = b->n_obs; n > 1; n >>= 1) ++bucket;
+  std::ostringstream keyss;
+  keyss << prop.gcnArchName << "|" << s->precision << "|" << b->wins.size() << "|" << bucket << "|" << b->max_nf;
+  const std::string key = keyss.str();
+  const char* cache = std::getenv("BA_TUNE_CACHE");
+  if (cache) {
+    std::ifstream in(cache);
+    std::string k;
+    int v;
+    while (in >> k >> v)
+      if (k == key && v >= kChunkMin && v <= kChunkMax) {
+        if ((st = ba_set_launch(b, v)) != BA_OK) return st;
+        if (chosen_chunk_obs) *chosen_chunk_obs = v;
+        return BA_OK;
+      }
+  }
+  // The timed runs solve a copy-free short problem: the state arrays are
+  // modified, so the caller passes scratch copies.
+  ba_settings probe = *s;
+  probe.max_iters = std::min(s->max_iters, 3);
+  if (probe.max_iters < 1) probe.max_iters = 1;
+  ba_report* reports = nullptr;
+  e = hipMalloc(&reports, sizeof(ba_report) * b->wins.size());
+  if (e != hipSuccess) return set_error(BA_ERR_OOM, "autotune reports");
+  const int cands[] = {1024, 2048, 4096, 8192, 16384};
+  float best_ms = 1e30f;
+  int best = b->chunk_obs;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  for (int c : cands) {
+    if ((st = ba_set_launch(b, c)) != BA_OK) break;
+    size_t need = 0;
+    if ((st = ba_workspace_size(nullptr, b, &probe, &need)) != BA_OK) break;
+    if (need > ws_bytes) continue;
+    float ms_best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      (void)hipEventRecord(e0, hs);
+      st = ba_solve_batched(b, &probe, poses, points, obs_uv, obs_w, workspace, ws_bytes, reports,
+                            nullptr, stream);
+      (void)hipEventRecord(e1, hs);
+      if (st != BA_OK) break;
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ms_best = std::min(ms_best, ms);
+    }
+    if (st != BA_OK) break;
+    if (ms_best < best_ms) {
+      best_ms = ms_best;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(reports);
+  if (st != BA_OK) return st;
+  if ((st = ba_set_launch(b, best)) != BA_OK) return st;
+  if (cache) {
+    std::ofstream outf(cache, std::ios::app);
+    outf << key << " " << best << "\n";
+  }
+  if (chosen_chunk_obs) *chosen_chunk_obs = best;
+  return BA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Structures shared by the host launcher and the gfx950 kernels.
+#pragma once
+
+#include <cstdint>
+
+#include "../../include/ba.h"
+
+namespace ba {
+
+// Per-window structure, uploaded once per plan.
+struct WinDev {
+  int32_t n_poses, n_points, n_cams, n_free;
+  int32_t pose_off, point_off, cam_off, obs_off;   // first pose / landmark / camera / observation
+  int32_t pair_off, chunk_begin, chunk_end, pad;
+};
+
+// Per-window LM state, in the workspace.
+struct WinState {
+  double lambda;      // damping of the next attempt
+  double cost;        // F at the current state
+  double cand_cost;   // F at the last candidate
+  double init_cost;   // F at the input state
+  int32_t cur;        // which buffer holds the current state: 0 user arrays, 1 workspace
+  int32_t fail;       // this attempt met a non-positive pivot
+  int32_t accepted, chol_failures, depth_rejects, iters, status, pad;
+};
+
+// Read-only plan arrays (batch-global indices unless stated).
+struct DevPlan {
+  const WinDev* win;
+  const int32_t* free_slot;       // per pose: free slot in its window or -1
+  const double* cam;              // per camera: fx fy cx cy R(9) t(3)
+  const int32_t* lm_pair_begin;   // per landmark + 1: first pair
+  const uint8_t* lm_nfree;        // per landmark: free pairs (stored first)
+  const int32_t* pair_obs_begin;  // per pair + 1: first observation (plan order)
+  const int32_t* pair_lm;         // per pair: landmark
+  const uint8_t* pair_pose;       // per pair: window-local pose
+  const uint8_t* obs_cam;         // per observation: window-local camera
+  const int32_t* obs_perm;        // per observation: window-local user index
+  int32_t n_windows;
+};
+
+struct DevTiles {
+  const int32_t* tile_lm_begin;
+  const int32_t* chunk_window;
+  const int32_t* chunk_tile_begin;
+  const int64_t* chunk_part_off;
+  int32_t n_chunks;
+};
+
+template <typename Real>
+struct DevWork {
+  Real* du;                 // per observation, plan order: u - cx
+  Real* dv;                 // v - cy
+  Real* w;                  // weight, NULL when every weight is 1
+  double* poses_b;          // second state buffer (candidate / current)
+  double* points_b;
+  WinState* state;
+  double* dp;               // per window, kDpStride doubles: the reduced-system solution
+  Real* part;               // chunk partials of S, the reduced rhs and diag(U)
+  double* part_cost_a;      // per chunk: sum w rho at the current state
+  double* part_cost_b;      // per chunk: sum w rho at the candidate
+  int32_t* part_flag_a;     // per chunk: a landmark block was not positive definite
+  int32_t* part_flag_b;     // per chunk: a candidate depth <= min_depth
+};
+
+struct DevUser {
+  double* poses;
+  double* points;
+  const double* obs_uv;
+  const double* obs_w;
+  ba_report* reports;
+  ba_iter_trace* traces;
+  const double* grad_poses;
+  const double* grad_points;
+  double* grad_uv;
+  double* grad_w;
+};
+
+struct DevSettings {
+  double lambda_init, lambda_up, lambda_down, lambda_min, lambda_max;
+  double huber_delta, min_depth;
+  int32_t max_iters;
+  int32_t pad;
+};
+
+constexpr int kDpStride = 192;
+
+}  // namespace ba

@@ -1,0 +1,1381 @@
+// gfx950 kernels of the sliding-window sparse Levenberg-Marquardt bundle adjuster.
+//
+// The method (paper Sec. 2.2, Eq. 2 and Eq. 3, and the sentence after Eq. 3):
+// per-observation pinhole reprojection residuals with a Huber kernel, the
+// normal equations in blocks (U_i per pose, V_j per landmark, W_ij per
+// pose-landmark pair), elimination of the landmarks by the Schur complement,
+// a Cholesky solve of the reduced camera system for the poses, then point
+// back-substitution.  One LM attempt is four launches over all windows of a
+// batch:
+//
+//   pass_a     per chunk of landmarks: linearise every observation, reduce the
+//              per-pair W, per-landmark V and per-pose U blocks, eliminate each
+//              landmark (V* = L D L^T, Z = W L^-T |D|^-1/2) and accumulate the
+//              chunk's private partial of S = U* - sum Z Z^T and of the reduced
+//              right-hand side in LDS
+//   reduce     per window: sum the chunk partials in FP64 in a fixed order,
+//              damp, blocked Cholesky (6x6 blocks) of S, two triangular solves,
+//              candidate poses T' = Exp(dp) T
+//   pass_b     per chunk: re-linearise (cheaper than storing W), back-substitute
+//              dl_j, candidate points, robust cost of the candidate
+//   accept     per window: compare costs, update lambda, switch state buffers
+//
+// The observation stream is coalesced SoA (du, dv, w) in landmark-major order.
+// Within a workgroup, a tile of at most TP pairs is handled one thread per pair
+// (linearisation), one thread per landmark (3x3 elimination) and a flat loop
+// over the landmark's upper pose-pair blocks (Schur products, LDS atomics).
+// Every kernel of the adjoint (ADJ = true) reuses the same passes with the exact
+// Hessian, lambda = 0 and the loss cotangent as right-hand side.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace ba {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int xcd_chunk(int b, int G) {
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of chunks so that one window's chunks share an L2.
+  const int q = G >> 3, r = G & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ void huber(double s, double delta, double& rho, double& d1,
+                                      double& d2) {
+  if (delta > 0.0 && delta < 1e300 && s > delta * delta) {
+    const double sq = sqrt(s);
+    rho = 2.0 * delta * sq - delta * delta;
+    d1 = delta / sq;
+    d2 = -0.5 * delta / (s * sq);
+  } else {
+    rho = s;
+    d1 = 1.0;
+    d2 = 0.0;
+  }
+}
+
+__device__ __forceinline__ int blk_index(int i, int j, int nf) {
+  // upper block (i <= j) of an nf x nf block matrix, row-major over the triangle
+  return i * nf - (i * (i - 1)) / 2 + (j - i);
+}
+
+// Linearisation of one observation at (pose R, t | point p).
+template <typename Real>
+struct Lin {
+  double rho_w;     // w * rho(s)
+  double d1, d2;    // rho'(s), rho''(s)
+  double wo;        // observation weight
+  double X, Y, Z;   // camera-frame point
+  Real r[2];        // residual pi(x_c) - o
+  Real a0[3], a1[3];  // rows of A R_c (A = d pi / d x_c)
+  Real xb[3];       // base-frame point
+};
+
+template <typename Real>
+__device__ __forceinline__ Lin<Real> linearise(const double* __restrict__ xb, const double* C,
+                                               double du, double dv, double wo, double delta) {
+  Lin<Real> L;
+  const double X = C[4] * xb[0] + C[5] * xb[1] + C[6] * xb[2] + C[13];
+  const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
+  const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
+  const double iz = 1.0 / Z;
+  const double xz = X * iz, yz = Y * iz;
+  const double r0 = C[0] * xz - du, r1 = C[1] * yz - dv;
+  const double s = r0 * r0 + r1 * r1;
+  double rho, d1, d2;
+  huber(s, delta, rho, d1, d2);
+  L.rho_w = wo * rho;
+  L.d1 = d1;
+  L.d2 = d2;
+  L.wo = wo;
+  L.X = X;
+  L.Y = Y;
+  L.Z = Z;
+  L.r[0] = (Real)r0;
+  L.r[1] = (Real)r1;
+  const double fi = C[0] * iz, gi = C[1] * iz;
+  for (int c = 0; c < 3; ++c) {
+    L.a0[c] = (Real)(fi * (C[4 + c] - xz * C[10 + c]));
+    L.a1[c] = (Real)(gi * (C[7 + c] - yz * C[10 + c]));
+    L.xb[c] = (Real)xb[c];
+  }
+  return L;
+}
+
+template <typename Real>
+__device__ __forceinline__ void cross3(const Real* a, const Real* b, Real* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Block accumulators of one pose-landmark pair.
+template <typename Real>
+struct PairAcc {
+  Real U[21];   // upper triangle of the 6x6 pose block, row-major
+  Real gp[6];   // pose gradient
+  Real W[18];   // 6x3 pose-point block
+  Real V[6];    // upper triangle of the 3x3 point block (00 01 02 11 12 22)
+  Real gl[3];   // point gradient
+};
+
+template <typename Real>
+__device__ __forceinline__ void pair_zero(PairAcc<Real>& A) {
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A.U[k] = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) A.gp[k] = 0;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) A.W[k] = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) A.V[k] = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) A.gl[k] = 0;
+}
+
+// Add one observation: the Gauss-Newton blocks with IRLS weight w rho', and in
+// ADJ mode the remaining terms of the exact Hessian (second derivatives of the
+// residual and the rho'' term).
+template <typename Real, bool ADJ>
+__device__ __forceinline__ void pair_add(PairAcc<Real>& A, const Lin<Real>& L, const Real* Rp,
+                                         bool free_pose, const double* C) {
+  Real Jp[2][6], Jl[2][3];
+  const Real* ar[2] = {L.a0, L.a1};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const Real* a = ar[k];
+    Jp[k][0] = a[0];
+    Jp[k][1] = a[1];
+    Jp[k][2] = a[2];
+    Real c[3];
+    cross3(L.xb, a, c);
+    Jp[k][3] = c[0];
+    Jp[k][4] = c[1];
+    Jp[k][5] = c[2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Jl[k][m] = Rp[m] * a[0] + Rp[3 + m] * a[1] + Rp[6 + m] * a[2];
+  }
+  const Real w1 = (Real)(L.wo * L.d1);
+  Real wJp[2][6], wJl[2][3];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) wJp[k][m] = w1 * Jp[k][m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) wJl[k][m] = w1 * Jl[k][m];
+  }
+  if (free_pose) {
+    int u = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+#pragma unroll
+      for (int c = r; c < 6; ++c) A.U[u++] += wJp[0][r] * Jp[0][c] + wJp[1][r] * Jp[1][c];
+      A.gp[r] += wJp[0][r] * L.r[0] + wJp[1][r] * L.r[1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A.W[3 * r + c] += wJp[0][r] * Jl[0][c] + wJp[1][r] * Jl[1][c];
+    }
+  }
+  {
+    int v = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = r; c < 3; ++c) A.V[v++] += wJl[0][r] * Jl[0][c] + wJl[1][r] * Jl[1][c];
+      A.gl[r] += wJl[0][r] * L.r[0] + wJl[1][r] * L.r[1];
+    }
+  }
+  if constexpr (ADJ) {
+    // 2 w rho'' (J^T r)(J^T r)^T
+    Real q[9];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) q[m] = Jp[0][m] * L.r[0] + Jp[1][m] * L.r[1];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) q[6 + m] = Jl[0][m] * L.r[0] + Jl[1][m] * L.r[1];
+    const Real w2 = (Real)(2.0 * L.wo * L.d2);
+    // w rho' sum_k r_k Hess(r_k) = w rho' (B^T Q B + M(a)),  B = [I, -[x_b]x, R_i]
+    const double X = L.X, Y = L.Y;
+    const double iz = 1.0 / L.Z;
+    const Real pxz = (Real)(-(double)L.r[0] * C[0] * iz * iz);
+    const Real pyz = (Real)(-(double)L.r[1] * C[1] * iz * iz);
+    const Real pzz = (Real)(2.0 * ((double)L.r[0] * C[0] * X + (double)L.r[1] * C[1] * Y) * iz * iz * iz);
+    Real c0[3], c1[3], c2[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      c0[m] = (Real)C[4 + m];
+      c1[m] = (Real)C[7 + m];
+      c2[m] = (Real)C[10 + m];
+    }
+    Real Q[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        Q[a][b] = pxz * (c0[a] * c2[b] + c2[a] * c0[b]) + pyz * (c1[a] * c2[b] + c2[a] * c1[b]) +
+                  pzz * c2[a] * c2[b];
+    // columns of B
+    Real Bc[9][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      Real e[3] = {0, 0, 0};
+      e[m] = 1;
+      Bc[m][0] = e[0];
+      Bc[m][1] = e[1];
+      Bc[m][2] = e[2];
+      cross3(e, L.xb, Bc[3 + m]);   // e_m x x_b = -[x_b]x e_m
+      Bc[6 + m][0] = Rp[0 + m];
+      Bc[6 + m][1] = Rp[3 + m];
+      Bc[6 + m][2] = Rp[6 + m];
+    }
+    Real QB[9][3];
+#pragma unroll
+    for (int n = 0; n < 9; ++n)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        QB[n][a] = Q[a][0] * Bc[n][0] + Q[a][1] * Bc[n][1] + Q[a][2] * Bc[n][2];
+    Real ab[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) ab[m] = L.r[0] * L.a0[m] + L.r[1] * L.a1[m];
+    const Real ax = ab[0] * L.xb[0] + ab[1] * L.xb[1] + ab[2] * L.xb[2];
+    // M(a) entry (m, n) in (rho, phi, point) order
+    auto Mab = [&](int m, int n) -> Real {
+      if (m > n) {
+        const int t = m;
+        m = n;
+        n = t;
+      }
+      if (m >= 3 && m < 6 && n >= 3 && n < 6) {
+        const int a = m - 3, b = n - 3;
+        return (Real)0.5 * (L.xb[a] * ab[b] + ab[a] * L.xb[b]) - (a == b ? ax : (Real)0);
+      }
+      if (m < 3 && n >= 3 && n < 6) {
+        // M_rho,phi[a][b] = ([a]x)[a][b] / 2
+        const int a = m, b = n - 3;
+        Real sk;
+        if (a == b) sk = 0;
+        else if (a == 0) sk = (b == 1) ? -ab[2] : ab[1];
+        else if (a == 1) sk = (b == 0) ? ab[2] : -ab[0];
+        else sk = (b == 0) ? -ab[1] : ab[0];
+        return (Real)0.5 * sk;
+      }
+      if (m >= 3 && m < 6 && n >= 6) {
+        // M_phi,point = -[a]x R_i
+        const int a = m - 3, c = n - 6;
+        Real s[3];   // row a of [a]x
+        if (a == 0) { s[0] = 0; s[1] = -ab[2]; s[2] = ab[1]; }
+        else if (a == 1) { s[0] = ab[2]; s[1] = 0; s[2] = -ab[0]; }
+        else { s[0] = -ab[1]; s[1] = ab[0]; s[2] = 0; }
+        return -(s[0] * Rp[c] + s[1] * Rp[3 + c] + s[2] * Rp[6 + c]);
+      }
+      return (Real)0;
+    };
+    auto H2 = [&](int m, int n) -> Real {
+      const Real t = Bc[m][0] * QB[n][0] + Bc[m][1] * QB[n][1] + Bc[m][2] * QB[n][2];
+      return w1 * (t + Mab(m, n)) + w2 * q[m] * q[n];
+    };
+    if (free_pose) {
+      int u = 0;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+#pragma unroll
+        for (int c = r; c < 6; ++c) A.U[u++] += H2(r, c);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) A.W[3 * r + c] += H2(r, 6 + c);
+      }
+    }
+    int v = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = r; c < 3; ++c) A.V[v++] += H2(6 + r, 6 + c);
+  }
+}
+
+// 3x3 symmetric L D L^T (no pivoting).  V = (v00 v01 v02 v11 v12 v22).
+// ok = all pivots positive (spd) or merely non-zero (indef).
+template <typename Real>
+struct LDL3 {
+  Real l10, l20, l21;
+  Real isd[3];   // |d_k|^-1/2
+  Real sg[3];    // sign(d_k)
+};
+
+template <typename Real>
+__device__ __forceinline__ bool ldl3(const Real* V, bool spd, LDL3<Real>& F) {
+  const Real d0 = V[0];
+  const Real l10 = V[1] / d0, l20 = V[2] / d0;
+  const Real d1 = V[3] - l10 * l10 * d0;
+  const Real l21 = (V[4] - l20 * l10 * d0) / d1;
+  const Real d2 = V[5] - l20 * l20 * d0 - l21 * l21 * d1;
+  F.l10 = l10;
+  F.l20 = l20;
+  F.l21 = l21;
+  const Real d[3] = {d0, d1, d2};
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const bool good = spd ? (d[k] > (Real)0) : (d[k] != (Real)0);
+    ok = ok && good && isfinite((double)d[k]);
+    const Real ad = fabs(d[k]);
+    F.isd[k] = (Real)1 / sqrt(ad);
+    F.sg[k] = d[k] < (Real)0 ? (Real)-1 : (Real)1;
+  }
+  return ok && isfinite((double)l10) && isfinite((double)l20) && isfinite((double)l21);
+}
+
+// solve L z = w (unit lower), then scale by |D|^-1/2: z_bar = |D|^-1/2 L^-1 w
+template <typename Real>
+__device__ __forceinline__ void ldl3_half(const LDL3<Real>& F, const Real* w, Real* z) {
+  const Real z0 = w[0];
+  const Real z1 = w[1] - F.l10 * z0;
+  const Real z2 = w[2] - F.l20 * z0 - F.l21 * z1;
+  z[0] = z0 * F.isd[0];
+  z[1] = z1 * F.isd[1];
+  z[2] = z2 * F.isd[2];
+}
+
+// x = V^-1 c = L^-T D^-1 L^-1 c
+template <typename Real>
+__device__ __forceinline__ void ldl3_solve(const LDL3<Real>& F, const Real* c, Real* x) {
+  Real h[3];
+  ldl3_half(F, c, h);
+  const Real y0 = h[0] * F.isd[0] * F.sg[0];
+  const Real y1 = h[1] * F.isd[1] * F.sg[1];
+  const Real y2 = h[2] * F.isd[2] * F.sg[2];
+  x[2] = y2;
+  x[1] = y1 - F.l21 * x[2];
+  x[0] = y0 - F.l10 * x[1] - F.l20 * x[2];
+}
+
+// V + lambda * diag(max(V_kk, 1e-9)) on the packed upper triangle
+template <typename Real>
+__device__ __forceinline__ void damp3(Real* V, double lam) {
+  const int dI[3] = {0, 3, 5};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double v = (double)V[dI[k]];
+    V[dI[k]] = (Real)(v + lam * (v > 1e-9 ? v : 1e-9));
+  }
+}
+
+// Block-wide sum of a double, deterministic (fixed shuffle tree + fixed order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) scratch[wv] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NT / 64; ++k) t += scratch[k];
+  __syncthreads();
+  return t;   // valid in thread 0
+}
+
+// Exclusive scan of n (<= NT) ints in LDS, in place, total at a[n].
+template <int NT>
+__device__ __forceinline__ void block_scan(int* a, int n, int* scratch) {
+  const int t = threadIdx.x;
+  int v = t < n ? a[t] : 0;
+  // inclusive scan inside the wave
+  const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  if (lane == 63) scratch[wv] = v;
+  __syncthreads();
+  int base = 0;
+  for (int k = 0; k < wv; ++k) base += scratch[k];
+  int total = 0;
+  for (int k = 0; k < NT / 64; ++k) total += scratch[k];
+  const int orig = t < n ? a[t] : 0;
+  __syncthreads();
+  if (t < n) a[t] = base + v - orig;
+  if (t == 0) a[n] = total;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout of the chunk kernels
+// ---------------------------------------------------------------------------
+
+struct ChunkLds {
+  // window caches
+  static constexpr int kPose = 64 * 12;   // doubles
+  static constexpr int kCam = 32 * 16;    // doubles
+};
+
+// Window caches: poses (current state), camera table, free slots.
+__device__ __forceinline__ void load_window(const DevPlan& P, const WinDev& W,
+                                            const double* __restrict__ poses, double* sPose,
+                                            double* sCam, int* sFree) {
+  for (int k = threadIdx.x; k < W.n_poses * 12; k += blockDim.x) sPose[k] = poses[k];
+  for (int k = threadIdx.x; k < W.n_cams * 16; k += blockDim.x)
+    sCam[k] = P.cam[16 * W.cam_off + k];
+  for (int k = threadIdx.x; k < W.n_poses; k += blockDim.x)
+    sFree[k] = P.free_slot[W.pose_off + k];
+}
+
+// ---------------------------------------------------------------------------
+// init, pack
+// ---------------------------------------------------------------------------
+
+template <typename Real>
+__global__ void k_init(DevPlan P, DevWork<Real> K, DevSettings S) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= P.n_windows) return;
+  WinState st;
+  st.lambda = S.lambda_init;
+  st.cost = 0.0;
+  st.cand_cost = 0.0;
+  st.init_cost = 0.0;
+  st.cur = 0;
+  st.fail = 0;
+  st.accepted = st.chol_failures = st.depth_rejects = st.iters = st.status = st.pad = 0;
+  K.state[w] = st;
+}
+
+// Gather the user's observations (user order, FP64) into the plan-ordered SoA
+// stream: du = u - cx, dv = v - cy (principal point removed before rounding to
+// the stream precision), w.
+template <typename Real>
+__global__ void k_pack(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U) {
+  const int chunk = blockIdx.x;
+  const int wi = T.chunk_window[chunk];
+  const WinDev W = P.win[wi];
+  const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
+  if (t1 <= t0) return;
+  const int l0 = T.tile_lm_begin[t0], l1 = T.tile_lm_begin[t1];
+  const int o0 = P.pair_obs_begin[P.lm_pair_begin[l0]];
+  const int o1 = P.pair_obs_begin[P.lm_pair_begin[l1]];
+  for (int o = o0 + threadIdx.x; o < o1; o += blockDim.x) {
+    const int u = W.obs_off + P.obs_perm[o];
+    const double* C = P.cam + 16 * (W.cam_off + P.obs_cam[o]);
+    K.du[o] = (Real)(U.obs_uv[2 * u] - C[2]);
+    K.dv[o] = (Real)(U.obs_uv[2 * u + 1] - C[3]);
+    if (K.w) K.w[o] = (Real)U.obs_w[u];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass A: linearise + per-landmark elimination + chunk partial of S
+// ---------------------------------------------------------------------------
+
+template <typename Real, int TP, bool ADJ>
+__global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Real> K,
+                                               DevUser U, DevSettings S, int it) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const int wi = T.chunk_window[chunk];
+  const WinDev W = P.win[wi];
+  const WinState& st = K.state[wi];
+  const int tid = threadIdx.x;
+  const int cur = ADJ ? 0 : st.cur;
+  const double lam = ADJ ? 0.0 : st.lambda;
+  const double* poses = (cur ? K.poses_b : U.poses) + 12 * W.pose_off;
+  const double* points = (cur ? K.points_b : U.points) + 3 * W.point_off;
+  const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
+
+  double* sPose = reinterpret_cast<double*>(smem);
+  double* sCam = sPose + ChunkLds::kPose;
+  double* sRed = sCam + ChunkLds::kCam;                       // 16 doubles
+  int* sFree = reinterpret_cast<int*>(sRed + 16);             // 64
+  int* sScan = sFree + 64;                                    // 16
+  int* sLW = sScan + 16;                                      // TP + 1
+  int* sPS = sLW + TP + 4;                                    // TP: pair slot
+  int* sPL = sPS + TP;                                        // TP: pair landmark (tile-local)
+  int* sFlag = sPL + TP;                                      // 4
+  Real* sS = reinterpret_cast<Real*>(sFlag + 4);              // nblk * 36
+  Real* sB = sS + nblk * 36;                                  // nS
+  Real* sD = sB + nS;                                         // nS
+  Real* sPZ = sD + nS;                                        // TP * 18
+  Real* sPV = sPZ + TP * 18;                                  // TP * 9
+  Real* sLF = sPV + TP * 9;                                   // TP * 12
+
+  load_window(P, W, poses, sPose, sCam, sFree);
+  for (int k = tid; k < nblk * 36 + 2 * nS; k += TP) sS[k] = (Real)0;
+  if (tid == 0) sFlag[0] = 0;
+  __syncthreads();
+
+  double cost = 0.0;
+  const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
+  for (int t = t0; t < t1; ++t) {
+    const int l0 = T.tile_lm_begin[t], l1 = T.tile_lm_begin[t + 1];
+    const int p0 = P.lm_pair_begin[l0], p1 = P.lm_pair_begin[l1];
+    const int nP = p1 - p0, nL = l1 - l0;
+
+    // ---- phase 1: one thread per pair
+    if (tid < nP) {
+      const int gp = p0 + tid;
+      const int lm = P.pair_lm[gp];                   // batch-global landmark
+      const int pose = P.pair_pose[gp];
+      const int slot = sFree[pose];
+      sPS[tid] = slot;
+      sPL[tid] = lm - l0;
+      const double* Rt = sPose + 12 * pose;
+      const double px = points[3 * (lm - W.point_off)], py = points[3 * (lm - W.point_off) + 1],
+                   pz = points[3 * (lm - W.point_off) + 2];
+      double xb[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        xb[a] = Rt[4 * a] * px + Rt[4 * a + 1] * py + Rt[4 * a + 2] * pz + Rt[4 * a + 3];
+      Real Rp[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
+      PairAcc<Real> A;
+      pair_zero(A);
+      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
+      for (int o = o0; o < o1; ++o) {
+        const double* C = sCam + 16 * P.obs_cam[o];
+        const double wo = K.w ? (double)K.w[o] : 1.0;
+        const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
+                                            S.huber_delta);
+        cost += L.rho_w;
+        pair_add<Real, ADJ>(A, L, Rp, slot >= 0, C);
+      }
+      if (slot >= 0) {
+        Real* Sd = sS + 36 * blk_index(slot, slot, nf);
+        int u = 0;
+        for (int r = 0; r < 6; ++r)
+          for (int c = r; c < 6; ++c) atomicAdd(Sd + 6 * r + c, A.U[u++]);
+        if (!ADJ) {
+          const int dI[6] = {0, 6, 11, 15, 18, 20};
+          for (int r = 0; r < 6; ++r) {
+            atomicAdd(sB + 6 * slot + r, -A.gp[r]);
+            atomicAdd(sD + 6 * slot + r, A.U[dI[r]]);
+          }
+        }
+        for (int k = 0; k < 18; ++k) sPZ[18 * tid + k] = A.W[k];
+      }
+      for (int k = 0; k < 6; ++k) sPV[9 * tid + k] = A.V[k];
+      for (int k = 0; k < 3; ++k) sPV[9 * tid + 6 + k] = A.gl[k];
+    }
+    __syncthreads();
+
+    // ---- phase 2: one thread per landmark: V*, L D L^T, h
+    if (tid < nL) {
+      const int lm = l0 + tid;
+      const int q0 = P.lm_pair_begin[lm] - p0, q1 = P.lm_pair_begin[lm + 1] - p0;
+      Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
+      for (int q = q0; q < q1; ++q) {
+        for (int k = 0; k < 6; ++k) V[k] += sPV[9 * q + k];
+        for (int k = 0; k < 3; ++k) g[k] += sPV[9 * q + 6 + k];
+      }
+      Real c[3];
+      if (!ADJ) {
+        damp3(V, lam);
+        c[0] = -g[0];
+        c[1] = -g[1];
+        c[2] = -g[2];
+      } else {
+        const int ul = lm;   // batch-global landmark = packed user index
+        for (int k = 0; k < 3; ++k) c[k] = U.grad_points ? (Real)U.grad_points[3 * ul + k] : (Real)0;
+      }
+      LDL3<Real> F;
+      if (!ldl3(V, !ADJ, F)) sFlag[0] = 1;
+      Real hb[3];
+      ldl3_half(F, c, hb);
+      Real* f = sLF + 12 * tid;
+      f[0] = F.l10;
+      f[1] = F.l20;
+      f[2] = F.l21;
+      for (int k = 0; k < 3; ++k) {
+        f[3 + k] = F.isd[k];
+        f[6 + k] = F.sg[k];
+        f[9 + k] = hb[k];
+      }
+      const int nfp = P.lm_nfree[lm];
+      sLW[tid] = nfp * (nfp + 1) / 2;
+    }
+    __syncthreads();
+    block_scan<TP>(sLW, nL, sScan);
+
+    // ---- phase 3: one thread per free pair: Z_bar = W L^-T |D|^-1/2, rhs
+    if (tid < nP && sPS[tid] >= 0) {
+      const int slot = sPS[tid];
+      const Real* f = sLF + 12 * sPL[tid];
+      LDL3<Real> F;
+      F.l10 = f[0];
+      F.l20 = f[1];
+      F.l21 = f[2];
+      for (int k = 0; k < 3; ++k) {
+        F.isd[k] = f[3 + k];
+        F.sg[k] = f[6 + k];
+      }
+      Real* Z = sPZ + 18 * tid;
+      Real sh[3];
+      for (int k = 0; k < 3; ++k) sh[k] = f[6 + k] * f[9 + k];
+      for (int r = 0; r < 6; ++r) {
+        Real z[3];
+        ldl3_half(F, Z + 3 * r, z);
+        Z[3 * r] = z[0];
+        Z[3 * r + 1] = z[1];
+        Z[3 * r + 2] = z[2];
+        atomicAdd(sB + 6 * slot + r, -(z[0] * sh[0] + z[1] * sh[1] + z[2] * sh[2]));
+      }
+    }
+    __syncthreads();
+
+    // ---- phase 4: flat loop over the upper pose-pair blocks of every landmark
+    const int total = sLW[nL];
+    for (int fidx = tid; fidx < total; fidx += TP) {
+      // landmark: last j with sLW[j] <= fidx
+      int lo = 0, hi = nL;   // invariant sLW[lo] <= fidx < sLW[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sLW[mid] <= fidx) lo = mid;
+        else hi = mid;
+      }
+      const int j = lo;
+      int k = fidx - sLW[j];
+      const int lm = l0 + j;
+      const int nfp = P.lm_nfree[lm];
+      int a = 0;
+      while (k >= nfp - a) {
+        k -= nfp - a;
+        ++a;
+      }
+      const int b = a + k;
+      const int qb = P.lm_pair_begin[lm] - p0;
+      const int qa = qb + a, qc = qb + b;
+      const int sa = sPS[qa], sc = sPS[qc];
+      const Real* Za = sPZ + 18 * qa;
+      const Real* Zc = sPZ + 18 * qc;
+      const Real* sg = sLF + 12 * j + 6;
+      Real* Sb = sS + 36 * blk_index(sa, sc, nf);
+      for (int r = 0; r < 6; ++r) {
+        const Real z0 = Za[3 * r] * sg[0], z1 = Za[3 * r + 1] * sg[1], z2 = Za[3 * r + 2] * sg[2];
+        for (int c = (a == b ? r : 0); c < 6; ++c)
+          atomicAdd(Sb + 6 * r + c, -(z0 * Zc[3 * c] + z1 * Zc[3 * c + 1] + z2 * Zc[3 * c + 2]));
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- chunk partial out
+  Real* part = K.part + T.chunk_part_off[chunk];
+  for (int k = tid; k < nblk * 36 + 2 * nS; k += TP) part[k] = sS[k];
+  const double tot = block_sum<TP>(cost, sRed);
+  if (tid == 0) {
+    K.part_cost_a[chunk] = tot;
+    K.part_flag_a[chunk] = sFlag[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reduce + blocked Cholesky of S + candidate poses (one workgroup per window)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void exp_se3(const double* xi, double* T /*3x4*/) {
+  const double rx = xi[0], ry = xi[1], rz = xi[2];
+  const double px = xi[3], py = xi[4], pz = xi[5];
+  const double th2 = px * px + py * py + pz * pz;
+  const double th = sqrt(th2);
+  double A, B, Cc;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    A = sin(th) / th;
+    const double s = sin(0.5 * th);
+    B = 2.0 * s * s / th2;
+    Cc = (th - sin(th)) / (th2 * th);
+  }
+  const double K[9] = {0, -pz, py, pz, 0, -px, -py, px, 0};
+  double K2[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      K2[3 * a + b] = K[3 * a] * K[b] + K[3 * a + 1] * K[3 + b] + K[3 * a + 2] * K[6 + b];
+  double R[9], J[9];
+  for (int k = 0; k < 9; ++k) {
+    const double I = (k % 4 == 0) ? 1.0 : 0.0;
+    R[k] = I + A * K[k] + B * K2[k];
+    J[k] = I + B * K[k] + Cc * K2[k];
+  }
+  for (int a = 0; a < 3; ++a) {
+    T[4 * a] = R[3 * a];
+    T[4 * a + 1] = R[3 * a + 1];
+    T[4 * a + 2] = R[3 * a + 2];
+    T[4 * a + 3] = J[3 * a] * rx + J[3 * a + 1] * ry + J[3 * a + 2] * rz;
+  }
+}
+
+template <typename Real, int NT, bool ADJ>
+__global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U,
+                                               DevSettings S, int it) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x;
+  const WinDev W = P.win[wi];
+  WinState& st = K.state[wi];
+  const int tid = threadIdx.x;
+  const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
+  double* sS = reinterpret_cast<double*>(smem);   // nblk * 36
+  double* sB = sS + nblk * 36;                    // nS
+  double* sD = sB + nS;                           // nS
+  int* sFail = reinterpret_cast<int*>(sD + nS);   // 1
+  const int c0 = W.chunk_begin, c1 = W.chunk_end;
+  const int ne = nblk * 36 + 2 * nS;
+
+  if (tid == 0) {
+    int f = 0;
+    for (int c = c0; c < c1; ++c) f |= K.part_flag_a[c];
+    sFail[0] = f;
+    if (!ADJ && it == 0) {
+      double F = 0.0;
+      for (int c = c0; c < c1; ++c) F += K.part_cost_a[c];
+      F *= 0.5;
+      st.cost = F;
+      st.init_cost = F;
+      if (!isfinite(F)) st.status = 1;
+    }
+  }
+  for (int e = tid; e < ne; e += NT) {
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) acc += (double)K.part[T.chunk_part_off[c] + e];
+    sS[e] = acc;
+  }
+  __syncthreads();
+  const double lam = st.lambda;
+  const double* poses = (ADJ || st.cur == 0 ? U.poses : K.poses_b) + 12 * W.pose_off;
+  if (ADJ) {
+    // right-hand side: tangent cotangent of the free poses plus the partials
+    for (int i = tid; i < W.n_poses; i += NT) {
+      const int f = P.free_slot[W.pose_off + i];
+      if (f < 0) continue;
+      const double* G = U.grad_poses + 12 * (W.pose_off + i);
+      const double* Tp = poses + 12 * i;
+      double M[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          M[3 * a + b] = G[4 * a] * Tp[4 * b] + G[4 * a + 1] * Tp[4 * b + 1] +
+                         G[4 * a + 2] * Tp[4 * b + 2] + G[4 * a + 3] * Tp[4 * b + 3];
+      sB[6 * f + 0] += G[3];
+      sB[6 * f + 1] += G[7];
+      sB[6 * f + 2] += G[11];
+      sB[6 * f + 3] += M[7] - M[5];
+      sB[6 * f + 4] += M[2] - M[6];
+      sB[6 * f + 5] += M[3] - M[1];
+    }
+  } else {
+    for (int e = tid; e < nS; e += NT) {
+      const int f = e / 6, r = e % 6;
+      const double d = sD[e];
+      sS[36 * blk_index(f, f, nf) + 7 * r] += lam * (d > 1e-9 ? d : 1e-9);
+    }
+  }
+  __syncthreads();
+  // mirror the diagonal blocks (only their upper triangles were accumulated)
+  for (int e = tid; e < nf * 36; e += NT) {
+    const int f = e / 36, r = (e % 36) / 6, c = e % 6;
+    if (c < r) {
+      double* D = sS + 36 * blk_index(f, f, nf);
+      D[6 * r + c] = D[6 * c + r];
+    }
+  }
+  __syncthreads();
+
+  // blocked Cholesky S = R^T R on 6x6 blocks (upper block storage)
+  bool failed = sFail[0] != 0;
+  for (int k = 0; k < nf && !failed; ++k) {
+    double* Dk = sS + 36 * blk_index(k, k, nf);
+    if (tid == 0) {
+      int ok = 1;
+      for (int a = 0; a < 6; ++a) {
+        double d = Dk[7 * a];
+        for (int m = 0; m < a; ++m) d -= Dk[6 * m + a] * Dk[6 * m + a];
+        if (!(d > 0.0) || !isfinite(d)) {
+          ok = 0;
+          break;
+        }
+        const double ra = sqrt(d);
+        Dk[7 * a] = ra;
+        for (int c = a + 1; c < 6; ++c) {
+          double v = Dk[6 * a + c];
+          for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * Dk[6 * m + c];
+          Dk[6 * a + c] = v / ra;
+        }
+      }
+      if (!ok) sFail[0] = 1;
+    }
+    __syncthreads();
+    failed = sFail[0] != 0;
+    if (failed) break;
+    // panel: R_kj = R_kk^-T S_kj, j > k (thread per column of each block)
+    const int npan = (nf - k - 1) * 6;
+    for (int e = tid; e < npan; e += NT) {
+      const int j = k + 1 + e / 6, col = e % 6;
+      double* B = sS + 36 * blk_index(k, j, nf);
+      double y[6];
+      for (int a = 0; a < 6; ++a) {
+        double v = B[6 * a + col];
+        for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * y[m];
+        y[a] = v / Dk[7 * a];
+      }
+      for (int a = 0; a < 6; ++a) B[6 * a + col] = y[a];
+    }
+    __syncthreads();
+    // trailing update: S_ij -= R_ki^T R_kj, k < i <= j
+    const int nt = nf - k - 1;
+    const int ntr = nt * (nt + 1) / 2 * 36;
+    for (int e = tid; e < ntr; e += NT) {
+      int bidx = e / 36;
+      const int rc = e % 36, r = rc / 6, c = rc % 6;
+      int i = 0;
+      while (bidx >= nt - i) {
+        bidx -= nt - i;
+        ++i;
+      }
+      const int j = i + bidx;
+      const double* Rki = sS + 36 * blk_index(k, k + 1 + i, nf);
+      const double* Rkj = sS + 36 * blk_index(k, k + 1 + j, nf);
+      double v = 0.0;
+      for (int m = 0; m < 6; ++m) v += Rki[6 * m + r] * Rkj[6 * m + c];
+      sS[36 * blk_index(k + 1 + i, k + 1 + j, nf) + rc] -= v;
+    }
+    __syncthreads();
+  }
+  if (!failed) {
+    // forward: R^T y = b
+    for (int k = 0; k < nf; ++k) {
+      const double* Dk = sS + 36 * blk_index(k, k, nf);
+      if (tid == 0) {
+        double* b = sB + 6 * k;
+        for (int a = 0; a < 6; ++a) {
+          double v = b[a];
+          for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * b[m];
+          b[a] = v / Dk[7 * a];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < (nf - k - 1) * 6; e += NT) {
+        const int j = k + 1 + e / 6, c = e % 6;
+        const double* B = sS + 36 * blk_index(k, j, nf);
+        double v = 0.0;
+        for (int m = 0; m < 6; ++m) v += B[6 * m + c] * sB[6 * k + m];
+        sB[6 * j + c] -= v;
+      }
+      __syncthreads();
+    }
+    // backward: R x = y
+    for (int k = nf - 1; k >= 0; --k) {
+      const double* Dk = sS + 36 * blk_index(k, k, nf);
+      if (tid == 0) {
+        double* b = sB + 6 * k;
+        for (int a = 5; a >= 0; --a) {
+          double v = b[a];
+          for (int m = a + 1; m < 6; ++m) v -= Dk[6 * a + m] * b[m];
+          b[a] = v / Dk[7 * a];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < k * 6; e += NT) {
+        const int i = e / 6, r = e % 6;
+        const double* B = sS + 36 * blk_index(i, k, nf);
+        double v = 0.0;
+        for (int m = 0; m < 6; ++m) v += B[6 * r + m] * sB[6 * k + m];
+        sB[6 * i + r] -= v;
+      }
+      __syncthreads();
+    }
+  }
+  double* dp = K.dp + kDpStride * wi;
+  for (int e = tid; e < nS; e += NT) dp[e] = failed ? 0.0 : sB[e];
+  if (ADJ) {
+    if (tid == 0 && U.reports) U.reports[wi].chol_failures = failed ? 1 : 0;
+    return;
+  }
+  if (tid == 0) st.fail = failed ? 1 : 0;
+  if (failed) return;
+  // candidate poses into the other buffer
+  double* cand = (st.cur == 0 ? K.poses_b : U.poses) + 12 * W.pose_off;
+  for (int i = tid; i < W.n_poses; i += NT) {
+    const int f = P.free_slot[W.pose_off + i];
+    const double* Tp = poses + 12 * i;
+    double* Tc = cand + 12 * i;
+    if (f < 0) {
+      for (int k = 0; k < 12; ++k) Tc[k] = Tp[k];
+      continue;
+    }
+    double D[12];
+    exp_se3(sB + 6 * f, D);
+    for (int a = 0; a < 3; ++a) {
+      for (int b = 0; b < 3; ++b)
+        Tc[4 * a + b] = D[4 * a] * Tp[b] + D[4 * a + 1] * Tp[4 + b] + D[4 * a + 2] * Tp[8 + b];
+      Tc[4 * a + 3] = D[4 * a] * Tp[3] + D[4 * a + 1] * Tp[7] + D[4 * a + 2] * Tp[11] + D[4 * a + 3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass B: back-substitution + candidate cost (LM) / adjoint gather (ADJ)
+// ---------------------------------------------------------------------------
+
+template <typename Real, int TP, bool ADJ>
+__global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U,
+                                               DevSettings S, int it) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const int wi = T.chunk_window[chunk];
+  const WinDev W = P.win[wi];
+  const WinState& st = K.state[wi];
+  const int tid = threadIdx.x;
+  if (!ADJ && st.fail) {
+    if (tid == 0) {
+      K.part_cost_b[chunk] = 0.0;
+      K.part_flag_b[chunk] = 0;
+    }
+    return;
+  }
+  const int cur = ADJ ? 0 : st.cur;
+  const double lam = ADJ ? 0.0 : st.lambda;
+  const double* poses = (cur ? K.poses_b : U.poses) + 12 * W.pose_off;
+  const double* points = (cur ? K.points_b : U.points) + 3 * W.point_off;
+  const double* cposes = (cur ? U.poses : K.poses_b) + 12 * W.pose_off;
+  double* cpoints = (cur ? U.points : K.points_b) + 3 * W.point_off;
+  const int nS = 6 * W.n_free;
+
+  double* sPose = reinterpret_cast<double*>(smem);
+  double* sCam = sPose + ChunkLds::kPose;
+  double* sPoseC = sCam + ChunkLds::kCam;          // 64 * 12 (candidate poses)
+  double* sDp = sPoseC + ChunkLds::kPose;          // kDpStride
+  double* sLP = sDp + kDpStride;                   // TP * 3 (candidate point / a_l)
+  double* sRed = sLP + 3 * TP;                     // 16
+  int* sFree = reinterpret_cast<int*>(sRed + 16);  // 64
+  int* sFlag = sFree + 64;                         // 4
+  int* sPS = sFlag + 4;                            // TP
+  int* sPL = sPS + TP;                             // TP
+  Real* sPW = reinterpret_cast<Real*>(sPL + TP);   // TP * 18
+  Real* sPV = sPW + TP * 18;                       // TP * 12
+
+  load_window(P, W, poses, sPose, sCam, sFree);
+  if (!ADJ)
+    for (int k = tid; k < W.n_poses * 12; k += TP) sPoseC[k] = cposes[k];
+  for (int k = tid; k < nS; k += TP) sDp[k] = K.dp[kDpStride * wi + k];
+  if (tid == 0) sFlag[0] = 0;
+  __syncthreads();
+
+  double cost = 0.0;
+  const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
+  for (int t = t0; t < t1; ++t) {
+    const int l0 = T.tile_lm_begin[t], l1 = T.tile_lm_begin[t + 1];
+    const int p0 = P.lm_pair_begin[l0], p1 = P.lm_pair_begin[l1];
+    const int nP = p1 - p0, nL = l1 - l0;
+
+    // ---- phase 1: per pair: W, V, g at the current state and W^T dp
+    if (tid < nP) {
+      const int gp = p0 + tid;
+      const int lm = P.pair_lm[gp];
+      const int pose = P.pair_pose[gp];
+      const int slot = sFree[pose];
+      sPS[tid] = slot;
+      sPL[tid] = lm - l0;
+      const double* Rt = sPose + 12 * pose;
+      const double* pt = points + 3 * (lm - W.point_off);
+      double xb[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
+      Real Rp[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
+      PairAcc<Real> A;
+      pair_zero(A);
+      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
+      for (int o = o0; o < o1; ++o) {
+        const double* C = sCam + 16 * P.obs_cam[o];
+        const double wo = K.w ? (double)K.w[o] : 1.0;
+        const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
+                                            S.huber_delta);
+        pair_add<Real, ADJ>(A, L, Rp, slot >= 0, C);
+      }
+      Real wtd[3] = {0, 0, 0};
+      if (slot >= 0) {
+        const double* d = sDp + 6 * slot;
+        for (int c = 0; c < 3; ++c) {
+          double v = 0.0;
+          for (int r = 0; r < 6; ++r) v += (double)A.W[3 * r + c] * d[r];
+          wtd[c] = (Real)v;
+        }
+      }
+      for (int k = 0; k < 6; ++k) sPV[12 * tid + k] = A.V[k];
+      for (int k = 0; k < 3; ++k) sPV[12 * tid + 6 + k] = A.gl[k];
+      for (int k = 0; k < 3; ++k) sPV[12 * tid + 9 + k] = wtd[k];
+    }
+    __syncthreads();
+
+    // ---- phase 2: per landmark: dl = V*^-1 (c_l - sum W^T dp)
+    if (tid < nL) {
+      const int lm = l0 + tid;
+      const int q0 = P.lm_pair_begin[lm] - p0, q1 = P.lm_pair_begin[lm + 1] - p0;
+      Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0}, s3[3] = {0, 0, 0};
+      for (int q = q0; q < q1; ++q) {
+        for (int k = 0; k < 6; ++k) V[k] += sPV[12 * q + k];
+        for (int k = 0; k < 3; ++k) g[k] += sPV[12 * q + 6 + k];
+        for (int k = 0; k < 3; ++k) s3[k] += sPV[12 * q + 9 + k];
+      }
+      Real c[3];
+      if (!ADJ) {
+        damp3(V, lam);
+        for (int k = 0; k < 3; ++k) c[k] = -g[k] - s3[k];
+      } else {
+        for (int k = 0; k < 3; ++k)
+          c[k] = (U.grad_points ? (Real)U.grad_points[3 * lm + k] : (Real)0) - s3[k];
+      }
+      LDL3<Real> F;
+      ldl3(V, !ADJ, F);
+      Real x[3];
+      ldl3_solve(F, c, x);
+      const double* pt = points + 3 * (lm - W.point_off);
+      if (!ADJ) {
+        double* cp = cpoints + 3 * (lm - W.point_off);
+        for (int k = 0; k < 3; ++k) {
+          const double v = pt[k] + (double)x[k];
+          sLP[3 * tid + k] = v;
+          cp[k] = v;
+        }
+      } else {
+        for (int k = 0; k < 3; ++k) sLP[3 * tid + k] = (double)x[k];
+      }
+    }
+    __syncthreads();
+
+    // ---- phase 3: per pair: candidate cost (LM) / per-observation gradients (ADJ)
+    if (tid < nP) {
+      const int gp = p0 + tid;
+      const int pose = P.pair_pose[gp];
+      const int j = sPL[tid];
+      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
+      if (!ADJ) {
+        const double* Rt = sPoseC + 12 * pose;
+        const double* pt = sLP + 3 * j;
+        double xb[3];
+        for (int a = 0; a < 3; ++a)
+          xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
+        for (int o = o0; o < o1; ++o) {
+          const double* C = sCam + 16 * P.obs_cam[o];
+          const double X = C[4] * xb[0] + C[5] * xb[1] + C[6] * xb[2] + C[13];
+          const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
+          const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
+          if (!(Z > S.min_depth)) sFlag[0] = 1;
+          const double r0 = C[0] * X / Z - (double)K.du[o];
+          const double r1 = C[1] * Y / Z - (double)K.dv[o];
+          double rho, d1, d2;
+          huber(r0 * r0 + r1 * r1, S.huber_delta, rho, d1, d2);
+          cost += (K.w ? (double)K.w[o] : 1.0) * rho;
+        }
+      } else {
+        const int lm = P.pair_lm[gp];
+        const int slot = sPS[tid];
+        const double* Rt = sPose + 12 * pose;
+        const double* pt = points + 3 * (lm - W.point_off);
+        double xb[3];
+        for (int a = 0; a < 3; ++a)
+          xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
+        const double* al = sLP + 3 * j;
+        const double zero6[6] = {0, 0, 0, 0, 0, 0};
+        const double* ap = slot >= 0 ? sDp + 6 * slot : zero6;
+        // R_i^T applied on the landmark part: J_l a_l = a . (R_i a_l)
+        double Ral[3];
+        for (int a = 0; a < 3; ++a)
+          Ral[a] = Rt[4 * a] * al[0] + Rt[4 * a + 1] * al[1] + Rt[4 * a + 2] * al[2];
+        // pose part: J_p a_p = a . rho + (x_b x a) . phi = a . (rho + phi x x_b)
+        double pc[3];
+        pc[0] = ap[4] * xb[2] - ap[5] * xb[1];
+        pc[1] = ap[5] * xb[0] - ap[3] * xb[2];
+        pc[2] = ap[3] * xb[1] - ap[4] * xb[0];
+        double v3[3];
+        for (int a = 0; a < 3; ++a) v3[a] = ap[a] + pc[a] + Ral[a];
+        for (int o = o0; o < o1; ++o) {
+          const double* C = sCam + 16 * P.obs_cam[o];
+          const double wo = K.w ? (double)K.w[o] : 1.0;
+          const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
+                                              S.huber_delta);
+          const double ja0 = (double)L.a0[0] * v3[0] + (double)L.a0[1] * v3[1] + (double)L.a0[2] * v3[2];
+          const double ja1 = (double)L.a1[0] * v3[0] + (double)L.a1[1] * v3[1] + (double)L.a1[2] * v3[2];
+          const double r0 = (double)L.r[0], r1 = (double)L.r[1];
+          const double rja = r0 * ja0 + r1 * ja1;
+          const int u = W.obs_off + P.obs_perm[o];
+          U.grad_uv[2 * u] = wo * (L.d1 * ja0 + 2.0 * L.d2 * r0 * rja);
+          U.grad_uv[2 * u + 1] = wo * (L.d1 * ja1 + 2.0 * L.d2 * r1 * rja);
+          if (U.grad_w) U.grad_w[u] = -L.d1 * rja;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!ADJ) {
+    const double tot = block_sum<TP>(cost, sRed);
+    if (tid == 0) {
+      K.part_cost_b[chunk] = tot;
+      K.part_flag_b[chunk] = sFlag[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// accept / finalize
+// ---------------------------------------------------------------------------
+
+template <typename Real>
+__global__ void k_accept(DevPlan P, DevWork<Real> K, DevUser U, DevSettings S, int it) {
+  const int wi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (wi >= P.n_windows) return;
+  const WinDev W = P.win[wi];
+  WinState st = K.state[wi];
+  ba_iter_trace tr;
+  tr.cost = st.cost;
+  tr.lambda = st.lambda;
+  tr.cand_cost = __builtin_nan("");
+  tr.accepted = 0;
+  tr.status = 0;
+  bool accept = false;
+  if (st.fail) {
+    tr.status = 1;
+    st.chol_failures++;
+  } else {
+    int depth = 0;
+    double F = 0.0;
+    for (int c = W.chunk_begin; c < W.chunk_end; ++c) {
+      depth |= K.part_flag_b[c];
+      F += K.part_cost_b[c];
+    }
+    if (depth) {
+      tr.status = 2;
+      st.depth_rejects++;
+    } else {
+      F *= 0.5;
+      tr.cand_cost = F;
+      st.cand_cost = F;
+      accept = F < st.cost;
+    }
+  }
+  if (accept) {
+    st.cost = tr.cand_cost;
+    st.cur ^= 1;
+    st.accepted++;
+    st.lambda = fmax(st.lambda / S.lambda_down, S.lambda_min);
+  } else {
+    st.lambda = fmin(st.lambda * S.lambda_up, S.lambda_max);
+  }
+  tr.accepted = accept ? 1 : 0;
+  st.iters++;
+  st.fail = 0;
+  K.state[wi] = st;
+  if (U.traces) U.traces[(size_t)wi * S.max_iters + it] = tr;
+}
+
+// Copy the final state into the user's arrays where it sits in the workspace
+// buffer, and write the report.  One workgroup per window.
+template <typename Real>
+__global__ void k_finalize(DevPlan P, DevWork<Real> K, DevUser U, int need_cost) {
+  const int wi = blockIdx.x;
+  const WinDev W = P.win[wi];
+  const WinState st = K.state[wi];
+  if (st.cur == 1) {
+    for (int k = threadIdx.x; k < 12 * W.n_poses; k += blockDim.x)
+      U.poses[12 * W.pose_off + k] = K.poses_b[12 * W.pose_off + k];
+    for (int k = threadIdx.x; k < 3 * W.n_points; k += blockDim.x)
+      U.points[3 * W.point_off + k] = K.points_b[3 * W.point_off + k];
+  }
+  if (threadIdx.x == 0) {
+    ba_report r;
+    double c0 = st.init_cost, cf = st.cost;
+    if (need_cost) {   // no attempt ran: the cost comes from the pass-A partials
+      double F = 0.0;
+      for (int c = W.chunk_begin; c < W.chunk_end; ++c) F += K.part_cost_a[c];
+      c0 = cf = 0.5 * F;
+    }
+    r.initial_cost = c0;
+    r.final_cost = cf;
+    r.final_lambda = st.lambda;
+    r.iters = st.iters;
+    r.accepted = st.accepted;
+    r.chol_failures = st.chol_failures;
+    r.depth_rejects = st.depth_rejects;
+    r.status = (need_cost && !isfinite(c0)) ? 1 : st.status;
+    r.reserved = 0;
+    U.reports[wi] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers (instantiated here, called by the ABI layer)
+// ---------------------------------------------------------------------------
+
+template <typename Real, int TP>
+size_t pass_a_lds(int max_nf) {
+  const int nblk = max_nf * (max_nf + 1) / 2;
+  return (ChunkLds::kPose + ChunkLds::kCam + 16) * sizeof(double) +
+         (64 + 16 + TP + 4 + TP + TP + 4) * sizeof(int) +
+         (size_t)(nblk * 36 + 12 * max_nf + TP * (18 + 9 + 12)) * sizeof(Real);
+}
+
+template <typename Real, int TP>
+size_t pass_b_lds() {
+  return (2 * ChunkLds::kPose + ChunkLds::kCam + kDpStride + 3 * TP + 16) * sizeof(double) +
+         (64 + 4 + 2 * TP) * sizeof(int) + (size_t)TP * (18 + 12) * sizeof(Real);
+}
+
+size_t reduce_lds(int max_nf) {
+  const int nblk = max_nf * (max_nf + 1) / 2;
+  return (size_t)(nblk * 36 + 12 * max_nf) * sizeof(double) + 16;
+}
+
+constexpr int kReduceThreads = 256;
+
+template <typename Real, int TP, bool ADJ>
+hipError_t set_attrs() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_a<Real, TP, ADJ>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_b<Real, TP, ADJ>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_reduce<Real, kReduceThreads, ADJ>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+struct LaunchArgs {
+  DevPlan plan;
+  DevTiles tiles;
+  DevUser user;
+  DevSettings settings;
+  int max_nf;
+  hipStream_t stream;
+};
+
+template <typename Real, int TP>
+hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
+  const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
+  const size_t la = pass_a_lds<Real, TP>(A.max_nf), lb = pass_b_lds<Real, TP>(),
+               lr = reduce_lds(A.max_nf);
+  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+                     A.settings);
+  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, A.stream, A.plan, A.tiles, K, A.user);
+  const int iters = A.settings.max_iters;
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL((k_pass_a<Real, TP, false>), dim3(nc), dim3(TP), la, A.stream, A.plan,
+                       A.tiles, K, A.user, A.settings, it);
+    hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr,
+                       A.stream, A.plan, A.tiles, K, A.user, A.settings, it);
+    hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, A.stream, A.plan,
+                       A.tiles, K, A.user, A.settings, it);
+    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+                       A.user, A.settings, it);
+  }
+  if (iters == 0)   // the report still needs the input cost
+    hipLaunchKernelGGL((k_pass_a<Real, TP, false>), dim3(nc), dim3(TP), la, A.stream, A.plan,
+                       A.tiles, K, A.user, A.settings, 0);
+  hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, A.stream, A.plan, K, A.user,
+                     iters == 0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename Real, int TP>
+hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
+  const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
+  const size_t la = pass_a_lds<Real, TP>(A.max_nf), lb = pass_b_lds<Real, TP>(),
+               lr = reduce_lds(A.max_nf);
+  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+                     A.settings);
+  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, A.stream, A.plan, A.tiles, K, A.user);
+  hipLaunchKernelGGL((k_pass_a<Real, TP, true>), dim3(nc), dim3(TP), la, A.stream, A.plan, A.tiles,
+                     K, A.user, A.settings, 0);
+  hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, true>), dim3(nw), dim3(kReduceThreads), lr,
+                     A.stream, A.plan, A.tiles, K, A.user, A.settings, 0);
+  hipLaunchKernelGGL((k_pass_b<Real, TP, true>), dim3(nc), dim3(TP), lb, A.stream, A.plan, A.tiles,
+                     K, A.user, A.settings, 0);
+  return hipGetLastError();
+}
+
+
+// Same sequence as run_solve with HIP events between the launches: the summed
+// device time of each stage (pass_a, reduce, pass_b, accept) in ms, for the
+// roofline figures of the benchmark.  Synchronises on the stream.
+template <typename Real, int TP>
+hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* stage_ms) {
+  const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
+  const size_t la = pass_a_lds<Real, TP>(A.max_nf), lb = pass_b_lds<Real, TP>(),
+               lr = reduce_lds(A.max_nf);
+  const int iters = A.settings.max_iters;
+  const int nev = 4 * iters + 1;
+  hipEvent_t* ev = new hipEvent_t[nev];
+  for (int k = 0; k < nev; ++k) (void)hipEventCreate(&ev[k]);
+  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+                     A.settings);
+  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, A.stream, A.plan, A.tiles, K, A.user);
+  (void)hipEventRecord(ev[0], A.stream);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL((k_pass_a<Real, TP, false>), dim3(nc), dim3(TP), la, A.stream, A.plan,
+                       A.tiles, K, A.user, A.settings, it);
+    (void)hipEventRecord(ev[4 * it + 1], A.stream);
+    hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr,
+                       A.stream, A.plan, A.tiles, K, A.user, A.settings, it);
+    (void)hipEventRecord(ev[4 * it + 2], A.stream);
+    hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, A.stream, A.plan,
+                       A.tiles, K, A.user, A.settings, it);
+    (void)hipEventRecord(ev[4 * it + 3], A.stream);
+    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+                       A.user, A.settings, it);
+    (void)hipEventRecord(ev[4 * it + 4], A.stream);
+  }
+  hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, A.stream, A.plan, K, A.user, 0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventSynchronize(ev[nev - 1]);
+  for (int k = 0; k < 4; ++k) stage_ms[k] = 0.0;
+  for (int it = 0; it < iters && e == hipSuccess; ++it)
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[4 * it + k], ev[4 * it + k + 1]);
+      stage_ms[k] += ms;
+    }
+  for (int k = 0; k < nev; ++k) (void)hipEventDestroy(ev[k]);
+  delete[] ev;
+  return e;
+}
+
+// explicit instantiations used by the ABI layer
+template size_t pass_a_lds<double, 64>(int);
+template size_t pass_a_lds<double, 256>(int);
+template size_t pass_a_lds<float, 64>(int);
+template size_t pass_a_lds<float, 256>(int);
+template size_t pass_b_lds<double, 64>();
+template size_t pass_b_lds<double, 256>();
+template size_t pass_b_lds<float, 64>();
+template size_t pass_b_lds<float, 256>();
+template hipError_t set_attrs<double, 64, false>();
+template hipError_t set_attrs<double, 256, false>();
+template hipError_t set_attrs<float, 64, false>();
+template hipError_t set_attrs<float, 256, false>();
+template hipError_t set_attrs<double, 64, true>();
+template hipError_t set_attrs<double, 256, true>();
+template hipError_t set_attrs<float, 64, true>();
+template hipError_t set_attrs<float, 256, true>();
+template hipError_t run_solve<double, 64>(const LaunchArgs&, const DevWork<double>&);
+template hipError_t run_solve<double, 256>(const LaunchArgs&, const DevWork<double>&);
+template hipError_t run_solve<float, 64>(const LaunchArgs&, const DevWork<float>&);
+template hipError_t run_solve<float, 256>(const LaunchArgs&, const DevWork<float>&);
+template hipError_t run_solve_timed<double, 64>(const LaunchArgs&, const DevWork<double>&, double*);
+template hipError_t run_solve_timed<double, 256>(const LaunchArgs&, const DevWork<double>&, double*);
+template hipError_t run_solve_timed<float, 64>(const LaunchArgs&, const DevWork<float>&, double*);
+template hipError_t run_solve_timed<float, 256>(const LaunchArgs&, const DevWork<float>&, double*);
+template hipError_t run_adjoint<double, 64>(const LaunchArgs&, const DevWork<double>&);
+template hipError_t run_adjoint<double, 256>(const LaunchArgs&, const DevWork<double>&);
+template hipError_t run_adjoint<float, 64>(const LaunchArgs&, const DevWork<float>&);
+template hipError_t run_adjoint<float, 256>(const LaunchArgs&, const DevWork<float>&);
+
+}  // namespace ba

@@ -1,0 +1,226 @@
+// Host-side plan construction (see plan.hpp).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <sstream>
+
+namespace ba {
+
+namespace {
+
+std::string fail(int* code, int c, const std::string& msg) {
+  *code = c;
+  return msg;
+}
+
+bool rotation_ok(const double* R) {
+  // R R^T = I within 1e-6 and det > 0
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0;
+      for (int c = 0; c < 3; ++c) s += R[3 * a + c] * R[3 * b + c];
+      if (std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-6) return false;
+    }
+  const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                     R[2] * (R[3] * R[7] - R[4] * R[6]);
+  return det > 0;
+}
+
+}  // namespace
+
+std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
+                         const int32_t* obs_pose, const int32_t* obs_point,
+                         const int32_t* obs_cam, const uint8_t* pose_fixed,
+                         const double* intrinsics, const double* extrinsics, HostWindow& w,
+                         int* code) {
+  *code = 0;
+  if (n_poses < 1) return fail(code, -1, "n_poses must be >= 1");
+  if (n_points < 0 || n_cams < 1 || n_obs < 0) return fail(code, -1, "negative size");
+  if (n_obs > 0 && (!obs_pose || !obs_point)) return fail(code, -1, "obs_pose/obs_point is NULL");
+  if (!intrinsics) return fail(code, -1, "intrinsics is NULL");
+  if (n_poses > kMaxPoses) return fail(code, -5, "more than 64 poses in a window");
+  if (n_cams > kMaxCams) return fail(code, -5, "more than 32 cameras in a window");
+  if (n_obs > (int64_t)INT32_MAX / 2) return fail(code, -5, "too many observations");
+
+  w.n_poses = n_poses;
+  w.n_points = n_points;
+  w.n_cams = n_cams;
+  w.n_obs = n_obs;
+  w.fixed.assign(n_poses, 0);
+  if (pose_fixed) {
+    for (int i = 0; i < n_poses; ++i) w.fixed[i] = pose_fixed[i] ? 1 : 0;
+  } else {
+    w.fixed[0] = 1;
+  }
+  w.free_slot.assign(n_poses, -1);
+  w.n_free = 0;
+  for (int i = 0; i < n_poses; ++i)
+    if (!w.fixed[i]) w.free_slot[i] = w.n_free++;
+  if (w.n_free > kMaxFree) return fail(code, -5, "more than 32 free poses in a window");
+
+  w.cam.assign((size_t)n_cams * 16, 0.0);
+  for (int k = 0; k < n_cams; ++k) {
+    const double* K = intrinsics + 4 * k;
+    for (int c = 0; c < 4; ++c)
+      if (!std::isfinite(K[c])) return fail(code, -1, "non-finite intrinsics");
+    if (!(K[0] > 0 && K[1] > 0)) return fail(code, -1, "focal lengths must be positive");
+    double* C = w.cam.data() + 16 * k;
+    for (int c = 0; c < 4; ++c) C[c] = K[c];
+    if (extrinsics) {
+      const double* E = extrinsics + 12 * k;
+      for (int c = 0; c < 12; ++c)
+        if (!std::isfinite(E[c])) return fail(code, -1, "non-finite extrinsics");
+      const double R[9] = {E[0], E[1], E[2], E[4], E[5], E[6], E[8], E[9], E[10]};
+      if (!rotation_ok(R)) return fail(code, -1, "extrinsic rotation is not a rotation");
+      for (int c = 0; c < 9; ++c) C[4 + c] = R[c];
+      C[13] = E[3];
+      C[14] = E[7];
+      C[15] = E[11];
+    } else {
+      C[4] = C[8] = C[12] = 1.0;
+    }
+  }
+
+  for (int64_t o = 0; o < n_obs; ++o) {
+    if (obs_pose[o] < 0 || obs_pose[o] >= n_poses) {
+      std::ostringstream s;
+      s << "obs_pose[" << o << "] = " << obs_pose[o] << " out of range";
+      return fail(code, -1, s.str());
+    }
+    if (obs_point[o] < 0 || obs_point[o] >= n_points) {
+      std::ostringstream s;
+      s << "obs_point[" << o << "] = " << obs_point[o] << " out of range";
+      return fail(code, -1, s.str());
+    }
+    if (obs_cam && (obs_cam[o] < 0 || obs_cam[o] >= n_cams)) {
+      std::ostringstream s;
+      s << "obs_cam[" << o << "] = " << obs_cam[o] << " out of range";
+      return fail(code, -1, s.str());
+    }
+  }
+
+  // landmark-major order: (landmark, fixed, free slot or pose, camera, user index)
+  auto cam_of = [&](int64_t o) { return obs_cam ? obs_cam[o] : 0; };
+  auto pose_key = [&](int32_t i) {
+    return w.fixed[i] ? (int32_t)(kMaxPoses + i) : w.free_slot[i];
+  };
+  std::vector<int32_t> order(n_obs);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (obs_point[a] != obs_point[b]) return obs_point[a] < obs_point[b];
+    const int32_t ka = pose_key(obs_pose[a]), kb = pose_key(obs_pose[b]);
+    if (ka != kb) return ka < kb;
+    if (cam_of(a) != cam_of(b)) return cam_of(a) < cam_of(b);
+    return a < b;
+  });
+  w.perm = order;
+  w.obs_cam.resize(n_obs);
+  for (int64_t k = 0; k < n_obs; ++k) w.obs_cam[k] = (uint8_t)cam_of(order[k]);
+
+  // pairs and landmark ranges
+  w.pair_obs_begin.clear();
+  w.pair_lm.clear();
+  w.pair_pose.clear();
+  w.lm_pair_begin.assign((size_t)n_points + 1, 0);
+  w.lm_nfree.assign(n_points, 0);
+  std::vector<int32_t> lm_obs(n_points, 0);
+  std::vector<uint64_t> lm_views(n_points, 0);   // distinct (pose, cam) count, capped
+  for (int64_t k = 0; k < n_obs; ++k) {
+    const int32_t o = order[k];
+    const int32_t j = obs_point[o], i = obs_pose[o];
+    const bool new_pair = (k == 0) || obs_point[order[k - 1]] != j || obs_pose[order[k - 1]] != i;
+    const bool new_view = new_pair || cam_of(order[k - 1]) != cam_of(o);
+    if (new_pair) {
+      w.pair_obs_begin.push_back((int32_t)k);
+      w.pair_lm.push_back(j);
+      w.pair_pose.push_back((uint8_t)i);
+      w.lm_pair_begin[j + 1]++;
+      if (!w.fixed[i]) w.lm_nfree[j]++;
+    }
+    if (new_view) lm_views[j]++;
+    lm_obs[j]++;
+  }
+  w.pair_obs_begin.push_back((int32_t)n_obs);
+  for (int j = 0; j < n_points; ++j) {
+    if (lm_views[j] < 2) {
+      std::ostringstream s;
+      s << "landmark " << j << " has fewer than 2 distinct (pose, camera) views";
+      return fail(code, -1, s.str());
+    }
+    if (lm_obs[j] > kMaxObsPerLandmark) return fail(code, -5, "too many observations of one landmark");
+    w.lm_pair_begin[j + 1] += w.lm_pair_begin[j];
+  }
+  w.schur_blocks = 0;
+  w.n_free_pairs = 0;
+  for (int j = 0; j < n_points; ++j) {
+    const int64_t P = w.lm_nfree[j];
+    w.schur_blocks += P * (P + 1) / 2;
+    w.n_free_pairs += P;
+  }
+  return std::string();
+}
+
+void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_obs,
+                 LaunchTables& t) {
+  t.tp = tp;
+  t.chunk_obs = chunk_obs;
+  t.tile_lm_begin.clear();
+  t.chunk_window.clear();
+  t.chunk_tile_begin.clear();
+  t.win_chunk_begin.clear();
+  t.chunk_part_off.clear();
+  t.part_elems = 0;
+  int32_t lm_base = 0;
+  for (size_t wi = 0; wi < wins.size(); ++wi) {
+    const HostWindow& w = *wins[wi];
+    // tiles: whole landmarks, at most tp pairs and tp landmarks
+    std::vector<int32_t> tiles;      // window-local landmark starts
+    std::vector<int64_t> tile_obs;   // observations per tile
+    int32_t j = 0;
+    while (j < w.n_points) {
+      const int32_t start = j;
+      int32_t pairs = 0;
+      while (j < w.n_points) {
+        const int32_t pj = w.lm_pair_begin[j + 1] - w.lm_pair_begin[j];
+        if (j > start && (pairs + pj > tp || j - start >= tp)) break;
+        pairs += pj;
+        ++j;
+      }
+      tiles.push_back(start);
+      const int32_t p0 = w.lm_pair_begin[start], p1 = w.lm_pair_begin[j];
+      tile_obs.push_back((int64_t)w.pair_obs_begin[p1] - w.pair_obs_begin[p0]);
+    }
+    const int32_t first_tile = (int32_t)t.tile_lm_begin.size();
+    for (int32_t s : tiles) t.tile_lm_begin.push_back(lm_base + s);
+    // chunks: split the window's tiles into about n_obs / chunk_obs runs of
+    // balanced observation counts; a window always has at least one chunk
+    t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
+    const int64_t nt = (int64_t)tiles.size();
+    int64_t want = std::max<int64_t>(1, (w.n_obs + chunk_obs / 2) / std::max(1, chunk_obs));
+    want = std::min<int64_t>(want, std::max<int64_t>(1, nt));
+    int64_t done_obs = 0, k = 0;
+    const int64_t pe = partial_elems(w.n_free);
+    for (int64_t c = 0; c < want; ++c) {
+      t.chunk_window.push_back((int32_t)wi);
+      t.chunk_tile_begin.push_back(first_tile + (int32_t)k);
+      t.chunk_part_off.push_back(t.part_elems);
+      t.part_elems += pe;
+      // advance until this chunk holds its share of the remaining observations
+      const int64_t target = (w.n_obs * (c + 1)) / want;
+      const int64_t left = want - c - 1;          // chunks still to place
+      while (k < nt && (done_obs < target || k == (int64_t)t.chunk_tile_begin.back() - first_tile) &&
+             nt - k > left) {
+        done_obs += tile_obs[k];
+        ++k;
+      }
+    }
+    lm_base += w.n_points;
+  }
+  t.tile_lm_begin.push_back(lm_base);
+  t.chunk_tile_begin.push_back((int32_t)t.tile_lm_begin.size() - 1);
+  t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
+}
+
+}  // namespace ba

@@ -1,0 +1,84 @@
+// Host-side plan of a bundle-adjustment window and of a batch of windows.
+//
+// The plan turns the user's observation index lists (pose i, landmark j,
+// camera k per observation, the observed set of Eq. 3 in Sec. 2.2) into the
+// landmark-major layout the device kernels stream:
+//
+//   observations  sorted by (landmark, pose is fixed, free slot / pose, camera)
+//   pairs         maximal runs of one (landmark, pose): the W_ij blocks
+//   landmarks     contiguous pair ranges, free pairs first
+//   tiles         runs of whole landmarks with at most TP pairs: one pass of a
+//                 workgroup's per-pair / per-landmark phases
+//   chunks        runs of tiles of one window with about `chunk_obs`
+//                 observations: one workgroup of the Schur kernels; each chunk
+//                 owns a private partial of the reduced camera system
+//
+// Plain C++ (no HIP) so that it can be built and sanitised on the host alone.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ba {
+
+constexpr int kMaxPoses = 64;        // poses per window (LDS pose cache)
+constexpr int kMaxCams = 32;         // cameras per window (LDS camera cache)
+constexpr int kMaxFree = 32;         // free poses per window (6 x 32 = 192 = n_S)
+constexpr int kMaxFreeFp64 = 29;     // FP64 partial of S must fit in LDS
+constexpr int kMaxObsPerLandmark = 4096;
+constexpr int kTileSmall = 64;       // pairs per tile, small-LDS configuration
+constexpr int kTileLarge = 256;      // pairs per tile, large configuration
+
+struct HostWindow {
+  int32_t n_poses = 0, n_points = 0, n_cams = 0, n_free = 0;
+  int64_t n_obs = 0;
+  std::vector<uint8_t> fixed;          // per pose
+  std::vector<int32_t> free_slot;      // per pose, -1 when fixed
+  std::vector<double> cam;             // per camera: fx fy cx cy R(9) t(3)
+  // landmark-major plan order
+  std::vector<int32_t> perm;           // plan position -> user observation index
+  std::vector<uint8_t> obs_cam;        // plan order
+  std::vector<int32_t> pair_obs_begin; // n_pairs + 1, window-local plan positions
+  std::vector<int32_t> pair_lm;        // n_pairs, window-local landmark
+  std::vector<uint8_t> pair_pose;      // n_pairs, window-local pose
+  std::vector<int32_t> lm_pair_begin;  // n_points + 1, window-local pair index
+  std::vector<uint8_t> lm_nfree;       // free pairs of each landmark (they come first)
+  int64_t schur_blocks = 0;            // sum of P(P+1)/2 over landmarks
+  int64_t n_free_pairs = 0;            // sum of P over landmarks
+  int64_t n_pairs() const { return (int64_t)pair_pose.size(); }
+};
+
+// Validate and build.  Returns an empty string on success, else the error.
+// code_out: 0 ok, -1 invalid argument, -5 unsupported structure.
+std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
+                         const int32_t* obs_pose, const int32_t* obs_point,
+                         const int32_t* obs_cam, const uint8_t* pose_fixed,
+                         const double* intrinsics, const double* extrinsics, HostWindow& out,
+                         int* code_out);
+
+// Tiles and chunks of a batch for one tile size and chunk target.
+struct LaunchTables {
+  int tp = 0;                            // pairs per tile
+  int chunk_obs = 0;                     // observation target per chunk
+  std::vector<int32_t> tile_lm_begin;    // n_tiles + 1, batch-global landmark
+  std::vector<int32_t> chunk_window;     // n_chunks
+  std::vector<int32_t> chunk_tile_begin; // n_chunks + 1
+  std::vector<int32_t> win_chunk_begin;  // n_windows + 1
+  std::vector<int64_t> chunk_part_off;   // n_chunks, element offset of its S partial
+  int64_t part_elems = 0;                // total partial elements
+  int32_t n_tiles() const { return (int32_t)tile_lm_begin.size() - 1; }
+  int32_t n_chunks() const { return (int32_t)chunk_window.size(); }
+};
+
+// Elements of one chunk's partial: the upper 6x6 blocks of S (36 each), then
+// the reduced right-hand side (6 n_free) and diag(U) (6 n_free).
+inline int64_t partial_elems(int n_free) {
+  const int64_t nblk = (int64_t)n_free * (n_free + 1) / 2;
+  return nblk * 36 + 12 * (int64_t)n_free;
+}
+
+void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_obs,
+                 LaunchTables& out);
+
+}  // namespace ba

@@ -1,0 +1,94 @@
+"""Shared helpers of the GPU tests: run the library through the C ABI and the
+oracle side by side on the same seeded inputs."""
+import math
+
+import numpy as np
+
+import oracle
+
+
+def settings_for(w, precision=None, max_iters=None, **kw):
+    import paper_2506_04359_amd as ba
+    prec = precision if precision is not None else (ba.BA_MIXED if w.mixed else ba.BA_FP64)
+    return ba.Settings(max_iters=w.max_iters if max_iters is None else max_iters, precision=prec,
+                       lambda_init=w.lambda_init, huber_delta=w.huber_delta, **kw)
+
+
+def oracle_settings(s):
+    return oracle.LMSettings(max_iters=s.max_iters, lambda_init=s.lambda_init,
+                             lambda_up=s.lambda_up, lambda_down=s.lambda_down,
+                             lambda_min=s.lambda_min, lambda_max=s.lambda_max,
+                             huber_delta=s.huber_delta, min_depth=s.min_depth)
+
+
+def gpu_solve(w, s, poses=None, points=None, obs_uv=None, obs_w=None, with_trace=True):
+    """Solve one window on cuda:0 through ba_solve; numpy results."""
+    import torch
+    import paper_2506_04359_amd as ba
+    dev = torch.device("cuda:0")
+    W = ba.Window.from_problem(w)
+    P = torch.tensor(w.poses_init if poses is None else poses, dtype=torch.float64, device=dev).contiguous()
+    L = torch.tensor(w.points_init if points is None else points, dtype=torch.float64, device=dev).contiguous()
+    uv = torch.tensor(w.obs_uv if obs_uv is None else obs_uv, dtype=torch.float64, device=dev).contiguous()
+    ww = None if obs_w is None else torch.tensor(obs_w, dtype=torch.float64, device=dev).contiguous()
+    tr = torch.zeros(32 * max(1, s.max_iters), dtype=torch.uint8, device=dev) if with_trace else None
+    rep, tr, _ = ba.solve(W, s, P, L, uv, ww, trace=tr)
+    torch.cuda.synchronize()
+    out = dict(poses=P.cpu().numpy(), points=L.cpu().numpy(), report=ba.parse_reports(rep)[0])
+    out["trace"] = ba.parse_traces(tr, 1, max(1, s.max_iters))[0][: s.max_iters] if with_trace else None
+    return out
+
+
+def gpu_solve_batched(ws, s, chunk_obs=None):
+    import torch
+    import paper_2506_04359_amd as ba
+    dev = torch.device("cuda:0")
+    wins = [ba.Window.from_problem(w, host_only=True) for w in ws]
+    B = ba.Batch(wins)
+    if chunk_obs:
+        B.set_launch(chunk_obs)
+    P = torch.tensor(np.concatenate([w.poses_init for w in ws]), dtype=torch.float64, device=dev)
+    L = torch.tensor(np.concatenate([w.points_init for w in ws]), dtype=torch.float64, device=dev)
+    uv = torch.tensor(np.concatenate([w.obs_uv for w in ws]), dtype=torch.float64, device=dev)
+    tr = torch.zeros(32 * len(ws) * max(1, s.max_iters), dtype=torch.uint8, device=dev)
+    rep, tr, _ = ba.solve_batched(B, s, P, L, uv, None, traces=tr)
+    torch.cuda.synchronize()
+    Pn, Ln = P.cpu().numpy(), L.cpu().numpy()
+    reps = ba.parse_reports(rep)
+    trs = ba.parse_traces(tr, len(ws), max(1, s.max_iters))
+    out = []
+    po = lo = 0
+    for k, w in enumerate(ws):
+        out.append(dict(poses=Pn[po:po + w.n_poses], points=Ln[lo:lo + w.n_points], report=reps[k],
+                        trace=trs[k][: s.max_iters]))
+        po += w.n_poses
+        lo += w.n_points
+    return out
+
+
+def oracle_replay(w, s, gpu_trace, backend="dense", obs_w=None):
+    """The oracle run that follows the GPU's accept/reject sequence."""
+    prob = oracle.Problem.from_window(w, obs_w=obs_w)
+    dec = [bool(a) for a in gpu_trace["accepted"]]
+    return prob, oracle.lm_solve(w.poses_init, w.points_init, prob, oracle_settings(s),
+                                 backend=backend, decisions=dec)
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
+
+
+def check_decisions(ref, gpu_trace, tie=1e-12):
+    """Every accept flag equals the oracle's own decision, or the oracle's own
+    comparison was a near-tie (|F' - F| / F < tie)."""
+    for t, g in zip(ref.trace, gpu_trace):
+        if t["own_decision"] != bool(g["accepted"]):
+            assert math.isfinite(t["cand_cost"]), (t, g)
+            assert abs(t["cand_cost"] - t["cost"]) <= tie * abs(t["cost"]), (t, g)
+
+
+def pose_errors(Pa, Pb):
+    ang, dt = oracle.rotation_errors(Pa, Pb)
+    tn = np.maximum(np.linalg.norm(Pb[:, :, 3], axis=1), 1.0)
+    return float(ang.max()), float((dt / tn).max())
