@@ -23,20 +23,12 @@ namespace ba {
 
 // defined in kernels.hip
 template <typename Real, int TP>
-size_t pass_a_lds(int max_nf);
+size_t pass_a_lds(int np, int nc, int nf, int list_bytes);
 template <typename Real, int TP>
 size_t pass_b_lds();
-size_t reduce_lds(int max_nf);
+size_t reduce_lds(int max_nf, int max_chunks, int* max_off);
 template <typename Real, int TP, bool ADJ>
 hipError_t set_attrs();
-struct LaunchArgs {
-  DevPlan plan;
-  DevTiles tiles;
-  DevUser user;
-  DevSettings settings;
-  int max_nf;
-  hipStream_t stream;
-};
 template <typename Real, int TP>
 hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K);
 template <typename Real, int TP>
@@ -82,6 +74,16 @@ struct DeviceTables {
   int32_t* chunk_window = nullptr;
   int32_t* chunk_tile_begin = nullptr;
   int64_t* chunk_part_off = nullptr;
+  int32_t* chunk_order = nullptr;
+  uint8_t* pair_order = nullptr;
+  uint16_t* prods = nullptr;
+  uint32_t* segs = nullptr;
+  int32_t* tile_prod_begin = nullptr;
+  int32_t* tile_seg_begin = nullptr;
+  int cls_begin[kClasses + 1] = {0, 0, 0, 0, 0};
+  int cls_nf[kClasses] = {0, 0, 0, 0};
+  int list_bytes = 0;   // largest per-tile segment + product list
+  int max_cpw = 0;      // largest chunk count of one window
 };
 
 }  // namespace ba
@@ -90,7 +92,7 @@ using namespace ba;
 
 struct ba_batch_s {
   std::vector<HostWindow> wins;
-  int max_nf = 0;
+  int max_nf = 0, max_np = 0, max_nc = 0;
   int64_t n_poses = 0, n_points = 0, n_cams = 0, n_obs = 0, n_pairs = 0;
   int device = 0;
   void* mem = nullptr;   // plan arrays
@@ -152,6 +154,12 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   const size_t o_cw = blob.add(t.chunk_window);
   const size_t o_ct = blob.add(t.chunk_tile_begin);
   const size_t o_cp = blob.add(t.chunk_part_off);
+  const size_t o_co = blob.add(t.chunk_order);
+  const size_t o_po = blob.add(t.pair_order);
+  const size_t o_pr = blob.add(t.prods);
+  const size_t o_sg = blob.add(t.segs);
+  const size_t o_tpb = blob.add(t.tile_prod_begin);
+  const size_t o_tsb = blob.add(t.tile_seg_begin);
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, blob.size);
   if (e != hipSuccess) return set_error(BA_ERR_OOM, "plan tables: hipMalloc failed");
@@ -175,6 +183,18 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   D.chunk_window = (int32_t*)((char*)mem + o_cw);
   D.chunk_tile_begin = (int32_t*)((char*)mem + o_ct);
   D.chunk_part_off = (int64_t*)((char*)mem + o_cp);
+  D.chunk_order = (int32_t*)((char*)mem + o_co);
+  D.pair_order = (uint8_t*)((char*)mem + o_po);
+  D.prods = (uint16_t*)((char*)mem + o_pr);
+  D.segs = (uint32_t*)((char*)mem + o_sg);
+  D.tile_prod_begin = (int32_t*)((char*)mem + o_tpb);
+  D.tile_seg_begin = (int32_t*)((char*)mem + o_tsb);
+  D.list_bytes = t.max_tile_segs * 4 + t.max_tile_prods * 2 + 16;
+  D.max_cpw = 0;
+  for (size_t i = 0; i + 1 < t.win_chunk_begin.size(); ++i)
+    D.max_cpw = std::max(D.max_cpw, t.win_chunk_begin[i + 1] - t.win_chunk_begin[i]);
+  for (int c = 0; c <= kClasses; ++c) D.cls_begin[c] = t.class_begin[c];
+  for (int c = 0; c < kClasses; ++c) D.cls_nf[c] = t.class_nf[c];
   return BA_OK;
 }
 
@@ -192,6 +212,8 @@ ba_status batch_build(std::vector<HostWindow>&& wins, ba_batch_s** out) {
   int32_t lm_base = 0, pair_base = 0, obs_base = 0;
   for (auto& w : b->wins) {
     b->max_nf = std::max(b->max_nf, w.n_free);
+    b->max_np = std::max(b->max_np, w.n_poses);
+    b->max_nc = std::max(b->max_nc, w.n_cams);
     for (int i = 0; i < w.n_poses; ++i) free_slot.push_back(w.free_slot[i]);
     cam.insert(cam.end(), w.cam.begin(), w.cam.end());
     for (int j = 0; j < w.n_points; ++j) {
@@ -268,17 +290,25 @@ ba_status check_settings(const ba_settings* s) {
 // Tile configuration for a precision: the large tiles when their LDS fits.
 ba_status pick_config(const ba_batch_s* b, int precision, int* which) {
   const int nf = b->max_nf;
-  if (precision == BA_MIXED) {
-    if (pass_a_lds<float, kTileLarge>(nf) <= kLdsLimit) *which = 1;
-    else if (pass_a_lds<float, kTileSmall>(nf) <= kLdsLimit) *which = 0;
-    else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
-  } else {
-    if (nf > kMaxFreeFp64) return set_error(BA_ERR_UNSUPPORTED, "BA_FP64 supports at most 29 free poses per window");
-    if (pass_a_lds<double, kTileLarge>(nf) <= kLdsLimit) *which = 1;
-    else if (pass_a_lds<double, kTileSmall>(nf) <= kLdsLimit) *which = 0;
-    else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
-  }
-  if (reduce_lds(nf) > kLdsLimit) return set_error(BA_ERR_UNSUPPORTED, "reduced system too large for LDS");
+  if (precision == BA_FP64 && nf > kMaxFreeFp64)
+    return set_error(BA_ERR_UNSUPPORTED, "BA_FP64 supports at most 29 free poses per window");
+  auto fits = [&](int w) {
+    const DeviceTables& t = b->tables[w];
+    const size_t la = precision == BA_FP64
+                          ? (t.tp == kTileLarge ? pass_a_lds<double, kTileLarge>(b->max_np, b->max_nc, nf, t.list_bytes)
+                                                : pass_a_lds<double, kTileSmall>(b->max_np, b->max_nc, nf, t.list_bytes))
+                          : (t.tp == kTileLarge ? pass_a_lds<float, kTileLarge>(b->max_np, b->max_nc, nf, t.list_bytes)
+                                                : pass_a_lds<float, kTileSmall>(b->max_np, b->max_nc, nf, t.list_bytes));
+    const size_t lb = precision == BA_FP64
+                          ? (t.tp == kTileLarge ? pass_b_lds<double, kTileLarge>() : pass_b_lds<double, kTileSmall>())
+                          : (t.tp == kTileLarge ? pass_b_lds<float, kTileLarge>() : pass_b_lds<float, kTileSmall>());
+    return la <= kLdsLimit && lb <= kLdsLimit;
+  };
+  if (fits(1)) *which = 1;
+  else if (fits(0)) *which = 0;
+  else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
+  int moff = 0;
+  if (reduce_lds(nf, 1, &moff) > kLdsLimit) return set_error(BA_ERR_UNSUPPORTED, "reduced system too large for LDS");
   return BA_OK;
 }
 
@@ -367,6 +397,12 @@ DevTiles dev_tiles(const DeviceTables& t) {
   d.chunk_window = t.chunk_window;
   d.chunk_tile_begin = t.chunk_tile_begin;
   d.chunk_part_off = t.chunk_part_off;
+  d.chunk_order = t.chunk_order;
+  d.pair_order = t.pair_order;
+  d.prods = t.prods;
+  d.segs = t.segs;
+  d.tile_prod_begin = t.tile_prod_begin;
+  d.tile_seg_begin = t.tile_seg_begin;
   d.n_chunks = t.n_chunks;
   return d;
 }
@@ -392,7 +428,13 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.user = U;
   A.settings = dev_settings(s);
   A.max_nf = b->max_nf;
-  A.stream = (hipStream_t)stream;
+  for (int c = 0; c <= kClasses; ++c) A.cls_begin[c] = t.cls_begin[c];
+  for (int c = 0; c < kClasses; ++c) A.cls_nf[c] = t.cls_nf[c];
+  A.dims.np = b->max_np;
+  A.dims.nc = b->max_nc;
+  A.list_bytes = t.list_bytes;
+  A.max_cpw = t.max_cpw;
+  A.stream = stream;
   hipError_t e;
   if (s->precision == BA_FP64) {
     const DevWork<double> K = make_work<double>(L, ws, has_w);

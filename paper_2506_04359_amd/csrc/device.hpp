@@ -4,6 +4,7 @@
 #include <cstdint>
 
 #include "../../include/ba.h"
+#include "plan.hpp"
 
 namespace ba {
 
@@ -41,6 +42,12 @@ struct DevPlan {
 };
 
 struct DevTiles {
+  const int32_t* chunk_order;     // chunks grouped by size class
+  const uint8_t* pair_order;      // per pair position: tile-local pair of that thread
+  const uint16_t* prods;          // Schur products (qa | qc << 8), per tile
+  const uint32_t* segs;           // product segments by target block, per tile
+  const int32_t* tile_prod_begin; // per tile + 1
+  const int32_t* tile_seg_begin;  // per tile + 1
   const int32_t* tile_lm_begin;
   const int32_t* chunk_window;
   const int32_t* chunk_tile_begin;
@@ -85,5 +92,25 @@ struct DevSettings {
 };
 
 constexpr int kDpStride = 192;
+
+// Dimensions of the window caches in LDS (largest in the launch).
+struct LdsDims {
+  int np, nc;
+};
+
+// Everything one launch sequence needs (built by the ABI layer).
+struct LaunchArgs {
+  DevPlan plan;
+  DevTiles tiles;
+  DevUser user;
+  DevSettings settings;
+  int max_nf;
+  int cls_begin[kClasses + 1];   // chunk_order ranges of the size classes
+  int cls_nf[kClasses];          // largest free-pose count of each class
+  LdsDims dims;                  // largest pose / camera count of the batch
+  int list_bytes;                // largest per-tile product list (segments + products)
+  int max_cpw;                   // largest number of chunks of one window
+  void* stream;                  // hipStream_t
+};
 
 }  // namespace ba

@@ -470,39 +470,77 @@ __global__ void k_pack(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U) {
 // pass A: linearise + per-landmark elimination + chunk partial of S
 // ---------------------------------------------------------------------------
 
+// Suffix sums of v[0..N) over runs of lanes with equal key inside a wave: after
+// the call the first lane of each run holds the run's total.
+template <typename Real, int N>
+__device__ __forceinline__ void run_sums(Real* v, int key) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int k2 = __shfl_down(key, off, 64);
+    const bool ok = (lane + off < 64) && (k2 == key);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const Real u = __shfl_down(v[i], off, 64);
+      if (ok) v[i] += u;
+    }
+  }
+}
+
+// Upper-triangle entry e (0..20) of a 6x6 block -> row-major offset r*6+c.
+__constant__ int kUpperOff[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
+                                  21, 22, 23, 28, 29, 35};
+
+// LDS carve of pass A.  Window caches and the reduced-system partial are sized
+// by the launch's largest window; the per-tile buffers by TP.
+template <typename Real, int TP>
+struct PassALds {
+  static constexpr int NW = TP / 64;
+  static size_t bytes(int np, int nc, int nf, int list_bytes) {
+    const size_t nblk = (size_t)nf * (nf + 1) / 2;
+    const size_t region = std::max<size_t>((size_t)TP * 9 * sizeof(Real), (size_t)list_bytes);
+    return (size_t)(np * 12 + nc * 16 + 16) * sizeof(double) + (64 + TP + 4) * sizeof(int) +
+           (nblk * kBS + 12 * (size_t)nf + (size_t)NW * nf * 27 + (size_t)TP * (18 + 12)) * sizeof(Real) +
+           (region + 15) / 16 * 16;
+  }
+};
+
 template <typename Real, int TP, bool ADJ>
 __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Real> K,
-                                               DevUser U, DevSettings S, int it) {
+                                               DevUser U, DevSettings S, int it, int cls_begin,
+                                               LdsDims D) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  constexpr int NW = TP / 64;
+  const int chunk = T.chunk_order[cls_begin + xcd_chunk(blockIdx.x, gridDim.x)];
   const int wi = T.chunk_window[chunk];
   const WinDev W = P.win[wi];
   const WinState& st = K.state[wi];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cur = ADJ ? 0 : st.cur;
   const double lam = ADJ ? 0.0 : st.lambda;
   const double* poses = (cur ? K.poses_b : U.poses) + 12 * W.pose_off;
   const double* points = (cur ? K.points_b : U.points) + 3 * W.point_off;
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
 
-  double* sPose = reinterpret_cast<double*>(smem);
-  double* sCam = sPose + ChunkLds::kPose;
-  double* sRed = sCam + ChunkLds::kCam;                       // 16 doubles
+  double* sPose = reinterpret_cast<double*>(smem);            // np * 12
+  double* sCam = sPose + D.np * 12;                           // nc * 16
+  double* sRed = sCam + D.nc * 16;                            // 16
   int* sFree = reinterpret_cast<int*>(sRed + 16);             // 64
-  int* sScan = sFree + 64;                                    // 16
-  int* sLW = sScan + 16;                                      // TP + 1
-  int* sPS = sLW + TP + 4;                                    // TP: pair slot
-  int* sPL = sPS + TP;                                        // TP: pair landmark (tile-local)
+  int* sPL = sFree + 64;                                      // TP: pair -> tile-local landmark
   int* sFlag = sPL + TP;                                      // 4
-  Real* sS = reinterpret_cast<Real*>(sFlag + 4);              // nblk * 36
-  Real* sB = sS + nblk * 36;                                  // nS
+  Real* sS = reinterpret_cast<Real*>(sFlag + 4);              // nblk * kBS
+  Real* sB = sS + nblk * kBS;                                 // nS
   Real* sD = sB + nS;                                         // nS
-  Real* sPZ = sD + nS;                                        // TP * 18
-  Real* sPV = sPZ + TP * 18;                                  // TP * 9
-  Real* sLF = sPV + TP * 9;                                   // TP * 12
+  Real* sUw = sD + nS;                                        // NW * nf * 27
+  Real* sPZ = sUw + NW * nf * 27;                             // TP * 18
+  Real* sLF = sPZ + TP * 18;                                  // TP * 12
+  unsigned char* sReg = reinterpret_cast<unsigned char*>(
+      (reinterpret_cast<uintptr_t>(sLF + TP * 12) + 15) & ~uintptr_t(15));
+  Real* sPV = reinterpret_cast<Real*>(sReg);                  // TP * 9 (phases 1-2)
+  uint32_t* sSeg = reinterpret_cast<uint32_t*>(sReg);         // segments (phase 4)
 
   load_window(P, W, poses, sPose, sCam, sFree);
-  for (int k = tid; k < nblk * 36 + 2 * nS; k += TP) sS[k] = (Real)0;
+  for (int k = tid; k < nblk * kBS + 2 * nS + NW * nf * 27; k += TP) sS[k] = (Real)0;
   if (tid == 0) sFlag[0] = 0;
   __syncthreads();
 
@@ -513,17 +551,21 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     const int p0 = P.lm_pair_begin[l0], p1 = P.lm_pair_begin[l1];
     const int nP = p1 - p0, nL = l1 - l0;
 
-    // ---- phase 1: one thread per pair
+    // ---- phase 1: thread t linearises pair order[t] (free pairs sorted by slot)
+    int q = -1, slot = -1;
+    PairAcc<Real> A;
+    pair_zero(A);
     if (tid < nP) {
-      const int gp = p0 + tid;
+      q = T.pair_order[p0 + tid];
+      const int gp = p0 + q;
       const int lm = P.pair_lm[gp];                   // batch-global landmark
       const int pose = P.pair_pose[gp];
-      const int slot = sFree[pose];
-      sPS[tid] = slot;
-      sPL[tid] = lm - l0;
+      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
+      slot = sFree[pose];
+      sPL[q] = lm - l0;
       const double* Rt = sPose + 12 * pose;
-      const double px = points[3 * (lm - W.point_off)], py = points[3 * (lm - W.point_off) + 1],
-                   pz = points[3 * (lm - W.point_off) + 2];
+      const double* pt = points + 3 * (lm - W.point_off);
+      const double px = pt[0], py = pt[1], pz = pt[2];
       double xb[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -533,9 +575,6 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
-      PairAcc<Real> A;
-      pair_zero(A);
-      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
       for (int o = o0; o < o1; ++o) {
         const double* C = sCam + 16 * P.obs_cam[o];
         const double wo = K.w ? (double)K.w[o] : 1.0;
@@ -544,22 +583,10 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
         cost += L.rho_w;
         pair_add<Real, ADJ>(A, L, Rp, slot >= 0, C);
       }
-      if (slot >= 0) {
-        Real* Sd = sS + 36 * blk_index(slot, slot, nf);
-        int u = 0;
-        for (int r = 0; r < 6; ++r)
-          for (int c = r; c < 6; ++c) atomicAdd(Sd + 6 * r + c, A.U[u++]);
-        if (!ADJ) {
-          const int dI[6] = {0, 6, 11, 15, 18, 20};
-          for (int r = 0; r < 6; ++r) {
-            atomicAdd(sB + 6 * slot + r, -A.gp[r]);
-            atomicAdd(sD + 6 * slot + r, A.U[dI[r]]);
-          }
-        }
-        for (int k = 0; k < 18; ++k) sPZ[18 * tid + k] = A.W[k];
-      }
-      for (int k = 0; k < 6; ++k) sPV[9 * tid + k] = A.V[k];
-      for (int k = 0; k < 3; ++k) sPV[9 * tid + 6 + k] = A.gl[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sPV[9 * q + k] = A.V[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sPV[9 * q + 6 + k] = A.gl[k];
     }
     __syncthreads();
 
@@ -568,9 +595,11 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       const int lm = l0 + tid;
       const int q0 = P.lm_pair_begin[lm] - p0, q1 = P.lm_pair_begin[lm + 1] - p0;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
-      for (int q = q0; q < q1; ++q) {
-        for (int k = 0; k < 6; ++k) V[k] += sPV[9 * q + k];
-        for (int k = 0; k < 3; ++k) g[k] += sPV[9 * q + 6 + k];
+      for (int qq = q0; qq < q1; ++qq) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) V[k] += sPV[9 * qq + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] += sPV[9 * qq + 6 + k];
       }
       Real c[3];
       if (!ADJ) {
@@ -579,8 +608,8 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
         c[1] = -g[1];
         c[2] = -g[2];
       } else {
-        const int ul = lm;   // batch-global landmark = packed user index
-        for (int k = 0; k < 3; ++k) c[k] = U.grad_points ? (Real)U.grad_points[3 * ul + k] : (Real)0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c[k] = U.grad_points ? (Real)U.grad_points[3 * lm + k] : (Real)0;
       }
       LDL3<Real> F;
       if (!ldl3(V, !ADJ, F)) sFlag[0] = 1;
@@ -590,82 +619,114 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       f[0] = F.l10;
       f[1] = F.l20;
       f[2] = F.l21;
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
         f[3 + k] = F.isd[k];
         f[6 + k] = F.sg[k];
         f[9 + k] = hb[k];
       }
-      const int nfp = P.lm_nfree[lm];
-      sLW[tid] = nfp * (nfp + 1) / 2;
     }
     __syncthreads();
-    block_scan<TP>(sLW, nL, sScan);
+    // the V region now holds this tile's Schur product segments and products
+    const int sb0 = T.tile_seg_begin[t], nseg = T.tile_seg_begin[t + 1] - sb0;
+    const int pb0 = T.tile_prod_begin[t], nprod = T.tile_prod_begin[t + 1] - pb0;
+    uint16_t* sProd = reinterpret_cast<uint16_t*>(sSeg + nseg);
+    for (int k = tid; k < nseg; k += TP) sSeg[k] = T.segs[sb0 + k];
+    for (int k = tid; k < nprod; k += TP) sProd[k] = T.prods[pb0 + k];
 
-    // ---- phase 3: one thread per free pair: Z_bar = W L^-T |D|^-1/2, rhs
-    if (tid < nP && sPS[tid] >= 0) {
-      const int slot = sPS[tid];
-      const Real* f = sLF + 12 * sPL[tid];
+    // ---- phase 3: Z_bar = W L^-T |D|^-1/2 and the reduced rhs of this pair;
+    // then per-pose sums over adjacent lanes, added once per run
+    Real v[27];
+    if (slot >= 0) {
+      const Real* f = sLF + 12 * sPL[q];
       LDL3<Real> F;
       F.l10 = f[0];
       F.l20 = f[1];
       F.l21 = f[2];
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
         F.isd[k] = f[3 + k];
         F.sg[k] = f[6 + k];
       }
-      Real* Z = sPZ + 18 * tid;
       Real sh[3];
+#pragma unroll
       for (int k = 0; k < 3; ++k) sh[k] = f[6 + k] * f[9 + k];
+      Real* Z = sPZ + 18 * q;
+#pragma unroll
       for (int r = 0; r < 6; ++r) {
         Real z[3];
-        ldl3_half(F, Z + 3 * r, z);
+        ldl3_half(F, A.W + 3 * r, z);
         Z[3 * r] = z[0];
         Z[3 * r + 1] = z[1];
         Z[3 * r + 2] = z[2];
-        atomicAdd(sB + 6 * slot + r, -(z[0] * sh[0] + z[1] * sh[1] + z[2] * sh[2]));
+        v[21 + r] = (ADJ ? (Real)0 : -A.gp[r]) - (z[0] * sh[0] + z[1] * sh[1] + z[2] * sh[2]);
+      }
+#pragma unroll
+      for (int k = 0; k < 21; ++k) v[k] = A.U[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 27; ++k) v[k] = (Real)0;
+    }
+    run_sums<Real, 27>(v, slot);
+    {
+      const int prev = __shfl_up(slot, 1, 64);
+      if (slot >= 0 && (lane == 0 || prev != slot)) {
+        Real* dst = sUw + (wave * nf + slot) * 27;
+#pragma unroll
+        for (int k = 0; k < 27; ++k) dst[k] += v[k];
       }
     }
     __syncthreads();
 
-    // ---- phase 4: flat loop over the upper pose-pair blocks of every landmark
-    const int total = sLW[nL];
-    for (int fidx = tid; fidx < total; fidx += TP) {
-      // landmark: last j with sLW[j] <= fidx
-      int lo = 0, hi = nL;   // invariant sLW[lo] <= fidx < sLW[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (sLW[mid] <= fidx) lo = mid;
-        else hi = mid;
+    // ---- phase 4: Schur blocks.  Unit (segment, row r) owns row r of one
+    // target block for this tile: it sums -Z_a[r] sigma Z_b^T over the
+    // segment's products in registers and updates the partial once.
+    for (int u = tid; u < nseg * 6; u += TP) {
+      const uint32_t word = sSeg[u / 6];
+      const int r = u % 6;
+      const int blk = word & 1023, start = (word >> 10) & 8191, len = word >> 23;
+      Real acc[6] = {0, 0, 0, 0, 0, 0};
+      for (int k = start; k < start + len; ++k) {
+        const uint32_t pr = sProd[k];
+        const int qa = pr & 255, qc = pr >> 8;
+        const Real* Za = sPZ + 18 * qa + 3 * r;
+        Real z0 = Za[0], z1 = Za[1], z2 = Za[2];
+        if (ADJ) {
+          const Real* sg = sLF + 12 * sPL[qa] + 6;
+          z0 *= sg[0];
+          z1 *= sg[1];
+          z2 *= sg[2];
+        }
+        const Real* Zc = sPZ + 18 * qc;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += z0 * Zc[3 * c] + z1 * Zc[3 * c + 1] + z2 * Zc[3 * c + 2];
       }
-      const int j = lo;
-      int k = fidx - sLW[j];
-      const int lm = l0 + j;
-      const int nfp = P.lm_nfree[lm];
-      int a = 0;
-      while (k >= nfp - a) {
-        k -= nfp - a;
-        ++a;
-      }
-      const int b = a + k;
-      const int qb = P.lm_pair_begin[lm] - p0;
-      const int qa = qb + a, qc = qb + b;
-      const int sa = sPS[qa], sc = sPS[qc];
-      const Real* Za = sPZ + 18 * qa;
-      const Real* Zc = sPZ + 18 * qc;
-      const Real* sg = sLF + 12 * j + 6;
-      Real* Sb = sS + 36 * blk_index(sa, sc, nf);
-      for (int r = 0; r < 6; ++r) {
-        const Real z0 = Za[3 * r] * sg[0], z1 = Za[3 * r + 1] * sg[1], z2 = Za[3 * r + 2] * sg[2];
-        for (int c = (a == b ? r : 0); c < 6; ++c)
-          atomicAdd(Sb + 6 * r + c, -(z0 * Zc[3 * c] + z1 * Zc[3 * c + 1] + z2 * Zc[3 * c + 2]));
-      }
+      Real* row = sS + kBS * blk + 6 * r;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) row[c] -= acc[c];
     }
     __syncthreads();
   }
 
+  // ---- fold the per-wave pose sums into the partial: U (upper), rhs, diag(U)
+  for (int e = tid; e < nf * 27; e += TP) {
+    const int s = e / 27, k = e % 27;
+    Real sum = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += sUw[(w * nf + s) * 27 + k];
+    if (k < 21) {
+      const int off = kUpperOff[k];
+      sS[kBS * blk_index(s, s, nf) + off] += sum;
+      if (!ADJ && off % 7 == 0) sD[6 * s + off / 7] += sum;
+    } else {
+      sB[6 * s + (k - 21)] += sum;
+    }
+  }
+  __syncthreads();
+
   // ---- chunk partial out
   Real* part = K.part + T.chunk_part_off[chunk];
-  for (int k = tid; k < nblk * 36 + 2 * nS; k += TP) part[k] = sS[k];
+  for (int k = tid; k < nblk * kBS + 2 * nS; k += TP) part[k] = sS[k];
   const double tot = block_sum<TP>(cost, sRed);
   if (tid == 0) {
     K.part_cost_a[chunk] = tot;
@@ -712,22 +773,44 @@ __device__ __forceinline__ void exp_se3(const double* xi, double* T /*3x4*/) {
   }
 }
 
+// Upper Cholesky R^T R = A of a 6x6 block held in registers; false on a
+// non-positive or non-finite pivot.
+__device__ __forceinline__ bool chol6(double* A) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    double d = A[7 * a];
+#pragma unroll
+    for (int m = 0; m < a; ++m) d -= A[6 * m + a] * A[6 * m + a];
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    const double ra = sqrt(d);
+    A[7 * a] = ra;
+    const double ir = 1.0 / ra;
+#pragma unroll
+    for (int c = a + 1; c < 6; ++c) {
+      double v = A[6 * a + c];
+#pragma unroll
+      for (int m = 0; m < a; ++m) v -= A[6 * m + a] * A[6 * m + c];
+      A[6 * a + c] = v * ir;
+    }
+  }
+  return true;
+}
+
 template <typename Real, int NT, bool ADJ>
 __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U,
-                                               DevSettings S, int it) {
+                                               DevSettings S, int it, int max_off) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wi = blockIdx.x;
   const WinDev W = P.win[wi];
   WinState& st = K.state[wi];
   const int tid = threadIdx.x;
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
-  double* sS = reinterpret_cast<double*>(smem);   // nblk * 36
-  double* sB = sS + nblk * 36;                    // nS
+  double* sS = reinterpret_cast<double*>(smem);   // nblk * kBS
+  double* sB = sS + nblk * kBS;                   // nS
   double* sD = sB + nS;                           // nS
   int* sFail = reinterpret_cast<int*>(sD + nS);   // 1
   const int c0 = W.chunk_begin, c1 = W.chunk_end;
-  const int ne = nblk * 36 + 2 * nS;
-
+  const int ne = nblk * kBS + 2 * nS;
   if (tid == 0) {
     int f = 0;
     for (int c = c0; c < c1; ++c) f |= K.part_flag_a[c];
@@ -741,9 +824,22 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
       if (!isfinite(F)) st.status = 1;
     }
   }
+  // the window's chunk offsets, staged in LDS after the reduced system
+  int64_t* sOff = reinterpret_cast<int64_t*>(sD + nS + 2);
+  const int ncw = c1 - c0;
+  const bool off_in_lds = ncw <= max_off;
+  if (off_in_lds)
+    for (int c = tid; c < ncw; c += NT) sOff[c] = T.chunk_part_off[c0 + c];
+  __syncthreads();
+  // sum of the chunk partials in chunk order (independent loads, unrolled)
   for (int e = tid; e < ne; e += NT) {
     double acc = 0.0;
-    for (int c = c0; c < c1; ++c) acc += (double)K.part[T.chunk_part_off[c] + e];
+    if (off_in_lds) {
+#pragma unroll 4
+      for (int c = 0; c < ncw; ++c) acc += (double)K.part[sOff[c] + e];
+    } else {
+      for (int c = c0; c < c1; ++c) acc += (double)K.part[T.chunk_part_off[c] + e];
+    }
     sS[e] = acc;
   }
   __syncthreads();
@@ -772,7 +868,7 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     for (int e = tid; e < nS; e += NT) {
       const int f = e / 6, r = e % 6;
       const double d = sD[e];
-      sS[36 * blk_index(f, f, nf) + 7 * r] += lam * (d > 1e-9 ? d : 1e-9);
+      sS[kBS * blk_index(f, f, nf) + 7 * r] += lam * (d > 1e-9 ? d : 1e-9);
     }
   }
   __syncthreads();
@@ -780,7 +876,7 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   for (int e = tid; e < nf * 36; e += NT) {
     const int f = e / 36, r = (e % 36) / 6, c = e % 6;
     if (c < r) {
-      double* D = sS + 36 * blk_index(f, f, nf);
+      double* D = sS + kBS * blk_index(f, f, nf);
       D[6 * r + c] = D[6 * c + r];
     }
   }
@@ -789,24 +885,14 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   // blocked Cholesky S = R^T R on 6x6 blocks (upper block storage)
   bool failed = sFail[0] != 0;
   for (int k = 0; k < nf && !failed; ++k) {
-    double* Dk = sS + 36 * blk_index(k, k, nf);
+    double* Dk = sS + kBS * blk_index(k, k, nf);
     if (tid == 0) {
-      int ok = 1;
-      for (int a = 0; a < 6; ++a) {
-        double d = Dk[7 * a];
-        for (int m = 0; m < a; ++m) d -= Dk[6 * m + a] * Dk[6 * m + a];
-        if (!(d > 0.0) || !isfinite(d)) {
-          ok = 0;
-          break;
-        }
-        const double ra = sqrt(d);
-        Dk[7 * a] = ra;
-        for (int c = a + 1; c < 6; ++c) {
-          double v = Dk[6 * a + c];
-          for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * Dk[6 * m + c];
-          Dk[6 * a + c] = v / ra;
-        }
-      }
+      double A[36];
+#pragma unroll
+      for (int e = 0; e < 36; ++e) A[e] = Dk[e];
+      const bool ok = chol6(A);
+#pragma unroll
+      for (int e = 0; e < 36; ++e) Dk[e] = A[e];
       if (!ok) sFail[0] = 1;
     }
     __syncthreads();
@@ -816,13 +902,18 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     const int npan = (nf - k - 1) * 6;
     for (int e = tid; e < npan; e += NT) {
       const int j = k + 1 + e / 6, col = e % 6;
-      double* B = sS + 36 * blk_index(k, j, nf);
-      double y[6];
+      double* B = sS + kBS * blk_index(k, j, nf);
+      double x[6], y[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) x[a] = B[6 * a + col];
+#pragma unroll
       for (int a = 0; a < 6; ++a) {
-        double v = B[6 * a + col];
+        double v = x[a];
+#pragma unroll
         for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * y[m];
         y[a] = v / Dk[7 * a];
       }
+#pragma unroll
       for (int a = 0; a < 6; ++a) B[6 * a + col] = y[a];
     }
     __syncthreads();
@@ -838,31 +929,41 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
         ++i;
       }
       const int j = i + bidx;
-      const double* Rki = sS + 36 * blk_index(k, k + 1 + i, nf);
-      const double* Rkj = sS + 36 * blk_index(k, k + 1 + j, nf);
+      const double* Rki = sS + kBS * blk_index(k, k + 1 + i, nf);
+      const double* Rkj = sS + kBS * blk_index(k, k + 1 + j, nf);
       double v = 0.0;
+#pragma unroll
       for (int m = 0; m < 6; ++m) v += Rki[6 * m + r] * Rkj[6 * m + c];
-      sS[36 * blk_index(k + 1 + i, k + 1 + j, nf) + rc] -= v;
+      sS[kBS * blk_index(k + 1 + i, k + 1 + j, nf) + rc] -= v;
     }
     __syncthreads();
   }
   if (!failed) {
     // forward: R^T y = b
     for (int k = 0; k < nf; ++k) {
-      const double* Dk = sS + 36 * blk_index(k, k, nf);
+      const double* Dk = sS + kBS * blk_index(k, k, nf);
       if (tid == 0) {
-        double* b = sB + 6 * k;
+        double R[36], b[6];
+#pragma unroll
+        for (int e = 0; e < 36; ++e) R[e] = Dk[e];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) b[a] = sB[6 * k + a];
+#pragma unroll
         for (int a = 0; a < 6; ++a) {
           double v = b[a];
-          for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * b[m];
-          b[a] = v / Dk[7 * a];
+#pragma unroll
+          for (int m = 0; m < a; ++m) v -= R[6 * m + a] * b[m];
+          b[a] = v / R[7 * a];
         }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) sB[6 * k + a] = b[a];
       }
       __syncthreads();
       for (int e = tid; e < (nf - k - 1) * 6; e += NT) {
         const int j = k + 1 + e / 6, c = e % 6;
-        const double* B = sS + 36 * blk_index(k, j, nf);
+        const double* B = sS + kBS * blk_index(k, j, nf);
         double v = 0.0;
+#pragma unroll
         for (int m = 0; m < 6; ++m) v += B[6 * m + c] * sB[6 * k + m];
         sB[6 * j + c] -= v;
       }
@@ -870,20 +971,29 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     }
     // backward: R x = y
     for (int k = nf - 1; k >= 0; --k) {
-      const double* Dk = sS + 36 * blk_index(k, k, nf);
+      const double* Dk = sS + kBS * blk_index(k, k, nf);
       if (tid == 0) {
-        double* b = sB + 6 * k;
+        double R[36], b[6];
+#pragma unroll
+        for (int e = 0; e < 36; ++e) R[e] = Dk[e];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) b[a] = sB[6 * k + a];
+#pragma unroll
         for (int a = 5; a >= 0; --a) {
           double v = b[a];
-          for (int m = a + 1; m < 6; ++m) v -= Dk[6 * a + m] * b[m];
-          b[a] = v / Dk[7 * a];
+#pragma unroll
+          for (int m = a + 1; m < 6; ++m) v -= R[6 * a + m] * b[m];
+          b[a] = v / R[7 * a];
         }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) sB[6 * k + a] = b[a];
       }
       __syncthreads();
       for (int e = tid; e < k * 6; e += NT) {
         const int i = e / 6, r = e % 6;
-        const double* B = sS + 36 * blk_index(i, k, nf);
+        const double* B = sS + kBS * blk_index(i, k, nf);
         double v = 0.0;
+#pragma unroll
         for (int m = 0; m < 6; ++m) v += B[6 * r + m] * sB[6 * k + m];
         sB[6 * i + r] -= v;
       }
@@ -1217,11 +1327,8 @@ __global__ void k_finalize(DevPlan P, DevWork<Real> K, DevUser U, int need_cost)
 // ---------------------------------------------------------------------------
 
 template <typename Real, int TP>
-size_t pass_a_lds(int max_nf) {
-  const int nblk = max_nf * (max_nf + 1) / 2;
-  return (ChunkLds::kPose + ChunkLds::kCam + 16) * sizeof(double) +
-         (64 + 16 + TP + 4 + TP + TP + 4) * sizeof(int) +
-         (size_t)(nblk * 36 + 12 * max_nf + TP * (18 + 9 + 12)) * sizeof(Real);
+size_t pass_a_lds(int np, int nc, int nf, int list_bytes) {
+  return PassALds<Real, TP>::bytes(np, nc, nf, list_bytes);
 }
 
 template <typename Real, int TP>
@@ -1230,9 +1337,14 @@ size_t pass_b_lds() {
          (64 + 4 + 2 * TP) * sizeof(int) + (size_t)TP * (18 + 12) * sizeof(Real);
 }
 
-size_t reduce_lds(int max_nf) {
+// The reduce kernel's LDS: the reduced system, then room for the chunk
+// offsets of a window (as many as fit in the 160 KiB, at most max_chunks).
+size_t reduce_lds(int max_nf, int max_chunks, int* max_off) {
   const int nblk = max_nf * (max_nf + 1) / 2;
-  return (size_t)(nblk * 36 + 12 * max_nf) * sizeof(double) + 16;
+  const size_t base = (size_t)(nblk * kBS + 12 * max_nf + 2) * sizeof(double);
+  const size_t room = base < 160 * 1024 ? (160 * 1024 - base) / sizeof(int64_t) : 0;
+  *max_off = (int)std::min<size_t>(room, (size_t)std::max(max_chunks, 1));
+  return base + (size_t)(*max_off) * sizeof(int64_t);
 }
 
 constexpr int kReduceThreads = 256;
@@ -1249,38 +1361,39 @@ hipError_t set_attrs() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-struct LaunchArgs {
-  DevPlan plan;
-  DevTiles tiles;
-  DevUser user;
-  DevSettings settings;
-  int max_nf;
-  hipStream_t stream;
-};
+// Pass A once per size class, each with the LDS its largest window needs.
+template <typename Real, int TP, bool ADJ>
+void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
+  for (int c = 0; c < kClasses; ++c) {
+    const int n = A.cls_begin[c + 1] - A.cls_begin[c];
+    if (n <= 0) continue;
+    const size_t lds = pass_a_lds<Real, TP>(A.dims.np, A.dims.nc, A.cls_nf[c], A.list_bytes);
+    hipLaunchKernelGGL((k_pass_a<Real, TP, ADJ>), dim3(n), dim3(TP), lds, (hipStream_t)A.stream,
+                       A.plan, A.tiles, K, A.user, A.settings, it, A.cls_begin[c], A.dims);
+  }
+}
 
 template <typename Real, int TP>
 hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
-  const size_t la = pass_a_lds<Real, TP>(A.max_nf), lb = pass_b_lds<Real, TP>(),
-               lr = reduce_lds(A.max_nf);
-  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+  int moff = 0;
+  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf, A.max_cpw, &moff);
+  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                      A.settings);
-  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, A.stream, A.plan, A.tiles, K, A.user);
+  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, (hipStream_t)A.stream, A.plan, A.tiles, K, A.user);
   const int iters = A.settings.max_iters;
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((k_pass_a<Real, TP, false>), dim3(nc), dim3(TP), la, A.stream, A.plan,
-                       A.tiles, K, A.user, A.settings, it);
+    launch_pass_a<Real, TP, false>(A, K, it);
     hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr,
-                       A.stream, A.plan, A.tiles, K, A.user, A.settings, it);
-    hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, A.stream, A.plan,
+                       (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, it, moff);
+    hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, (hipStream_t)A.stream, A.plan,
                        A.tiles, K, A.user, A.settings, it);
-    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                        A.user, A.settings, it);
   }
   if (iters == 0)   // the report still needs the input cost
-    hipLaunchKernelGGL((k_pass_a<Real, TP, false>), dim3(nc), dim3(TP), la, A.stream, A.plan,
-                       A.tiles, K, A.user, A.settings, 0);
-  hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, A.stream, A.plan, K, A.user,
+    launch_pass_a<Real, TP, false>(A, K, 0);
+  hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, (hipStream_t)A.stream, A.plan, K, A.user,
                      iters == 0 ? 1 : 0);
   return hipGetLastError();
 }
@@ -1288,20 +1401,18 @@ hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
 template <typename Real, int TP>
 hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
-  const size_t la = pass_a_lds<Real, TP>(A.max_nf), lb = pass_b_lds<Real, TP>(),
-               lr = reduce_lds(A.max_nf);
-  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+  int moff = 0;
+  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf, A.max_cpw, &moff);
+  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                      A.settings);
-  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, A.stream, A.plan, A.tiles, K, A.user);
-  hipLaunchKernelGGL((k_pass_a<Real, TP, true>), dim3(nc), dim3(TP), la, A.stream, A.plan, A.tiles,
-                     K, A.user, A.settings, 0);
+  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, (hipStream_t)A.stream, A.plan, A.tiles, K, A.user);
+  launch_pass_a<Real, TP, true>(A, K, 0);
   hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, true>), dim3(nw), dim3(kReduceThreads), lr,
-                     A.stream, A.plan, A.tiles, K, A.user, A.settings, 0);
-  hipLaunchKernelGGL((k_pass_b<Real, TP, true>), dim3(nc), dim3(TP), lb, A.stream, A.plan, A.tiles,
+                     (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, 0, moff);
+  hipLaunchKernelGGL((k_pass_b<Real, TP, true>), dim3(nc), dim3(TP), lb, (hipStream_t)A.stream, A.plan, A.tiles,
                      K, A.user, A.settings, 0);
   return hipGetLastError();
 }
-
 
 // Same sequence as run_solve with HIP events between the launches: the summed
 // device time of each stage (pass_a, reduce, pass_b, accept) in ms, for the
@@ -1309,31 +1420,30 @@ hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
 template <typename Real, int TP>
 hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* stage_ms) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
-  const size_t la = pass_a_lds<Real, TP>(A.max_nf), lb = pass_b_lds<Real, TP>(),
-               lr = reduce_lds(A.max_nf);
+  int moff = 0;
+  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf, A.max_cpw, &moff);
   const int iters = A.settings.max_iters;
   const int nev = 4 * iters + 1;
   hipEvent_t* ev = new hipEvent_t[nev];
   for (int k = 0; k < nev; ++k) (void)hipEventCreate(&ev[k]);
-  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+  hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                      A.settings);
-  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, A.stream, A.plan, A.tiles, K, A.user);
-  (void)hipEventRecord(ev[0], A.stream);
+  hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, (hipStream_t)A.stream, A.plan, A.tiles, K, A.user);
+  (void)hipEventRecord(ev[0], (hipStream_t)A.stream);
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((k_pass_a<Real, TP, false>), dim3(nc), dim3(TP), la, A.stream, A.plan,
-                       A.tiles, K, A.user, A.settings, it);
-    (void)hipEventRecord(ev[4 * it + 1], A.stream);
+    launch_pass_a<Real, TP, false>(A, K, it);
+    (void)hipEventRecord(ev[4 * it + 1], (hipStream_t)A.stream);
     hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr,
-                       A.stream, A.plan, A.tiles, K, A.user, A.settings, it);
-    (void)hipEventRecord(ev[4 * it + 2], A.stream);
-    hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, A.stream, A.plan,
+                       (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, it, moff);
+    (void)hipEventRecord(ev[4 * it + 2], (hipStream_t)A.stream);
+    hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, (hipStream_t)A.stream, A.plan,
                        A.tiles, K, A.user, A.settings, it);
-    (void)hipEventRecord(ev[4 * it + 3], A.stream);
-    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, A.stream, A.plan, K,
+    (void)hipEventRecord(ev[4 * it + 3], (hipStream_t)A.stream);
+    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                        A.user, A.settings, it);
-    (void)hipEventRecord(ev[4 * it + 4], A.stream);
+    (void)hipEventRecord(ev[4 * it + 4], (hipStream_t)A.stream);
   }
-  hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, A.stream, A.plan, K, A.user, 0);
+  hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, (hipStream_t)A.stream, A.plan, K, A.user, 0);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipEventSynchronize(ev[nev - 1]);
   for (int k = 0; k < 4; ++k) stage_ms[k] = 0.0;
@@ -1349,10 +1459,10 @@ hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* 
 }
 
 // explicit instantiations used by the ABI layer
-template size_t pass_a_lds<double, 64>(int);
-template size_t pass_a_lds<double, 256>(int);
-template size_t pass_a_lds<float, 64>(int);
-template size_t pass_a_lds<float, 256>(int);
+template size_t pass_a_lds<double, 64>(int, int, int, int);
+template size_t pass_a_lds<double, 256>(int, int, int, int);
+template size_t pass_a_lds<float, 64>(int, int, int, int);
+template size_t pass_a_lds<float, 256>(int, int, int, int);
 template size_t pass_b_lds<double, 64>();
 template size_t pass_b_lds<double, 256>();
 template size_t pass_b_lds<float, 64>();

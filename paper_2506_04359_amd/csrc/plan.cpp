@@ -172,6 +172,12 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
   t.win_chunk_begin.clear();
   t.chunk_part_off.clear();
   t.part_elems = 0;
+  t.pair_order.clear();
+  t.prods.clear();
+  t.segs.clear();
+  t.tile_prod_begin.clear();
+  t.tile_seg_begin.clear();
+  t.max_tile_prods = t.max_tile_segs = 0;
   int32_t lm_base = 0;
   for (size_t wi = 0; wi < wins.size(); ++wi) {
     const HostWindow& w = *wins[wi];
@@ -194,6 +200,49 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
     }
     const int32_t first_tile = (int32_t)t.tile_lm_begin.size();
     for (int32_t s : tiles) t.tile_lm_begin.push_back(lm_base + s);
+    // per-tile pair order and Schur product lists
+    const int nblk = w.n_free * (w.n_free + 1) / 2;
+    std::vector<std::vector<uint16_t>> by_blk(nblk);
+    for (size_t ti = 0; ti < tiles.size(); ++ti) {
+      const int32_t la = tiles[ti];
+      const int32_t lb = ti + 1 < tiles.size() ? tiles[ti + 1] : w.n_points;
+      const int32_t p0 = w.lm_pair_begin[la], p1 = w.lm_pair_begin[lb];
+      std::vector<int32_t> ord(p1 - p0);
+      std::iota(ord.begin(), ord.end(), 0);
+      auto key = [&](int32_t q) {
+        const int sl = w.free_slot[w.pair_pose[p0 + q]];
+        return sl >= 0 ? sl : kMaxFree + 1;
+      };
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+      for (int32_t q : ord) t.pair_order.push_back((uint8_t)q);
+      for (auto& v : by_blk) v.clear();
+      for (int32_t l = la; l < lb; ++l) {
+        const int32_t q0 = w.lm_pair_begin[l] - p0;
+        const int nfp = w.lm_nfree[l];
+        for (int a = 0; a < nfp; ++a)
+          for (int b = a; b < nfp; ++b) {
+            const int sa = w.free_slot[w.pair_pose[p0 + q0 + a]];
+            const int sb = w.free_slot[w.pair_pose[p0 + q0 + b]];
+            const int blk = sa * w.n_free - (sa * (sa - 1)) / 2 + (sb - sa);
+            by_blk[blk].push_back((uint16_t)((q0 + a) | ((q0 + b) << 8)));
+          }
+      }
+      std::vector<int> order;
+      for (int k = 0; k < nblk; ++k)
+        if (!by_blk[k].empty()) order.push_back(k);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return by_blk[a].size() > by_blk[b].size(); });
+      t.tile_prod_begin.push_back((int32_t)t.prods.size());
+      t.tile_seg_begin.push_back((int32_t)t.segs.size());
+      int start = 0;
+      for (int k : order) {
+        t.segs.push_back(seg_word(k, start, (int)by_blk[k].size()));
+        for (uint16_t v : by_blk[k]) t.prods.push_back(v);
+        start += (int)by_blk[k].size();
+      }
+      t.max_tile_prods = std::max(t.max_tile_prods, start);
+      t.max_tile_segs = std::max(t.max_tile_segs, (int32_t)order.size());
+    }
     // chunks: split the window's tiles into about n_obs / chunk_obs runs of
     // balanced observation counts; a window always has at least one chunk
     t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
@@ -219,8 +268,24 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
     lm_base += w.n_points;
   }
   t.tile_lm_begin.push_back(lm_base);
+  t.tile_prod_begin.push_back((int32_t)t.prods.size());
+  t.tile_seg_begin.push_back((int32_t)t.segs.size());
   t.chunk_tile_begin.push_back((int32_t)t.tile_lm_begin.size() - 1);
   t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
+  // group chunks by size class (stable: windows stay in order inside a class)
+  t.chunk_order.clear();
+  for (int c = 0; c < kClasses; ++c) {
+    t.class_begin[c] = (int32_t)t.chunk_order.size();
+    t.class_nf[c] = 0;
+    for (int32_t k = 0; k < t.n_chunks(); ++k) {
+      const int nf = wins[t.chunk_window[k]]->n_free;
+      if (size_class(nf) == c) {
+        t.chunk_order.push_back(k);
+        t.class_nf[c] = std::max(t.class_nf[c], nf);
+      }
+    }
+  }
+  t.class_begin[kClasses] = (int32_t)t.chunk_order.size();
 }
 
 }  // namespace ba

@@ -29,6 +29,9 @@ constexpr int kMaxFreeFp64 = 29;     // FP64 partial of S must fit in LDS
 constexpr int kMaxObsPerLandmark = 4096;
 constexpr int kTileSmall = 64;       // pairs per tile, small-LDS configuration
 constexpr int kTileLarge = 256;      // pairs per tile, large configuration
+constexpr int kBS = 37;              // stored stride of a 6x6 block (odd: spreads LDS banks)
+constexpr int kClasses = 4;          // size classes of chunks: n_free <= 8, 16, 24, 32
+constexpr int kClassNf[kClasses] = {8, 16, 24, 32};
 
 struct HostWindow {
   int32_t n_poses = 0, n_points = 0, n_cams = 0, n_free = 0;
@@ -66,19 +69,46 @@ struct LaunchTables {
   std::vector<int32_t> chunk_tile_begin; // n_chunks + 1
   std::vector<int32_t> win_chunk_begin;  // n_windows + 1
   std::vector<int64_t> chunk_part_off;   // n_chunks, element offset of its S partial
+  std::vector<int32_t> chunk_order;      // n_chunks, grouped by size class
+  int32_t class_begin[kClasses + 1] = {0, 0, 0, 0, 0};
+  int32_t class_nf[kClasses] = {0, 0, 0, 0};   // largest n_free in each class
   int64_t part_elems = 0;                // total partial elements
+  // Per tile, the order in which its pairs are handled: free pairs sorted by
+  // free slot (so that equal poses sit in adjacent lanes), then fixed pairs.
+  // Indexed by the batch-global pair position of the tile: pair_order[p0 + t]
+  // is the tile-local pair handled by thread t.
+  std::vector<uint8_t> pair_order;       // n_pairs (batch)
+  // Per tile, the Schur products (a, b) of pairs of one landmark (a <= b,
+  // both free) grouped by their target block of S: segments of
+  // (target block, first product, count), longest first.
+  std::vector<uint16_t> prods;           // qa | qc << 8 (tile-local pairs)
+  std::vector<uint32_t> segs;            // blk | start << 10 | len << 23
+  std::vector<int32_t> tile_prod_begin;  // n_tiles + 1
+  std::vector<int32_t> tile_seg_begin;   // n_tiles + 1
+  int32_t max_tile_prods = 0, max_tile_segs = 0;
   int32_t n_tiles() const { return (int32_t)tile_lm_begin.size() - 1; }
   int32_t n_chunks() const { return (int32_t)chunk_window.size(); }
 };
 
-// Elements of one chunk's partial: the upper 6x6 blocks of S (36 each), then
+// Elements of one chunk's partial: the upper 6x6 blocks of S (kBS each), then
 // the reduced right-hand side (6 n_free) and diag(U) (6 n_free).
 inline int64_t partial_elems(int n_free) {
   const int64_t nblk = (int64_t)n_free * (n_free + 1) / 2;
-  return nblk * 36 + 12 * (int64_t)n_free;
+  return nblk * kBS + 12 * (int64_t)n_free;
+}
+
+inline int size_class(int n_free) {
+  for (int c = 0; c < kClasses; ++c)
+    if (n_free <= kClassNf[c]) return c;
+  return kClasses - 1;
 }
 
 void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_obs,
                  LaunchTables& out);
+
+// Segment word of the product lists.
+inline uint32_t seg_word(int blk, int start, int len) {
+  return (uint32_t)blk | ((uint32_t)start << 10) | ((uint32_t)len << 23);
+}
 
 }  // namespace ba
