@@ -26,7 +26,7 @@ template <typename Real, int TP>
 size_t pass_a_lds(int np, int nc, int nf, int list_bytes);
 template <typename Real, int TP>
 size_t pass_b_lds();
-size_t reduce_lds(int max_nf, int max_chunks, int* max_off);
+size_t reduce_lds(int max_nf);
 template <typename Real, int TP, bool ADJ>
 hipError_t set_attrs();
 template <typename Real, int TP>
@@ -75,11 +75,9 @@ struct DeviceTables {
   int32_t* chunk_tile_begin = nullptr;
   int64_t* chunk_part_off = nullptr;
   int32_t* chunk_order = nullptr;
-  uint8_t* pair_order = nullptr;
-  uint16_t* prods = nullptr;
-  uint32_t* segs = nullptr;
-  int32_t* tile_prod_begin = nullptr;
-  int32_t* tile_seg_begin = nullptr;
+  int32_t* pair_rec = nullptr;
+  int32_t* tile_rec = nullptr;
+  uint32_t* lists = nullptr;
   int cls_begin[kClasses + 1] = {0, 0, 0, 0, 0};
   int cls_nf[kClasses] = {0, 0, 0, 0};
   int list_bytes = 0;   // largest per-tile segment + product list
@@ -126,7 +124,7 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   build_tiles(ws, tp, chunk_obs, t);
   // per-window records with this table's chunk ranges
   std::vector<WinDev> wd(b->wins.size());
-  int32_t po = 0, lo = 0, co = 0, oo = 0, pa = 0;
+  int32_t po = 0, lo = 0, co = 0, oo = 0, pa = 0, so = 0;
   for (size_t i = 0; i < b->wins.size(); ++i) {
     const HostWindow& w = b->wins[i];
     WinDev& d = wd[i];
@@ -141,7 +139,8 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
     d.pair_off = pa;
     d.chunk_begin = t.win_chunk_begin[i];
     d.chunk_end = t.win_chunk_begin[i + 1];
-    d.pad = 0;
+    d.sum_off = so;
+    so += (int32_t)partial_elems(w.n_free);
     po += w.n_poses;
     lo += w.n_points;
     co += w.n_cams;
@@ -155,11 +154,9 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   const size_t o_ct = blob.add(t.chunk_tile_begin);
   const size_t o_cp = blob.add(t.chunk_part_off);
   const size_t o_co = blob.add(t.chunk_order);
-  const size_t o_po = blob.add(t.pair_order);
-  const size_t o_pr = blob.add(t.prods);
-  const size_t o_sg = blob.add(t.segs);
-  const size_t o_tpb = blob.add(t.tile_prod_begin);
-  const size_t o_tsb = blob.add(t.tile_seg_begin);
+  const size_t o_pr = blob.add(t.pair_rec);
+  const size_t o_tr = blob.add(t.tile_rec);
+  const size_t o_ls = blob.add(t.lists);
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, blob.size);
   if (e != hipSuccess) return set_error(BA_ERR_OOM, "plan tables: hipMalloc failed");
@@ -184,12 +181,10 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   D.chunk_tile_begin = (int32_t*)((char*)mem + o_ct);
   D.chunk_part_off = (int64_t*)((char*)mem + o_cp);
   D.chunk_order = (int32_t*)((char*)mem + o_co);
-  D.pair_order = (uint8_t*)((char*)mem + o_po);
-  D.prods = (uint16_t*)((char*)mem + o_pr);
-  D.segs = (uint32_t*)((char*)mem + o_sg);
-  D.tile_prod_begin = (int32_t*)((char*)mem + o_tpb);
-  D.tile_seg_begin = (int32_t*)((char*)mem + o_tsb);
-  D.list_bytes = t.max_tile_segs * 4 + t.max_tile_prods * 2 + 16;
+  D.pair_rec = (int32_t*)((char*)mem + o_pr);
+  D.tile_rec = (int32_t*)((char*)mem + o_tr);
+  D.lists = (uint32_t*)((char*)mem + o_ls);
+  D.list_bytes = t.max_tile_words * 4 + 16;
   D.max_cpw = 0;
   for (size_t i = 0; i + 1 < t.win_chunk_begin.size(); ++i)
     D.max_cpw = std::max(D.max_cpw, t.win_chunk_begin[i + 1] - t.win_chunk_begin[i]);
@@ -307,13 +302,12 @@ ba_status pick_config(const ba_batch_s* b, int precision, int* which) {
   if (fits(1)) *which = 1;
   else if (fits(0)) *which = 0;
   else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
-  int moff = 0;
-  if (reduce_lds(nf, 1, &moff) > kLdsLimit) return set_error(BA_ERR_UNSUPPORTED, "reduced system too large for LDS");
+  if (reduce_lds(nf) > kLdsLimit) return set_error(BA_ERR_UNSUPPORTED, "reduced system too large for LDS");
   return BA_OK;
 }
 
 struct Layout {
-  size_t du, dv, w, poses_b, points_b, state, dp, part, cost_a, cost_b, flag_a, flag_b, total;
+  size_t du, dv, w, poses_b, points_b, state, dp, ssum, part, cost_a, cost_b, flag_a, flag_b, total;
 };
 
 Layout layout(const ba_batch_s* b, const DeviceTables& t, size_t real) {
@@ -331,6 +325,9 @@ Layout layout(const ba_batch_s* b, const DeviceTables& t, size_t real) {
   L.points_b = take(sizeof(double) * 3 * b->n_points);
   L.state = take(sizeof(WinState) * b->wins.size());
   L.dp = take(sizeof(double) * kDpStride * b->wins.size());
+  int64_t sum_elems = 0;
+  for (auto& w : b->wins) sum_elems += partial_elems(w.n_free);
+  L.ssum = take(sizeof(double) * sum_elems);
   L.part = take(real * t.part_elems);
   L.cost_a = take(sizeof(double) * t.n_chunks);
   L.cost_b = take(sizeof(double) * t.n_chunks);
@@ -351,6 +348,7 @@ DevWork<Real> make_work(const Layout& L, void* ws, bool has_w) {
   K.points_b = (double*)(m + L.points_b);
   K.state = (WinState*)(m + L.state);
   K.dp = (double*)(m + L.dp);
+  K.ssum = (double*)(m + L.ssum);
   K.part = (Real*)(m + L.part);
   K.part_cost_a = (double*)(m + L.cost_a);
   K.part_cost_b = (double*)(m + L.cost_b);
@@ -398,11 +396,9 @@ DevTiles dev_tiles(const DeviceTables& t) {
   d.chunk_tile_begin = t.chunk_tile_begin;
   d.chunk_part_off = t.chunk_part_off;
   d.chunk_order = t.chunk_order;
-  d.pair_order = t.pair_order;
-  d.prods = t.prods;
-  d.segs = t.segs;
-  d.tile_prod_begin = t.tile_prod_begin;
-  d.tile_seg_begin = t.tile_seg_begin;
+  d.pair_rec = t.pair_rec;
+  d.tile_rec = t.tile_rec;
+  d.lists = t.lists;
   d.n_chunks = t.n_chunks;
   return d;
 }

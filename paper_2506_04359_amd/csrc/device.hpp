@@ -12,7 +12,7 @@ namespace ba {
 struct WinDev {
   int32_t n_poses, n_points, n_cams, n_free;
   int32_t pose_off, point_off, cam_off, obs_off;   // first pose / landmark / camera / observation
-  int32_t pair_off, chunk_begin, chunk_end, pad;
+  int32_t pair_off, chunk_begin, chunk_end, sum_off;   // sum_off: summed system in the workspace
 };
 
 // Per-window LM state, in the workspace.
@@ -43,11 +43,9 @@ struct DevPlan {
 
 struct DevTiles {
   const int32_t* chunk_order;     // chunks grouped by size class
-  const uint8_t* pair_order;      // per pair position: tile-local pair of that thread
-  const uint16_t* prods;          // Schur products (qa | qc << 8), per tile
-  const uint32_t* segs;           // product segments by target block, per tile
-  const int32_t* tile_prod_begin; // per tile + 1
-  const int32_t* tile_seg_begin;  // per tile + 1
+  const int32_t* pair_rec;        // 4 per pair position (thread order of its tile)
+  const int32_t* tile_rec;        // 8 per tile
+  const uint32_t* lists;          // per tile: segment words then products
   const int32_t* tile_lm_begin;
   const int32_t* chunk_window;
   const int32_t* chunk_tile_begin;
@@ -64,6 +62,7 @@ struct DevWork {
   double* points_b;
   WinState* state;
   double* dp;               // per window, kDpStride doubles: the reduced-system solution
+  double* ssum;             // per window: the chunk partials summed in FP64
   Real* part;               // chunk partials of S, the reduced rhs and diag(U)
   double* part_cost_a;      // per chunk: sum w rho at the current state
   double* part_cost_b;      // per chunk: sum w rho at the candidate
@@ -92,6 +91,8 @@ struct DevSettings {
 };
 
 constexpr int kDpStride = 192;
+constexpr int kSumSlice = 2048;   // entries of the summed system per workgroup of k_sum
+constexpr int kSumSlices = (528 * kBS + 12 * 32 + kSumSlice - 1) / kSumSlice;
 
 // Dimensions of the window caches in LDS (largest in the launch).
 struct LdsDims {

@@ -475,10 +475,10 @@ __global__ void k_pack(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U) {
 template <typename Real, int N>
 __device__ __forceinline__ void run_sums(Real* v, int key) {
   const int lane = threadIdx.x & 63;
-#pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const int k2 = __shfl_down(key, off, 64);
     const bool ok = (lane + off < 64) && (k2 == key);
+    if (!__any(ok)) break;   // no run in this wave is longer than off
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const Real u = __shfl_down(v[i], off, 64);
@@ -491,6 +491,21 @@ __device__ __forceinline__ void run_sums(Real* v, int key) {
 __constant__ int kUpperOff[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
                                   21, 22, 23, 28, 29, 35};
 
+// Stored row stride of a pair's Z_bar (6 rows of 3): padded to 4 in FP32 so a
+// row is one 16-byte LDS read; unpadded in FP64, where LDS is the constraint.
+template <typename Real>
+struct ZRow {
+  static constexpr int R = sizeof(Real) == 4 ? 4 : 3;
+  static constexpr int S = 6 * R;
+};
+
+// Words of a tile's product list kept in registers between its load (tile
+// start) and its store to LDS (after phase 2).
+template <int TP>
+struct ListRegs {
+  static constexpr int N = TP >= 256 ? 12 : 16;
+};
+
 // LDS carve of pass A.  Window caches and the reduced-system partial are sized
 // by the launch's largest window; the per-tile buffers by TP.
 template <typename Real, int TP>
@@ -500,8 +515,8 @@ struct PassALds {
     const size_t nblk = (size_t)nf * (nf + 1) / 2;
     const size_t region = std::max<size_t>((size_t)TP * 9 * sizeof(Real), (size_t)list_bytes);
     return (size_t)(np * 12 + nc * 16 + 16) * sizeof(double) + (64 + TP + 4) * sizeof(int) +
-           (nblk * kBS + 12 * (size_t)nf + (size_t)NW * nf * 27 + (size_t)TP * (18 + 12)) * sizeof(Real) +
-           (region + 15) / 16 * 16;
+           (nblk * kBS + 12 * (size_t)nf + (size_t)NW * nf * 27) * sizeof(Real) + 16 +
+           (size_t)TP * (ZRow<Real>::S + 12) * sizeof(Real) + (region + 15) / 16 * 16;
   }
 };
 
@@ -511,6 +526,8 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
                                                LdsDims D) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = TP / 64;
+  constexpr int LR = ListRegs<TP>::N;
+  constexpr int kZS = ZRow<Real>::S, ZR = ZRow<Real>::R;
   const int chunk = T.chunk_order[cls_begin + xcd_chunk(blockIdx.x, gridDim.x)];
   const int wi = T.chunk_window[chunk];
   const WinDev W = P.win[wi];
@@ -532,12 +549,24 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
   Real* sB = sS + nblk * kBS;                                 // nS
   Real* sD = sB + nS;                                         // nS
   Real* sUw = sD + nS;                                        // NW * nf * 27
-  Real* sPZ = sUw + NW * nf * 27;                             // TP * 18
-  Real* sLF = sPZ + TP * 18;                                  // TP * 12
+  Real* sPZ = reinterpret_cast<Real*>(
+      (reinterpret_cast<uintptr_t>(sUw + NW * nf * 27) + 15) & ~uintptr_t(15));   // TP * kZS
+  Real* sLF = sPZ + TP * kZS;                                 // TP * 12
   unsigned char* sReg = reinterpret_cast<unsigned char*>(
       (reinterpret_cast<uintptr_t>(sLF + TP * 12) + 15) & ~uintptr_t(15));
   Real* sPV = reinterpret_cast<Real*>(sReg);                  // TP * 9 (phases 1-2)
-  uint32_t* sSeg = reinterpret_cast<uint32_t*>(sReg);         // segments (phase 4)
+  uint32_t* sLst = reinterpret_cast<uint32_t*>(sReg);         // product lists (phase 4)
+
+  const int4* trec = reinterpret_cast<const int4*>(T.tile_rec);
+  const int4* prec = reinterpret_cast<const int4*>(T.pair_rec);
+  const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
+  int4 ta = make_int4(0, 0, 0, 0), tb = make_int4(0, 0, 0, 0);
+  int4 rec = make_int4(0, 0, 0, -1);
+  if (t0 < t1) {
+    ta = trec[2 * t0];
+    tb = trec[2 * t0 + 1];
+    if (tid < ta.y) rec = prec[ta.x + tid];
+  }
 
   load_window(P, W, poses, sPose, sCam, sFree);
   for (int k = tid; k < nblk * kBS + 2 * nS + NW * nf * 27; k += TP) sS[k] = (Real)0;
@@ -545,27 +574,53 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
   __syncthreads();
 
   double cost = 0.0;
-  const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
   for (int t = t0; t < t1; ++t) {
-    const int l0 = T.tile_lm_begin[t], l1 = T.tile_lm_begin[t + 1];
-    const int p0 = P.lm_pair_begin[l0], p1 = P.lm_pair_begin[l1];
-    const int nP = p1 - p0, nL = l1 - l0;
+    const int p0 = ta.x, nP = ta.y, l0 = ta.z, nL = ta.w;
+    const int lw0 = tb.x, nseg = tb.y, nprod = tb.z;
+    const int nwords = nseg + (nprod + 1) / 2;
+    // next tile's record, in flight during this tile
+    int4 nta = ta, ntb = tb;
+    if (t + 1 < t1) {
+      nta = trec[2 * (t + 1)];
+      ntb = trec[2 * (t + 1) + 1];
+    }
+    // this tile's pair data: point and first observation, and its list words
+    const int q = (rec.z >> 8) & 255, pose = rec.z & 255, nobs = rec.z >> 16;
+    const int slot = tid < nP ? rec.w : -1;
+    const int o0 = rec.x, lm = rec.y;
+    double px = 0, py = 0, pz = 0, du0 = 0, dv0 = 0, wo0 = 1;
+    int cam0 = 0;
+    if (tid < nP) {
+      const double* pt = points + 3 * (lm - W.point_off);
+      px = pt[0];
+      py = pt[1];
+      pz = pt[2];
+      cam0 = P.obs_cam[o0];
+      du0 = (double)K.du[o0];
+      dv0 = (double)K.dv[o0];
+      if (K.w) wo0 = (double)K.w[o0];
+    }
+    int lq0 = 0, lq1 = 0;
+    if (tid < nL) {
+      lq0 = P.lm_pair_begin[l0 + tid] - p0;
+      lq1 = P.lm_pair_begin[l0 + tid + 1] - p0;
+    }
+    const bool lregs = nwords <= LR * TP;
+    uint32_t lwv[LR];
+    if (lregs) {
+#pragma unroll
+      for (int k = 0; k < LR; ++k) {
+        const int i = tid + k * TP;
+        lwv[k] = i < nwords ? T.lists[lw0 + i] : 0u;
+      }
+    }
 
-    // ---- phase 1: thread t linearises pair order[t] (free pairs sorted by slot)
-    int q = -1, slot = -1;
+    // ---- phase 1: thread t linearises its pair (free pairs sorted by slot)
     PairAcc<Real> A;
     pair_zero(A);
     if (tid < nP) {
-      q = T.pair_order[p0 + tid];
-      const int gp = p0 + q;
-      const int lm = P.pair_lm[gp];                   // batch-global landmark
-      const int pose = P.pair_pose[gp];
-      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
-      slot = sFree[pose];
       sPL[q] = lm - l0;
       const double* Rt = sPose + 12 * pose;
-      const double* pt = points + 3 * (lm - W.point_off);
-      const double px = pt[0], py = pt[1], pz = pt[2];
       double xb[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -575,7 +630,13 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
-      for (int o = o0; o < o1; ++o) {
+      {
+        const double* C = sCam + 16 * cam0;
+        const Lin<Real> L = linearise<Real>(xb, C, du0, dv0, wo0, S.huber_delta);
+        cost += L.rho_w;
+        pair_add<Real, ADJ>(A, L, Rp, slot >= 0, C);
+      }
+      for (int o = o0 + 1; o < o0 + nobs; ++o) {
         const double* C = sCam + 16 * P.obs_cam[o];
         const double wo = K.w ? (double)K.w[o] : 1.0;
         const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
@@ -592,10 +653,9 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
 
     // ---- phase 2: one thread per landmark: V*, L D L^T, h
     if (tid < nL) {
-      const int lm = l0 + tid;
-      const int q0 = P.lm_pair_begin[lm] - p0, q1 = P.lm_pair_begin[lm + 1] - p0;
+      const int lmg = l0 + tid;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
-      for (int qq = q0; qq < q1; ++qq) {
+      for (int qq = lq0; qq < lq1; ++qq) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) V[k] += sPV[9 * qq + k];
 #pragma unroll
@@ -609,7 +669,7 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
         c[2] = -g[2];
       } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) c[k] = U.grad_points ? (Real)U.grad_points[3 * lm + k] : (Real)0;
+        for (int k = 0; k < 3; ++k) c[k] = U.grad_points ? (Real)U.grad_points[3 * lmg + k] : (Real)0;
       }
       LDL3<Real> F;
       if (!ldl3(V, !ADJ, F)) sFlag[0] = 1;
@@ -627,12 +687,19 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       }
     }
     __syncthreads();
-    // the V region now holds this tile's Schur product segments and products
-    const int sb0 = T.tile_seg_begin[t], nseg = T.tile_seg_begin[t + 1] - sb0;
-    const int pb0 = T.tile_prod_begin[t], nprod = T.tile_prod_begin[t + 1] - pb0;
-    uint16_t* sProd = reinterpret_cast<uint16_t*>(sSeg + nseg);
-    for (int k = tid; k < nseg; k += TP) sSeg[k] = T.segs[sb0 + k];
-    for (int k = tid; k < nprod; k += TP) sProd[k] = T.prods[pb0 + k];
+    // the V region now holds this tile's product list
+    if (lregs) {
+#pragma unroll
+      for (int k = 0; k < LR; ++k) {
+        const int i = tid + k * TP;
+        if (i < nwords) sLst[i] = lwv[k];
+      }
+    } else {
+      for (int i = tid; i < nwords; i += TP) sLst[i] = T.lists[lw0 + i];
+    }
+    // next tile's pair records (its tile record has arrived by now)
+    int4 nrec = make_int4(0, 0, 0, -1);
+    if (t + 1 < t1 && tid < nta.y) nrec = prec[nta.x + tid];
 
     // ---- phase 3: Z_bar = W L^-T |D|^-1/2 and the reduced rhs of this pair;
     // then per-pose sums over adjacent lanes, added once per run
@@ -651,14 +718,15 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       Real sh[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) sh[k] = f[6 + k] * f[9 + k];
-      Real* Z = sPZ + 18 * q;
+      Real* Z = sPZ + kZS * q;
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
         Real z[3];
         ldl3_half(F, A.W + 3 * r, z);
-        Z[3 * r] = z[0];
-        Z[3 * r + 1] = z[1];
-        Z[3 * r + 2] = z[2];
+        Z[ZR * r] = z[0];
+        Z[ZR * r + 1] = z[1];
+        Z[ZR * r + 2] = z[2];
+        if (ZR == 4) Z[ZR * r + 3] = (Real)0;
         v[21 + r] = (ADJ ? (Real)0 : -A.gp[r]) - (z[0] * sh[0] + z[1] * sh[1] + z[2] * sh[2]);
       }
 #pragma unroll
@@ -681,31 +749,62 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     // ---- phase 4: Schur blocks.  Unit (segment, row r) owns row r of one
     // target block for this tile: it sums -Z_a[r] sigma Z_b^T over the
     // segment's products in registers and updates the partial once.
+    const uint16_t* sProd = reinterpret_cast<const uint16_t*>(sLst + nseg);
     for (int u = tid; u < nseg * 6; u += TP) {
-      const uint32_t word = sSeg[u / 6];
+      const uint32_t word = sLst[u / 6];
       const int r = u % 6;
       const int blk = word & 1023, start = (word >> 10) & 8191, len = word >> 23;
-      Real acc[6] = {0, 0, 0, 0, 0, 0};
-      for (int k = start; k < start + len; ++k) {
-        const uint32_t pr = sProd[k];
-        const int qa = pr & 255, qc = pr >> 8;
-        const Real* Za = sPZ + 18 * qa + 3 * r;
-        Real z0 = Za[0], z1 = Za[1], z2 = Za[2];
+      Real acc[6] = {0, 0, 0, 0, 0, 0}, acd[6] = {0, 0, 0, 0, 0, 0};
+      int k = start;
+      const int kend = start + len;
+      for (; k + 1 < kend; k += 2) {
+        const uint32_t pa = sProd[k], pb = sProd[k + 1];
+        const int qa0 = pa & 255, qc0 = pa >> 8, qa1 = pb & 255, qc1 = pb >> 8;
+        const Real* Za0 = sPZ + kZS * qa0 + ZR * r;
+        const Real* Za1 = sPZ + kZS * qa1 + ZR * r;
+        Real a0 = Za0[0], a1 = Za0[1], a2 = Za0[2];
+        Real b0 = Za1[0], b1 = Za1[1], b2 = Za1[2];
         if (ADJ) {
-          const Real* sg = sLF + 12 * sPL[qa] + 6;
-          z0 *= sg[0];
-          z1 *= sg[1];
-          z2 *= sg[2];
+          const Real* g0 = sLF + 12 * sPL[qa0] + 6;
+          const Real* g1 = sLF + 12 * sPL[qa1] + 6;
+          a0 *= g0[0];
+          a1 *= g0[1];
+          a2 *= g0[2];
+          b0 *= g1[0];
+          b1 *= g1[1];
+          b2 *= g1[2];
         }
-        const Real* Zc = sPZ + 18 * qc;
+        const Real* Zc0 = sPZ + kZS * qc0;
+        const Real* Zc1 = sPZ + kZS * qc1;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += z0 * Zc[3 * c] + z1 * Zc[3 * c + 1] + z2 * Zc[3 * c + 2];
+        for (int c = 0; c < 6; ++c) {
+          acc[c] += a0 * Zc0[ZR * c] + a1 * Zc0[ZR * c + 1] + a2 * Zc0[ZR * c + 2];
+          acd[c] += b0 * Zc1[ZR * c] + b1 * Zc1[ZR * c + 1] + b2 * Zc1[ZR * c + 2];
+        }
+      }
+      if (k < kend) {
+        const uint32_t pa = sProd[k];
+        const int qa0 = pa & 255, qc0 = pa >> 8;
+        const Real* Za0 = sPZ + kZS * qa0 + ZR * r;
+        Real a0 = Za0[0], a1 = Za0[1], a2 = Za0[2];
+        if (ADJ) {
+          const Real* g0 = sLF + 12 * sPL[qa0] + 6;
+          a0 *= g0[0];
+          a1 *= g0[1];
+          a2 *= g0[2];
+        }
+        const Real* Zc0 = sPZ + kZS * qc0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += a0 * Zc0[ZR * c] + a1 * Zc0[ZR * c + 1] + a2 * Zc0[ZR * c + 2];
       }
       Real* row = sS + kBS * blk + 6 * r;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) row[c] -= acc[c];
+      for (int c = 0; c < 6; ++c) row[c] -= acc[c] + acd[c];
     }
     __syncthreads();
+    ta = nta;
+    tb = ntb;
+    rec = nrec;
   }
 
   // ---- fold the per-wave pose sums into the partial: U (upper), rhs, diag(U)
@@ -796,9 +895,54 @@ __device__ __forceinline__ bool chol6(double* A) {
   return true;
 }
 
+// Sum of a window's chunk partials in FP64, in chunk order.  Grid: (window,
+// slice of kSumSlice entries); every thread keeps 8 entries and 16 loads in
+// flight, so the sum runs at memory speed instead of one workgroup per window.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_sum(DevPlan P, DevTiles T, DevWork<Real> K) {
+  const int wi = blockIdx.x;
+  const WinDev W = P.win[wi];
+  const int nf = W.n_free, nblk = nf * (nf + 1) / 2;
+  const int ne = nblk * kBS + 12 * nf;
+  const int e0 = blockIdx.y * kSumSlice;
+  if (e0 >= ne) return;
+  constexpr int E = kSumSlice / 256;
+  double acc[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) acc[k] = 0.0;
+  int c = W.chunk_begin;
+  for (; c + 1 < W.chunk_end; c += 2) {
+    const Real* a = K.part + T.chunk_part_off[c];
+    const Real* b = K.part + T.chunk_part_off[c + 1];
+    Real va[E], vb[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = e0 + threadIdx.x + 256 * k;
+      va[k] = e < ne ? a[e] : (Real)0;
+      vb[k] = e < ne ? b[e] : (Real)0;
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) acc[k] += (double)va[k] + (double)vb[k];
+  }
+  if (c < W.chunk_end) {
+    const Real* a = K.part + T.chunk_part_off[c];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = e0 + threadIdx.x + 256 * k;
+      if (e < ne) acc[k] += (double)a[e];
+    }
+  }
+  double* dst = K.ssum + W.sum_off;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = e0 + threadIdx.x + 256 * k;
+    if (e < ne) dst[e] = acc[k];
+  }
+}
+
 template <typename Real, int NT, bool ADJ>
 __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U,
-                                               DevSettings S, int it, int max_off) {
+                                               DevSettings S, int it) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wi = blockIdx.x;
   const WinDev W = P.win[wi];
@@ -824,23 +968,9 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
       if (!isfinite(F)) st.status = 1;
     }
   }
-  // the window's chunk offsets, staged in LDS after the reduced system
-  int64_t* sOff = reinterpret_cast<int64_t*>(sD + nS + 2);
-  const int ncw = c1 - c0;
-  const bool off_in_lds = ncw <= max_off;
-  if (off_in_lds)
-    for (int c = tid; c < ncw; c += NT) sOff[c] = T.chunk_part_off[c0 + c];
-  __syncthreads();
-  // sum of the chunk partials in chunk order (independent loads, unrolled)
-  for (int e = tid; e < ne; e += NT) {
-    double acc = 0.0;
-    if (off_in_lds) {
-#pragma unroll 4
-      for (int c = 0; c < ncw; ++c) acc += (double)K.part[sOff[c] + e];
-    } else {
-      for (int c = c0; c < c1; ++c) acc += (double)K.part[T.chunk_part_off[c] + e];
-    }
-    sS[e] = acc;
+  {
+    const double* src = K.ssum + W.sum_off;
+    for (int e = tid; e < ne; e += NT) sS[e] = src[e];
   }
   __syncthreads();
   const double lam = st.lambda;
@@ -917,18 +1047,14 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
       for (int a = 0; a < 6; ++a) B[6 * a + col] = y[a];
     }
     __syncthreads();
-    // trailing update: S_ij -= R_ki^T R_kj, k < i <= j
+    // trailing update: S_ij -= R_ki^T R_kj, k < i <= j.  Work item = (i, j, r, c)
+    // with i, j over the nt x nt grid of remaining blocks (lower half skipped).
     const int nt = nf - k - 1;
-    const int ntr = nt * (nt + 1) / 2 * 36;
-    for (int e = tid; e < ntr; e += NT) {
-      int bidx = e / 36;
-      const int rc = e % 36, r = rc / 6, c = rc % 6;
-      int i = 0;
-      while (bidx >= nt - i) {
-        bidx -= nt - i;
-        ++i;
-      }
-      const int j = i + bidx;
+    for (int e = tid; e < nt * nt * 36; e += NT) {
+      const int bij = e / 36, rc = e % 36;
+      const int i = bij / nt, j = bij % nt;
+      if (j < i) continue;
+      const int r = rc / 6, c = rc % 6;
       const double* Rki = sS + kBS * blk_index(k, k + 1 + i, nf);
       const double* Rkj = sS + kBS * blk_index(k, k + 1 + j, nf);
       double v = 0.0;
@@ -1337,14 +1463,10 @@ size_t pass_b_lds() {
          (64 + 4 + 2 * TP) * sizeof(int) + (size_t)TP * (18 + 12) * sizeof(Real);
 }
 
-// The reduce kernel's LDS: the reduced system, then room for the chunk
-// offsets of a window (as many as fit in the 160 KiB, at most max_chunks).
-size_t reduce_lds(int max_nf, int max_chunks, int* max_off) {
+// The reduce kernel's LDS: the reduced system of the largest window.
+size_t reduce_lds(int max_nf) {
   const int nblk = max_nf * (max_nf + 1) / 2;
-  const size_t base = (size_t)(nblk * kBS + 12 * max_nf + 2) * sizeof(double);
-  const size_t room = base < 160 * 1024 ? (160 * 1024 - base) / sizeof(int64_t) : 0;
-  *max_off = (int)std::min<size_t>(room, (size_t)std::max(max_chunks, 1));
-  return base + (size_t)(*max_off) * sizeof(int64_t);
+  return (size_t)(nblk * kBS + 12 * max_nf + 2) * sizeof(double);
 }
 
 constexpr int kReduceThreads = 256;
@@ -1376,16 +1498,17 @@ void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
 template <typename Real, int TP>
 hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
-  int moff = 0;
-  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf, A.max_cpw, &moff);
+  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf);
   hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                      A.settings);
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, (hipStream_t)A.stream, A.plan, A.tiles, K, A.user);
   const int iters = A.settings.max_iters;
   for (int it = 0; it < iters; ++it) {
     launch_pass_a<Real, TP, false>(A, K, it);
+    hipLaunchKernelGGL(k_sum<Real>, dim3(nw, kSumSlices), dim3(256), 0, (hipStream_t)A.stream,
+                       A.plan, A.tiles, K);
     hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr,
-                       (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, it, moff);
+                       (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, it);
     hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, (hipStream_t)A.stream, A.plan,
                        A.tiles, K, A.user, A.settings, it);
     hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
@@ -1401,14 +1524,15 @@ hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
 template <typename Real, int TP>
 hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
-  int moff = 0;
-  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf, A.max_cpw, &moff);
+  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf);
   hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, (hipStream_t)A.stream, A.plan, K,
                      A.settings);
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, (hipStream_t)A.stream, A.plan, A.tiles, K, A.user);
   launch_pass_a<Real, TP, true>(A, K, 0);
+  hipLaunchKernelGGL(k_sum<Real>, dim3(nw, kSumSlices), dim3(256), 0, (hipStream_t)A.stream,
+                     A.plan, A.tiles, K);
   hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, true>), dim3(nw), dim3(kReduceThreads), lr,
-                     (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, 0, moff);
+                     (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, 0);
   hipLaunchKernelGGL((k_pass_b<Real, TP, true>), dim3(nc), dim3(TP), lb, (hipStream_t)A.stream, A.plan, A.tiles,
                      K, A.user, A.settings, 0);
   return hipGetLastError();
@@ -1420,8 +1544,7 @@ hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
 template <typename Real, int TP>
 hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* stage_ms) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
-  int moff = 0;
-  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf, A.max_cpw, &moff);
+  const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(A.max_nf);
   const int iters = A.settings.max_iters;
   const int nev = 4 * iters + 1;
   hipEvent_t* ev = new hipEvent_t[nev];
@@ -1433,8 +1556,10 @@ hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* 
   for (int it = 0; it < iters; ++it) {
     launch_pass_a<Real, TP, false>(A, K, it);
     (void)hipEventRecord(ev[4 * it + 1], (hipStream_t)A.stream);
+    hipLaunchKernelGGL(k_sum<Real>, dim3(nw, kSumSlices), dim3(256), 0, (hipStream_t)A.stream,
+                       A.plan, A.tiles, K);
     hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr,
-                       (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, it, moff);
+                       (hipStream_t)A.stream, A.plan, A.tiles, K, A.user, A.settings, it);
     (void)hipEventRecord(ev[4 * it + 2], (hipStream_t)A.stream);
     hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, (hipStream_t)A.stream, A.plan,
                        A.tiles, K, A.user, A.settings, it);

@@ -172,13 +172,11 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
   t.win_chunk_begin.clear();
   t.chunk_part_off.clear();
   t.part_elems = 0;
-  t.pair_order.clear();
-  t.prods.clear();
-  t.segs.clear();
-  t.tile_prod_begin.clear();
-  t.tile_seg_begin.clear();
-  t.max_tile_prods = t.max_tile_segs = 0;
-  int32_t lm_base = 0;
+  t.pair_rec.clear();
+  t.tile_rec.clear();
+  t.lists.clear();
+  t.max_tile_prods = t.max_tile_segs = t.max_tile_words = 0;
+  int32_t lm_base = 0, pair_base = 0, obs_base = 0;
   for (size_t wi = 0; wi < wins.size(); ++wi) {
     const HostWindow& w = *wins[wi];
     // tiles: whole landmarks, at most tp pairs and tp landmarks
@@ -214,7 +212,14 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
         return sl >= 0 ? sl : kMaxFree + 1;
       };
       std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
-      for (int32_t q : ord) t.pair_order.push_back((uint8_t)q);
+      for (int32_t q : ord) {
+        const int32_t wp = p0 + q;   // window-local pair
+        const int32_t nobs = w.pair_obs_begin[wp + 1] - w.pair_obs_begin[wp];
+        t.pair_rec.push_back(obs_base + w.pair_obs_begin[wp]);
+        t.pair_rec.push_back(lm_base + w.pair_lm[wp]);
+        t.pair_rec.push_back((int32_t)w.pair_pose[wp] | (q << 8) | (nobs << 16));
+        t.pair_rec.push_back(w.free_slot[w.pair_pose[wp]]);
+      }
       for (auto& v : by_blk) v.clear();
       for (int32_t l = la; l < lb; ++l) {
         const int32_t q0 = w.lm_pair_begin[l] - p0;
@@ -232,16 +237,23 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
         if (!by_blk[k].empty()) order.push_back(k);
       std::stable_sort(order.begin(), order.end(),
                        [&](int a, int b) { return by_blk[a].size() > by_blk[b].size(); });
-      t.tile_prod_begin.push_back((int32_t)t.prods.size());
-      t.tile_seg_begin.push_back((int32_t)t.segs.size());
+      const int32_t word_first = (int32_t)t.lists.size();
       int start = 0;
       for (int k : order) {
-        t.segs.push_back(seg_word(k, start, (int)by_blk[k].size()));
-        for (uint16_t v : by_blk[k]) t.prods.push_back(v);
+        t.lists.push_back(seg_word(k, start, (int)by_blk[k].size()));
         start += (int)by_blk[k].size();
       }
+      std::vector<uint16_t> prods;
+      for (int k : order)
+        for (uint16_t v : by_blk[k]) prods.push_back(v);
+      for (size_t k = 0; k < prods.size(); k += 2)
+        t.lists.push_back((uint32_t)prods[k] | ((k + 1 < prods.size() ? (uint32_t)prods[k + 1] : 0u) << 16));
       t.max_tile_prods = std::max(t.max_tile_prods, start);
       t.max_tile_segs = std::max(t.max_tile_segs, (int32_t)order.size());
+      t.max_tile_words = std::max(t.max_tile_words, (int32_t)t.lists.size() - word_first);
+      const int32_t rec[8] = {pair_base + p0, p1 - p0, lm_base + la, lb - la,
+                              word_first, (int32_t)order.size(), start, 0};
+      t.tile_rec.insert(t.tile_rec.end(), rec, rec + 8);
     }
     // chunks: split the window's tiles into about n_obs / chunk_obs runs of
     // balanced observation counts; a window always has at least one chunk
@@ -266,10 +278,10 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
       }
     }
     lm_base += w.n_points;
+    pair_base += (int32_t)w.n_pairs();
+    obs_base += (int32_t)w.n_obs;
   }
   t.tile_lm_begin.push_back(lm_base);
-  t.tile_prod_begin.push_back((int32_t)t.prods.size());
-  t.tile_seg_begin.push_back((int32_t)t.segs.size());
   t.chunk_tile_begin.push_back((int32_t)t.tile_lm_begin.size() - 1);
   t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
   // group chunks by size class (stable: windows stay in order inside a class)

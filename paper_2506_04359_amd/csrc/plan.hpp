@@ -75,17 +75,21 @@ struct LaunchTables {
   int64_t part_elems = 0;                // total partial elements
   // Per tile, the order in which its pairs are handled: free pairs sorted by
   // free slot (so that equal poses sit in adjacent lanes), then fixed pairs.
-  // Indexed by the batch-global pair position of the tile: pair_order[p0 + t]
-  // is the tile-local pair handled by thread t.
-  std::vector<uint8_t> pair_order;       // n_pairs (batch)
+  // Record of the pair handled by thread t of a tile, at pair_rec[4 (p0 + t)]:
+  // {first observation, landmark (both batch-global), pose | q << 8 | nobs << 16,
+  //  free slot or -1}; q = the pair's tile-local index in landmark order.
+  std::vector<int32_t> pair_rec;         // 4 per pair (batch)
+  // Per tile: {first pair, pairs, first landmark, landmarks, first list word,
+  // segments, products, 0}, batch-global.
+  std::vector<int32_t> tile_rec;         // 8 per tile
   // Per tile, the Schur products (a, b) of pairs of one landmark (a <= b,
   // both free) grouped by their target block of S: segments of
   // (target block, first product, count), longest first.
-  std::vector<uint16_t> prods;           // qa | qc << 8 (tile-local pairs)
-  std::vector<uint32_t> segs;            // blk | start << 10 | len << 23
-  std::vector<int32_t> tile_prod_begin;  // n_tiles + 1
-  std::vector<int32_t> tile_seg_begin;   // n_tiles + 1
-  int32_t max_tile_prods = 0, max_tile_segs = 0;
+  // Stored per tile as one word stream: nseg segment words
+  // (blk | start << 10 | len << 23), then the products two per word
+  // (qa | qc << 8 as 16-bit halves).
+  std::vector<uint32_t> lists;
+  int32_t max_tile_prods = 0, max_tile_segs = 0, max_tile_words = 0;
   int32_t n_tiles() const { return (int32_t)tile_lm_begin.size() - 1; }
   int32_t n_chunks() const { return (int32_t)chunk_window.size(); }
 };
