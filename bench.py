@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--chunk-obs", type=int, default=None,
+                    help="fixed observations per work item instead of the autotuned value")
     ap.add_argument("--cpu-sample", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -149,7 +151,11 @@ def main():
     reports = torch.zeros(48 * N_WINDOWS, dtype=torch.uint8, device=dev)
 
     chunk = None
-    if not args.no_tune:
+    if args.chunk_obs is not None:
+        batch.set_launch(args.chunk_obs)
+        chunk = args.chunk_obs
+        log(f"chunk_obs = {chunk} (fixed)")
+    elif not args.no_tune:
         big = torch.empty(max(batch.workspace_size(s_mixed), 1), dtype=torch.uint8, device=dev)
         # room for the finest candidate shape
         batch.set_launch(1024)

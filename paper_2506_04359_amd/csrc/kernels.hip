@@ -872,27 +872,40 @@ __device__ __forceinline__ void exp_se3(const double* xi, double* T /*3x4*/) {
   }
 }
 
-// Upper Cholesky R^T R = A of a 6x6 block held in registers; false on a
-// non-positive or non-finite pivot.
-__device__ __forceinline__ bool chol6(double* A) {
+// Upper Cholesky of one symmetric 6x6 block spread over a wave: lane l < 36
+// holds entry (l / 6, l % 6).  Writes the upper triangle of R to D and 1 / R_pp
+// to inv; raises *fail on a non-positive or non-finite pivot.  Every lane of
+// the wave takes part (the pivots are broadcast by shuffles).
+__device__ __forceinline__ void factor_diag(double a, double* D, double* inv, int* fail) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane / 6, c = lane - 6 * (lane / 6);
 #pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    double d = A[7 * a];
-#pragma unroll
-    for (int m = 0; m < a; ++m) d -= A[6 * m + a] * A[6 * m + a];
-    if (!(d > 0.0) || !isfinite(d)) return false;
-    const double ra = sqrt(d);
-    A[7 * a] = ra;
-    const double ir = 1.0 / ra;
-#pragma unroll
-    for (int c = a + 1; c < 6; ++c) {
-      double v = A[6 * a + c];
-#pragma unroll
-      for (int m = 0; m < a; ++m) v -= A[6 * m + a] * A[6 * m + c];
-      A[6 * a + c] = v * ir;
+  for (int p = 0; p < 6; ++p) {
+    const double d = __shfl(a, 7 * p, 64);
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (lane == 0) *fail = 1;
+      return;
     }
+    const double s = sqrt(d), ir = 1.0 / s;
+    if (r == p) a = c == p ? s : a * ir;
+    const double rr = __shfl(a, 6 * p + r, 64);   // R[p][r]
+    const double rc = __shfl(a, 6 * p + c, 64);   // R[p][c]
+    if (r > p && c > p) a -= rr * rc;
+    if (lane == p) inv[p] = ir;
   }
-  return true;
+  if (lane < 36 && c >= r) D[lane] = a;
+}
+
+// Pair (i, j), i <= j < n, of index e in the row-major upper triangle of an
+// n x n grid (row i starts at i*n - i*(i-1)/2).
+__device__ __forceinline__ void upper_pair(int e, int n, int& i, int& j) {
+  const float b = 2.0f * n + 1.0f;
+  int r = (int)((b - sqrtf(b * b - 8.0f * e)) * 0.5f);
+  r = r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
+  while (r > 0 && r * n - r * (r - 1) / 2 > e) --r;
+  while (r + 1 < n && (r + 1) * n - (r + 1) * r / 2 <= e) ++r;
+  i = r;
+  j = e - (r * n - r * (r - 1) / 2) + r;
 }
 
 // Sum of a window's chunk partials in FP64, in chunk order.  Grid: (window,
@@ -952,7 +965,8 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   double* sS = reinterpret_cast<double*>(smem);   // nblk * kBS
   double* sB = sS + nblk * kBS;                   // nS
   double* sD = sB + nS;                           // nS
-  int* sFail = reinterpret_cast<int*>(sD + nS);   // 1
+  double* sInv = sD + nS;                         // nS: 1 / R_pp of the diagonal blocks
+  int* sFail = reinterpret_cast<int*>(sInv + nS); // 1
   const int c0 = W.chunk_begin, c1 = W.chunk_end;
   const int ne = nblk * kBS + 2 * nS;
   if (tid == 0) {
@@ -1012,120 +1026,148 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   }
   __syncthreads();
 
-  // blocked Cholesky S = R^T R on 6x6 blocks (upper block storage)
+  // Blocked Cholesky S = R^T R on 6x6 blocks (upper block storage), right-
+  // looking.  The right-hand side rides along as one more column, so the
+  // forward substitution R^T y = b happens inside the factorisation.  Wave 0
+  // factors the next diagonal block while the other waves run the trailing
+  // update (one step of look-ahead); the back substitution runs in wave 0.
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lr = lane / 6, lc = lane - 6 * (lane / 6);   // entry of a 6x6 block (lanes 0..35)
   bool failed = sFail[0] != 0;
+  if (!failed && nf > 0 && wave == 0) {
+    double a = lane < 36 ? sS[kBS * blk_index(0, 0, nf) + lane] : 0.0;
+    factor_diag(a, sS + kBS * blk_index(0, 0, nf), sInv, sFail);
+  }
+  __syncthreads();
+  failed = sFail[0] != 0;
   for (int k = 0; k < nf && !failed; ++k) {
-    double* Dk = sS + kBS * blk_index(k, k, nf);
-    if (tid == 0) {
-      double A[36];
+    const double* Dk = sS + kBS * blk_index(k, k, nf);
+    const double* ik = sInv + 6 * k;
+    const int nt = nf - k - 1;
+    // panel: R_kj = R_kk^-T S_kj for j > k, one thread per column; the last
+    // item is the right-hand side y_k = R_kk^-T b_k
+    for (int e = tid; e <= 6 * nt; e += NT) {
+      double* B;
+      int stride;
+      if (e < 6 * nt) {
+        B = sS + kBS * blk_index(k, k + 1 + e / 6, nf) + e % 6;
+        stride = 6;
+      } else {
+        B = sB + 6 * k;
+        stride = 1;
+      }
+      double y[6];
 #pragma unroll
-      for (int e = 0; e < 36; ++e) A[e] = Dk[e];
-      const bool ok = chol6(A);
+      for (int i = 0; i < 6; ++i) {
+        double v = B[stride * i];
 #pragma unroll
-      for (int e = 0; e < 36; ++e) Dk[e] = A[e];
-      if (!ok) sFail[0] = 1;
+        for (int m = 0; m < i; ++m) v -= Dk[6 * m + i] * y[m];
+        y[i] = v * ik[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) B[stride * i] = y[i];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // look-ahead: update and factor the next diagonal block
+      if (nt > 0) {
+        const double* R = sS + kBS * blk_index(k, k + 1, nf);
+        double* Dn = sS + kBS * blk_index(k + 1, k + 1, nf);
+        double a = 0.0;
+        if (lane < 36) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) acc += R[6 * m + lr] * R[6 * m + lc];
+          a = Dn[lane] - acc;
+        }
+        factor_diag(a, Dn, sInv + 6 * (k + 1), sFail);
+      }
+    } else {
+      // trailing update S_ij -= R_ki^T R_kj over the upper pairs k < i <= j
+      // except the next diagonal block, then b_i -= R_ki^T y_k
+      const int npair = nt * (nt + 1) / 2 - 1;
+      for (int e = tid - 64; e < npair + nt; e += NT - 64) {
+        if (e < npair) {
+          int i, j;
+          upper_pair(e + 1, nt, i, j);
+          const double* A = sS + kBS * blk_index(k, k + 1 + i, nf);
+          const double* Bm = sS + kBS * blk_index(k, k + 1 + j, nf);
+          double acc[36];
+#pragma unroll
+          for (int x = 0; x < 36; ++x) acc[x] = 0.0;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            double u[6], v[6];
+#pragma unroll
+            for (int x = 0; x < 6; ++x) {
+              u[x] = A[6 * m + x];
+              v[x] = Bm[6 * m + x];
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) acc[6 * r + c] += u[r] * v[c];
+          }
+          double* D = sS + kBS * blk_index(k + 1 + i, k + 1 + j, nf);
+#pragma unroll
+          for (int x = 0; x < 36; ++x) D[x] -= acc[x];
+        } else {
+          const int i = e - npair;
+          const double* A = sS + kBS * blk_index(k, k + 1 + i, nf);
+          double yk[6];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) yk[m] = sB[6 * k + m];
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) v += A[6 * m + r] * yk[m];
+            sB[6 * (k + 1 + i) + r] -= v;
+          }
+        }
+      }
     }
     __syncthreads();
     failed = sFail[0] != 0;
-    if (failed) break;
-    // panel: R_kj = R_kk^-T S_kj, j > k (thread per column of each block)
-    const int npan = (nf - k - 1) * 6;
-    for (int e = tid; e < npan; e += NT) {
-      const int j = k + 1 + e / 6, col = e % 6;
-      double* B = sS + kBS * blk_index(k, j, nf);
-      double x[6], y[6];
-#pragma unroll
-      for (int a = 0; a < 6; ++a) x[a] = B[6 * a + col];
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        double v = x[a];
-#pragma unroll
-        for (int m = 0; m < a; ++m) v -= Dk[6 * m + a] * y[m];
-        y[a] = v / Dk[7 * a];
-      }
-#pragma unroll
-      for (int a = 0; a < 6; ++a) B[6 * a + col] = y[a];
-    }
-    __syncthreads();
-    // trailing update: S_ij -= R_ki^T R_kj, k < i <= j.  Work item = (i, j, r, c)
-    // with i, j over the nt x nt grid of remaining blocks (lower half skipped).
-    const int nt = nf - k - 1;
-    for (int e = tid; e < nt * nt * 36; e += NT) {
-      const int bij = e / 36, rc = e % 36;
-      const int i = bij / nt, j = bij % nt;
-      if (j < i) continue;
-      const int r = rc / 6, c = rc % 6;
-      const double* Rki = sS + kBS * blk_index(k, k + 1 + i, nf);
-      const double* Rkj = sS + kBS * blk_index(k, k + 1 + j, nf);
-      double v = 0.0;
-#pragma unroll
-      for (int m = 0; m < 6; ++m) v += Rki[6 * m + r] * Rkj[6 * m + c];
-      sS[kBS * blk_index(k + 1 + i, k + 1 + j, nf) + rc] -= v;
-    }
-    __syncthreads();
   }
-  if (!failed) {
-    // forward: R^T y = b
-    for (int k = 0; k < nf; ++k) {
-      const double* Dk = sS + kBS * blk_index(k, k, nf);
-      if (tid == 0) {
-        double R[36], b[6];
-#pragma unroll
-        for (int e = 0; e < 36; ++e) R[e] = Dk[e];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) b[a] = sB[6 * k + a];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-          double v = b[a];
-#pragma unroll
-          for (int m = 0; m < a; ++m) v -= R[6 * m + a] * b[m];
-          b[a] = v / R[7 * a];
-        }
-#pragma unroll
-        for (int a = 0; a < 6; ++a) sB[6 * k + a] = b[a];
-      }
-      __syncthreads();
-      for (int e = tid; e < (nf - k - 1) * 6; e += NT) {
-        const int j = k + 1 + e / 6, c = e % 6;
-        const double* B = sS + kBS * blk_index(k, j, nf);
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < 6; ++m) v += B[6 * m + c] * sB[6 * k + m];
-        sB[6 * j + c] -= v;
-      }
-      __syncthreads();
-    }
-    // backward: R x = y
+  if (!failed && wave == 0) {
+    // back substitution R x = y in one wave: lane l keeps rows l, l + 64, l + 128
+    double y0 = lane < nS ? sB[lane] : 0.0;
+    double y1 = lane + 64 < nS ? sB[lane + 64] : 0.0;
+    double y2 = lane + 128 < nS ? sB[lane + 128] : 0.0;
     for (int k = nf - 1; k >= 0; --k) {
       const double* Dk = sS + kBS * blk_index(k, k, nf);
-      if (tid == 0) {
-        double R[36], b[6];
+      double x[6];
 #pragma unroll
-        for (int e = 0; e < 36; ++e) R[e] = Dk[e];
+      for (int i = 5; i >= 0; --i) {
+        const int row = 6 * k + i;
+        const int sel = row >> 6;
+        const double own = sel == 0 ? y0 : (sel == 1 ? y1 : y2);
+        double v = __shfl(own, row & 63, 64);
 #pragma unroll
-        for (int a = 0; a < 6; ++a) b[a] = sB[6 * k + a];
+        for (int m = i + 1; m < 6; ++m) v -= Dk[6 * i + m] * x[m];
+        x[i] = v * sInv[row];
+      }
+      const int lim = 6 * k;
 #pragma unroll
-        for (int a = 5; a >= 0; --a) {
-          double v = b[a];
-#pragma unroll
-          for (int m = a + 1; m < 6; ++m) v -= R[6 * a + m] * b[m];
-          b[a] = v / R[7 * a];
+      for (int t = 0; t < 3; ++t) {
+        const int row = lane + 64 * t;
+        if (row < lim) {
+          const double* B = sS + kBS * blk_index(row / 6, k, nf) + 6 * (row % 6);
+          const double d = B[0] * x[0] + B[1] * x[1] + B[2] * x[2] + B[3] * x[3] + B[4] * x[4] +
+                           B[5] * x[5];
+          if (t == 0) y0 -= d;
+          else if (t == 1) y1 -= d;
+          else y2 -= d;
         }
-#pragma unroll
-        for (int a = 0; a < 6; ++a) sB[6 * k + a] = b[a];
       }
-      __syncthreads();
-      for (int e = tid; e < k * 6; e += NT) {
-        const int i = e / 6, r = e % 6;
-        const double* B = sS + kBS * blk_index(i, k, nf);
-        double v = 0.0;
+      if (lane == 0) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) v += B[6 * r + m] * sB[6 * k + m];
-        sB[6 * i + r] -= v;
+        for (int i = 0; i < 6; ++i) sB[6 * k + i] = x[i];
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
   double* dp = K.dp + kDpStride * wi;
   for (int e = tid; e < nS; e += NT) dp[e] = failed ? 0.0 : sB[e];
   if (ADJ) {
@@ -1466,10 +1508,10 @@ size_t pass_b_lds() {
 // The reduce kernel's LDS: the reduced system of the largest window.
 size_t reduce_lds(int max_nf) {
   const int nblk = max_nf * (max_nf + 1) / 2;
-  return (size_t)(nblk * kBS + 12 * max_nf + 2) * sizeof(double);
+  return (size_t)(nblk * kBS + 18 * max_nf + 2) * sizeof(double);
 }
 
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 512;
 
 template <typename Real, int TP, bool ADJ>
 hipError_t set_attrs() {
