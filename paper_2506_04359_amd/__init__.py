@@ -8,8 +8,15 @@ not been built (``python -m paper_2506_04359_amd.build``); there is no fallback.
 """
 from ._binding import (  # noqa: F401
     BA_CREATE_HOST_ONLY,
+    BA_ERR_HIP,
+    BA_ERR_INVALID_ARG,
+    BA_ERR_OOM,
+    BA_ERR_STATE,
+    BA_ERR_UNSUPPORTED,
+    BA_ERR_WORKSPACE_TOO_SMALL,
     BA_FP64,
     BA_MIXED,
+    BA_OK,
     BAError,
     Batch,
     Settings,

@@ -12,6 +12,14 @@ _LIB_PATH = os.path.join(_HERE, "libba.so")
 BA_FP64 = 0
 BA_MIXED = 1
 BA_CREATE_HOST_ONLY = 1
+# ba_status
+BA_OK = 0
+BA_ERR_INVALID_ARG = -1
+BA_ERR_OOM = -2
+BA_ERR_HIP = -3
+BA_ERR_WORKSPACE_TOO_SMALL = -4
+BA_ERR_UNSUPPORTED = -5
+BA_ERR_STATE = -6
 
 
 class BAError(RuntimeError):

@@ -92,3 +92,28 @@ def pose_errors(Pa, Pb):
     ang, dt = oracle.rotation_errors(Pa, Pb)
     tn = np.maximum(np.linalg.norm(Pb[:, :, 3], axis=1), 1.0)
     return float(ang.max()), float((dt / tn).max())
+
+
+def mixed_check(w, g, backend="schur", align=False, dec_replay=True, s=None):
+    """Mixed-precision bar against the FP64 oracle (decision replay when the
+    oracle can follow the GPU's sequence, else its own run): |dRMS| <= 1e-3 px,
+    rotation <= 1e-4 rad, translation <= 1e-4 * max(|t|, 1 m)."""
+    s = settings_for(w) if s is None else s
+    prob = oracle.Problem.from_window(w)
+    ref = None
+    if dec_replay:
+        try:
+            _, ref = oracle_replay(w, s, g["trace"], backend=backend)
+        except ValueError:
+            ref = None
+    if ref is None:
+        ref = oracle.lm_solve(w.poses_init, w.points_init, prob, oracle_settings(s), backend=backend)
+    rms_g = oracle.rms(g["poses"], g["points"], prob)
+    rms_o = oracle.rms(ref.poses, ref.points, prob)
+    assert abs(rms_g - rms_o) <= 1e-3, (rms_g, rms_o)
+    P = g["poses"]
+    if align:
+        P, _, _ = oracle.align_scale(g["poses"], g["points"], ref.poses)
+    ang, dt = pose_errors(P, ref.poses)
+    assert ang <= 1e-4 and dt <= 1e-4, (ang, dt)
+    return ref

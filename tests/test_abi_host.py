@@ -140,3 +140,13 @@ def test_free_pose_limit_reported_as_unsupported():
         ba.Window(n, 2, op, oj, [[400.0, 400.0, 320.0, 240.0]], pose_fixed=np.zeros(n, np.uint8),
                   host_only=True)
     assert e.value.status == -5
+
+
+def test_window_without_landmarks_plans_to_nothing():
+    import paper_2506_04359_amd as ba
+    w = bagen.tiny_window(seed=71, n_kf=4, n_lm=15)
+    W = ba.Window(3, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), w.intrinsics,
+                  obs_cam=np.zeros(0, np.int32), pose_fixed=w.pose_fixed[:3], extrinsics=w.extrinsics,
+                  host_only=True)
+    i = W.info()
+    assert i["n_obs"] == 0 and i["n_pairs"] == 0 and i["n_points"] == 0 and i["n_free"] == 2
