@@ -59,14 +59,21 @@ def test_fp64_beyond_lds_is_unsupported_and_mixed_is_not():
     assert W.workspace_size(ba.Settings(max_iters=1, precision=ba.BA_MIXED)) > 0
 
 
-@pytest.mark.parametrize("n_kf,fixed", [(33, (0,)), (64, tuple(range(32)))])
-def test_mixed_largest_reduced_system(n_kf, fixed):
+@pytest.mark.parametrize("n_kf,fixed,gauge_fixed", [(34, (0, 1), True), (64, tuple(range(32)), True),
+                                                    (33, (0,), False)])
+def test_mixed_largest_reduced_system(n_kf, fixed, gauge_fixed):
+    # With one fixed keyframe a mono window keeps its scale gauge: S is singular
+    # along it (smallest eigenvalue ~1e-11 of ~3e6) and once lambda has been
+    # divided down, FP32 rounding of S exceeds the damping there; such attempts
+    # fail their pivot and are rejected (lambda raised), which the LM schedule
+    # allows.  Two fixed keyframes remove the gauge: then no pivot may fail.
     import paper_2506_04359_amd as ba
     w = bagen.tiny_window(seed=62, n_kf=n_kf, n_lm=250, noise=0.5, fixed=fixed)
     assert int((w.pose_fixed == 0).sum()) == 32
     s = ba.Settings(max_iters=10, precision=ba.BA_MIXED)
     g = gpu_solve(w, s)
-    assert g["report"]["chol_failures"] == 0
+    if gauge_fixed:
+        assert g["report"]["chol_failures"] == 0
     mixed_check(w, g, backend="dense", align=True, s=s)
 
 
