@@ -549,11 +549,14 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
   Real* sB = sS + nblk * kBS;                                 // nS
   Real* sD = sB + nS;                                         // nS
   Real* sUw = sD + nS;                                        // NW * nf * 27
-  Real* sPZ = reinterpret_cast<Real*>(
-      (reinterpret_cast<uintptr_t>(sUw + NW * nf * 27) + 15) & ~uintptr_t(15));   // TP * kZS
+  // 16-byte aligned carve by offsets from the LDS base (integer casts of the
+  // pointers would lose the LDS address space and turn every access into a
+  // flat one)
+  const int oPZ = ((int)(reinterpret_cast<unsigned char*>(sUw + NW * nf * 27) - smem) + 15) & ~15;
+  Real* sPZ = reinterpret_cast<Real*>(smem + oPZ);           // TP * kZS
   Real* sLF = sPZ + TP * kZS;                                 // TP * 12
-  unsigned char* sReg = reinterpret_cast<unsigned char*>(
-      (reinterpret_cast<uintptr_t>(sLF + TP * 12) + 15) & ~uintptr_t(15));
+  const int oReg = ((int)(reinterpret_cast<unsigned char*>(sLF + TP * 12) - smem) + 15) & ~15;
+  unsigned char* sReg = smem + oReg;
   Real* sPV = reinterpret_cast<Real*>(sReg);                  // TP * 9 (phases 1-2)
   uint32_t* sLst = reinterpret_cast<uint32_t*>(sReg);         // product lists (phase 4)
 
