@@ -487,6 +487,9 @@ __device__ __forceinline__ void run_sums(Real* v, int key) {
   }
 }
 
+// Per-pose sums of pass A: U - Z sigma Z^T (21, upper), reduced rhs (6), diag(U) (6).
+constexpr int kPoseSums = 33;
+
 // Upper-triangle entry e (0..20) of a 6x6 block -> row-major offset r*6+c.
 __constant__ int kUpperOff[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
                                   21, 22, 23, 28, 29, 35};
@@ -515,7 +518,7 @@ struct PassALds {
     const size_t nblk = (size_t)nf * (nf + 1) / 2;
     const size_t region = std::max<size_t>((size_t)TP * 9 * sizeof(Real), (size_t)list_bytes);
     return (size_t)(np * 12 + nc * 16 + 16) * sizeof(double) + (64 + TP + 4) * sizeof(int) +
-           (nblk * kBS + 12 * (size_t)nf + (size_t)NW * nf * 27) * sizeof(Real) + 16 +
+           (nblk * kBS + 12 * (size_t)nf + (size_t)NW * nf * kPoseSums) * sizeof(Real) + 16 +
            (size_t)TP * (ZRow<Real>::S + 12) * sizeof(Real) + (region + 15) / 16 * 16;
   }
 };
@@ -548,11 +551,11 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
   Real* sS = reinterpret_cast<Real*>(sFlag + 4);              // nblk * kBS
   Real* sB = sS + nblk * kBS;                                 // nS
   Real* sD = sB + nS;                                         // nS
-  Real* sUw = sD + nS;                                        // NW * nf * 27
+  Real* sUw = sD + nS;                                        // NW * nf * kPoseSums
   // 16-byte aligned carve by offsets from the LDS base (integer casts of the
   // pointers would lose the LDS address space and turn every access into a
   // flat one)
-  const int oPZ = ((int)(reinterpret_cast<unsigned char*>(sUw + NW * nf * 27) - smem) + 15) & ~15;
+  const int oPZ = ((int)(reinterpret_cast<unsigned char*>(sUw + NW * nf * kPoseSums) - smem) + 15) & ~15;
   Real* sPZ = reinterpret_cast<Real*>(smem + oPZ);           // TP * kZS
   Real* sLF = sPZ + TP * kZS;                                 // TP * 12
   const int oReg = ((int)(reinterpret_cast<unsigned char*>(sLF + TP * 12) - smem) + 15) & ~15;
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
   }
 
   load_window(P, W, poses, sPose, sCam, sFree);
-  for (int k = tid; k < nblk * kBS + 2 * nS + NW * nf * 27; k += TP) sS[k] = (Real)0;
+  for (int k = tid; k < nblk * kBS + 2 * nS + NW * nf * kPoseSums; k += TP) sS[k] = (Real)0;
   if (tid == 0) sFlag[0] = 0;
   __syncthreads();
 
@@ -704,9 +707,11 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     int4 nrec = make_int4(0, 0, 0, -1);
     if (t + 1 < t1 && tid < nta.y) nrec = prec[nta.x + tid];
 
-    // ---- phase 3: Z_bar = W L^-T |D|^-1/2 and the reduced rhs of this pair;
-    // then per-pose sums over adjacent lanes, added once per run
-    Real v[27];
+    // ---- phase 3: Z_bar = W L^-T |D|^-1/2 of this pair, its reduced rhs and
+    // its own diagonal Schur term U - Z_bar sigma Z_bar^T (the products of a
+    // pair with itself never enter the product lists), plus diag(U) for the
+    // damping; then per-pose sums over adjacent lanes, added once per run
+    Real v[kPoseSums];
     if (slot >= 0) {
       const Real* f = sLF + 12 * sPL[q];
       LDL3<Real> F;
@@ -722,29 +727,36 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
 #pragma unroll
       for (int k = 0; k < 3; ++k) sh[k] = f[6 + k] * f[9 + k];
       Real* Z = sPZ + kZS * q;
+      Real z[6][3];
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        Real z[3];
-        ldl3_half(F, A.W + 3 * r, z);
-        Z[ZR * r] = z[0];
-        Z[ZR * r + 1] = z[1];
-        Z[ZR * r + 2] = z[2];
+        ldl3_half(F, A.W + 3 * r, z[r]);
+        Z[ZR * r] = z[r][0];
+        Z[ZR * r + 1] = z[r][1];
+        Z[ZR * r + 2] = z[r][2];
         if (ZR == 4) Z[ZR * r + 3] = (Real)0;
-        v[21 + r] = (ADJ ? (Real)0 : -A.gp[r]) - (z[0] * sh[0] + z[1] * sh[1] + z[2] * sh[2]);
+        v[21 + r] = (ADJ ? (Real)0 : -A.gp[r]) - (z[r][0] * sh[0] + z[r][1] * sh[1] + z[r][2] * sh[2]);
       }
+      int e = 0;
 #pragma unroll
-      for (int k = 0; k < 21; ++k) v[k] = A.U[k];
+      for (int r = 0; r < 6; ++r) {
+        const Real zs0 = z[r][0] * F.sg[0], zs1 = z[r][1] * F.sg[1], zs2 = z[r][2] * F.sg[2];
+        v[27 + r] = A.U[e];   // diagonal entry (r, r)
+#pragma unroll
+        for (int c = r; c < 6; ++c, ++e)
+          v[e] = A.U[e] - (zs0 * z[c][0] + zs1 * z[c][1] + zs2 * z[c][2]);
+      }
     } else {
 #pragma unroll
-      for (int k = 0; k < 27; ++k) v[k] = (Real)0;
+      for (int k = 0; k < kPoseSums; ++k) v[k] = (Real)0;
     }
-    run_sums<Real, 27>(v, slot);
+    run_sums<Real, kPoseSums>(v, slot);
     {
       const int prev = __shfl_up(slot, 1, 64);
       if (slot >= 0 && (lane == 0 || prev != slot)) {
-        Real* dst = sUw + (wave * nf + slot) * 27;
+        Real* dst = sUw + (wave * nf + slot) * kPoseSums;
 #pragma unroll
-        for (int k = 0; k < 27; ++k) dst[k] += v[k];
+        for (int k = 0; k < kPoseSums; ++k) dst[k] += v[k];
       }
     }
     __syncthreads();
@@ -810,18 +822,19 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     rec = nrec;
   }
 
-  // ---- fold the per-wave pose sums into the partial: U (upper), rhs, diag(U)
-  for (int e = tid; e < nf * 27; e += TP) {
-    const int s = e / 27, k = e % 27;
+  // ---- fold the per-wave pose sums into the partial: U - Z sigma Z^T (upper
+  // triangle of the diagonal blocks), rhs, diag(U)
+  for (int e = tid; e < nf * kPoseSums; e += TP) {
+    const int s = e / kPoseSums, k = e % kPoseSums;
     Real sum = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) sum += sUw[(w * nf + s) * 27 + k];
+    for (int w = 0; w < NW; ++w) sum += sUw[(w * nf + s) * kPoseSums + k];
     if (k < 21) {
-      const int off = kUpperOff[k];
-      sS[kBS * blk_index(s, s, nf) + off] += sum;
-      if (!ADJ && off % 7 == 0) sD[6 * s + off / 7] += sum;
-    } else {
+      sS[kBS * blk_index(s, s, nf) + kUpperOff[k]] += sum;
+    } else if (k < 27) {
       sB[6 * s + (k - 21)] += sum;
+    } else if (!ADJ) {
+      sD[6 * s + (k - 27)] += sum;
     }
   }
   __syncthreads();

@@ -225,7 +225,7 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
         const int32_t q0 = w.lm_pair_begin[l] - p0;
         const int nfp = w.lm_nfree[l];
         for (int a = 0; a < nfp; ++a)
-          for (int b = a; b < nfp; ++b) {
+          for (int b = a + 1; b < nfp; ++b) {   // (a, a) is summed per pair in the kernels
             const int sa = w.free_slot[w.pair_pose[p0 + q0 + a]];
             const int sb = w.free_slot[w.pair_pose[p0 + q0 + b]];
             const int blk = sa * w.n_free - (sa * (sa - 1)) / 2 + (sb - sa);

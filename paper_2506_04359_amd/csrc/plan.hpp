@@ -82,8 +82,9 @@ struct LaunchTables {
   // Per tile: {first pair, pairs, first landmark, landmarks, first list word,
   // segments, products, 0}, batch-global.
   std::vector<int32_t> tile_rec;         // 8 per tile
-  // Per tile, the Schur products (a, b) of pairs of one landmark (a <= b,
-  // both free) grouped by their target block of S: segments of
+  // Per tile, the Schur products (a, b) of pairs of one landmark (a < b,
+  // both free; a pair's product with itself is summed per pose instead)
+  // grouped by their off-diagonal target block of S: segments of
   // (target block, first product, count), longest first.
   // Stored per tile as one word stream: nseg segment words
   // (blk | start << 10 | len << 23), then the products two per word
