@@ -765,20 +765,37 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     // target block for this tile: it sums -Z_a[r] sigma Z_b^T over the
     // segment's products in registers and updates the partial once.
     const uint16_t* sProd = reinterpret_cast<const uint16_t*>(sLst + nseg);
-    for (int u = tid; u < nseg * 6; u += TP) {
-      const uint32_t word = sLst[u / 6];
+    // Software-pipelined: the next unit's segment word and the next product
+    // pair are in flight while the current products are summed, so one LDS
+    // round trip (the Z rows) remains per pair of products.
+    const int nun = nseg * 6;
+    uint32_t word = tid < nun ? sLst[tid / 6] : 0u;
+    for (int u = tid; u < nun; u += TP) {
+      const int un = u + TP;
+      const uint32_t wnext = un < nun ? sLst[un / 6] : 0u;
       const int r = u % 6;
       const int blk = word & 1023, start = (word >> 10) & 8191, len = word >> 23;
+      const int kend = start + len;   // len >= 1: only non-empty segments are listed
       Real acc[6] = {0, 0, 0, 0, 0, 0}, acd[6] = {0, 0, 0, 0, 0, 0};
+      uint32_t pa = sProd[start], pb = start + 1 < kend ? sProd[start + 1] : 0u;
       int k = start;
-      const int kend = start + len;
       for (; k + 1 < kend; k += 2) {
-        const uint32_t pa = sProd[k], pb = sProd[k + 1];
         const int qa0 = pa & 255, qc0 = pa >> 8, qa1 = pb & 255, qc1 = pb >> 8;
         const Real* Za0 = sPZ + kZS * qa0 + ZR * r;
         const Real* Za1 = sPZ + kZS * qa1 + ZR * r;
+        const Real* Zc0 = sPZ + kZS * qc0;
+        const Real* Zc1 = sPZ + kZS * qc1;
         Real a0 = Za0[0], a1 = Za0[1], a2 = Za0[2];
         Real b0 = Za1[0], b1 = Za1[1], b2 = Za1[2];
+        Real z0[6][3], z1[6][3];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            z0[c][m] = Zc0[ZR * c + m];
+            z1[c][m] = Zc1[ZR * c + m];
+          }
+        }
         if (ADJ) {
           const Real* g0 = sLF + 12 * sPL[qa0] + 6;
           const Real* g1 = sLF + 12 * sPL[qa1] + 6;
@@ -789,16 +806,17 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
           b1 *= g1[1];
           b2 *= g1[2];
         }
-        const Real* Zc0 = sPZ + kZS * qc0;
-        const Real* Zc1 = sPZ + kZS * qc1;
+        if (k + 2 < kend) {   // next pair, in flight during the sums below
+          pa = sProd[k + 2];
+          pb = k + 3 < kend ? sProd[k + 3] : 0u;
+        }
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          acc[c] += a0 * Zc0[ZR * c] + a1 * Zc0[ZR * c + 1] + a2 * Zc0[ZR * c + 2];
-          acd[c] += b0 * Zc1[ZR * c] + b1 * Zc1[ZR * c + 1] + b2 * Zc1[ZR * c + 2];
+          acc[c] += a0 * z0[c][0] + a1 * z0[c][1] + a2 * z0[c][2];
+          acd[c] += b0 * z1[c][0] + b1 * z1[c][1] + b2 * z1[c][2];
         }
       }
       if (k < kend) {
-        const uint32_t pa = sProd[k];
         const int qa0 = pa & 255, qc0 = pa >> 8;
         const Real* Za0 = sPZ + kZS * qa0 + ZR * r;
         Real a0 = Za0[0], a1 = Za0[1], a2 = Za0[2];
@@ -815,6 +833,7 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       Real* row = sS + kBS * blk + 6 * r;
 #pragma unroll
       for (int c = 0; c < 6; ++c) row[c] -= acc[c] + acd[c];
+      word = wnext;
     }
     __syncthreads();
     ta = nta;
