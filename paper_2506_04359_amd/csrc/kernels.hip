@@ -470,21 +470,50 @@ __global__ void k_pack(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U) {
 // pass A: linearise + per-landmark elimination + chunk partial of S
 // ---------------------------------------------------------------------------
 
-// Suffix sums of v[0..N) over runs of lanes with equal key inside a wave: after
-// the call the first lane of each run holds the run's total.
+// Lane shift by DPP (row_shr:n within rows of 16 lanes, row_bcast:15 / :31
+// across rows) of a 32- or 64-bit value; lanes outside ROWMASK or without a
+// source lane read `old`.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_r(float x) {
+  return __int_as_float(dpp_i<CTRL, ROWMASK>(0, __float_as_int(x)));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_r(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i<CTRL, ROWMASK>(0, (int)(b & 0xffffffffll));
+  const int hi = dpp_i<CTRL, ROWMASK>(0, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One step of the segmented scan: v += (value of the source lane) where the
+// source lane carries the same key.
+template <typename Real, int N, int CTRL, int ROWMASK>
+__device__ __forceinline__ void run_step(Real* v, int key) {
+  const int k2 = dpp_i<CTRL, ROWMASK>(-2, key);
+  const bool ok = k2 == key;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const Real t = dpp_r<CTRL, ROWMASK>(v[i]);
+    if (ok) v[i] += t;
+  }
+}
+
+// Inclusive prefix sums of v[0..N) over runs of lanes with equal key inside a
+// wave (runs are contiguous: keys are sorted within the wave): after the call
+// the last lane of each run holds the run's total.  DPP only (no LDS): four
+// in-row shifts, then the two row broadcasts that carry a run across rows.
 template <typename Real, int N>
 __device__ __forceinline__ void run_sums(Real* v, int key) {
-  const int lane = threadIdx.x & 63;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int k2 = __shfl_down(key, off, 64);
-    const bool ok = (lane + off < 64) && (k2 == key);
-    if (!__any(ok)) break;   // no run in this wave is longer than off
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const Real u = __shfl_down(v[i], off, 64);
-      if (ok) v[i] += u;
-    }
-  }
+  run_step<Real, N, 0x111, 0xf>(v, key);   // row_shr:1
+  run_step<Real, N, 0x112, 0xf>(v, key);   // row_shr:2
+  run_step<Real, N, 0x114, 0xf>(v, key);   // row_shr:4
+  run_step<Real, N, 0x118, 0xf>(v, key);   // row_shr:8
+  run_step<Real, N, 0x142, 0xa>(v, key);   // row_bcast:15 into rows 1 and 3
+  run_step<Real, N, 0x143, 0xc>(v, key);   // row_bcast:31 into rows 2 and 3
 }
 
 // Per-pose sums of pass A: U - Z sigma Z^T (21, upper), reduced rhs (6), diag(U) (6).
@@ -752,8 +781,8 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     }
     run_sums<Real, kPoseSums>(v, slot);
     {
-      const int prev = __shfl_up(slot, 1, 64);
-      if (slot >= 0 && (lane == 0 || prev != slot)) {
+      const int next = __shfl_down(slot, 1, 64);
+      if (slot >= 0 && (lane == 63 || next != slot)) {
         Real* dst = sUw + (wave * nf + slot) * kPoseSums;
 #pragma unroll
         for (int k = 0; k < kPoseSums; ++k) dst[k] += v[k];
