@@ -516,6 +516,15 @@ __device__ __forceinline__ void run_sums(Real* v, int key) {
   run_step<Real, N, 0x143, 0xc>(v, key);   // row_bcast:31 into rows 2 and 3
 }
 
+// Rows of one target block per Schur work unit in pass A (1, 2, 3 or 6): three
+// rows read 9 Z rows per product for 54 FMAs and keep enough units per tile to
+// balance the threads.
+#ifndef BA_ROWS_PER_UNIT
+#define BA_ROWS_PER_UNIT 3
+#endif
+constexpr int kRowsPerUnit = BA_ROWS_PER_UNIT;
+static_assert(6 % kRowsPerUnit == 0, "rows per unit must divide 6");
+
 // Per-pose sums of pass A: U - Z sigma Z^T (21, upper), reduced rhs (6), diag(U) (6).
 constexpr int kPoseSums = 33;
 
@@ -790,79 +799,56 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     }
     __syncthreads();
 
-    // ---- phase 4: Schur blocks.  Unit (segment, row r) owns row r of one
-    // target block for this tile: it sums -Z_a[r] sigma Z_b^T over the
-    // segment's products in registers and updates the partial once.
+    // ---- phase 4: Schur blocks.  Unit (segment, rows r0..r0+kRowsPerUnit-1)
+    // owns those rows of one off-diagonal target block for this tile: it sums
+    // -Z_a[r] sigma Z_c^T over the segment's products in registers and
+    // updates its rows of the partial once.
     const uint16_t* sProd = reinterpret_cast<const uint16_t*>(sLst + nseg);
-    // Software-pipelined: the next unit's segment word and the next product
-    // pair are in flight while the current products are summed, so one LDS
-    // round trip (the Z rows) remains per pair of products.
-    const int nun = nseg * 6;
-    uint32_t word = tid < nun ? sLst[tid / 6] : 0u;
-    for (int u = tid; u < nun; u += TP) {
-      const int un = u + TP;
-      const uint32_t wnext = un < nun ? sLst[un / 6] : 0u;
-      const int r = u % 6;
-      const int blk = word & 1023, start = (word >> 10) & 8191, len = word >> 23;
-      const int kend = start + len;   // len >= 1: only non-empty segments are listed
-      Real acc[6] = {0, 0, 0, 0, 0, 0}, acd[6] = {0, 0, 0, 0, 0, 0};
-      uint32_t pa = sProd[start], pb = start + 1 < kend ? sProd[start + 1] : 0u;
-      int k = start;
-      for (; k + 1 < kend; k += 2) {
-        const int qa0 = pa & 255, qc0 = pa >> 8, qa1 = pb & 255, qc1 = pb >> 8;
-        const Real* Za0 = sPZ + kZS * qa0 + ZR * r;
-        const Real* Za1 = sPZ + kZS * qa1 + ZR * r;
-        const Real* Zc0 = sPZ + kZS * qc0;
-        const Real* Zc1 = sPZ + kZS * qc1;
-        Real a0 = Za0[0], a1 = Za0[1], a2 = Za0[2];
-        Real b0 = Za1[0], b1 = Za1[1], b2 = Za1[2];
-        Real z0[6][3], z1[6][3];
+    {
+      constexpr int RG = kRowsPerUnit, UPS = 6 / RG;
+      const int nun = nseg * UPS;
+      for (int u = tid; u < nun; u += TP) {
+        const uint32_t wd = sLst[u / UPS];
+        const int r0 = (u % UPS) * RG;
+        const int blk = wd & 1023, start = (wd >> 10) & 8191, len = wd >> 23;
+        Real acc[RG][6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
+        for (int i = 0; i < RG; ++i)
 #pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            z0[c][m] = Zc0[ZR * c + m];
-            z1[c][m] = Zc1[ZR * c + m];
+          for (int c = 0; c < 6; ++c) acc[i][c] = (Real)0;
+        for (int k = start; k < start + len; ++k) {
+          const uint32_t pp = sProd[k];
+          const int qa = pp & 255, qc = pp >> 8;
+          const Real* Za = sPZ + kZS * qa + ZR * r0;
+          const Real* Zc = sPZ + kZS * qc;
+          Real a[RG][3], z[6][3];
+#pragma unroll
+          for (int i = 0; i < RG; ++i)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) a[i][m] = Za[ZR * i + m];
+#pragma unroll
+          for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) z[c][m] = Zc[ZR * c + m];
+          if (ADJ) {
+            const Real* g = sLF + 12 * sPL[qa] + 6;
+#pragma unroll
+            for (int i = 0; i < RG; ++i)
+#pragma unroll
+              for (int m = 0; m < 3; ++m) a[i][m] *= g[m];
           }
-        }
-        if (ADJ) {
-          const Real* g0 = sLF + 12 * sPL[qa0] + 6;
-          const Real* g1 = sLF + 12 * sPL[qa1] + 6;
-          a0 *= g0[0];
-          a1 *= g0[1];
-          a2 *= g0[2];
-          b0 *= g1[0];
-          b1 *= g1[1];
-          b2 *= g1[2];
-        }
-        if (k + 2 < kend) {   // next pair, in flight during the sums below
-          pa = sProd[k + 2];
-          pb = k + 3 < kend ? sProd[k + 3] : 0u;
-        }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          acc[c] += a0 * z0[c][0] + a1 * z0[c][1] + a2 * z0[c][2];
-          acd[c] += b0 * z1[c][0] + b1 * z1[c][1] + b2 * z1[c][2];
+          for (int i = 0; i < RG; ++i)
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+              acc[i][c] += a[i][0] * z[c][0] + a[i][1] * z[c][1] + a[i][2] * z[c][2];
         }
+        Real* B = sS + kBS * blk + 6 * r0;
+#pragma unroll
+        for (int i = 0; i < RG; ++i)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) B[6 * i + c] -= acc[i][c];
       }
-      if (k < kend) {
-        const int qa0 = pa & 255, qc0 = pa >> 8;
-        const Real* Za0 = sPZ + kZS * qa0 + ZR * r;
-        Real a0 = Za0[0], a1 = Za0[1], a2 = Za0[2];
-        if (ADJ) {
-          const Real* g0 = sLF + 12 * sPL[qa0] + 6;
-          a0 *= g0[0];
-          a1 *= g0[1];
-          a2 *= g0[2];
-        }
-        const Real* Zc0 = sPZ + kZS * qc0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += a0 * Zc0[ZR * c] + a1 * Zc0[ZR * c + 1] + a2 * Zc0[ZR * c + 2];
-      }
-      Real* row = sS + kBS * blk + 6 * r;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) row[c] -= acc[c] + acd[c];
-      word = wnext;
     }
     __syncthreads();
     ta = nta;
@@ -1296,10 +1282,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
   double* sRed = sLP + 3 * TP;                     // 16
   int* sFree = reinterpret_cast<int*>(sRed + 16);  // 64
   int* sFlag = sFree + 64;                         // 4
-  int* sPS = sFlag + 4;                            // TP
-  int* sPL = sPS + TP;                             // TP
-  Real* sPW = reinterpret_cast<Real*>(sPL + TP);   // TP * 18
-  Real* sPV = sPW + TP * 18;                       // TP * 12
+  Real* sPV = reinterpret_cast<Real*>(sFlag + 4);  // TP * 12: V, g, W^T dp per pair
 
   load_window(P, W, poses, sPose, sCam, sFree);
   if (!ADJ)
@@ -1310,19 +1293,26 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
 
   double cost = 0.0;
   const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
+  const int4* trec = reinterpret_cast<const int4*>(T.tile_rec);
+  const int4* prec = reinterpret_cast<const int4*>(T.pair_rec);
+  int4 ta = make_int4(0, 0, 0, 0);
+  int4 rec = make_int4(0, 0, 0, -1);
+  if (t0 < t1) {
+    ta = trec[2 * t0];
+    if (tid < ta.y) rec = prec[ta.x + tid];
+  }
   for (int t = t0; t < t1; ++t) {
-    const int l0 = T.tile_lm_begin[t], l1 = T.tile_lm_begin[t + 1];
-    const int p0 = P.lm_pair_begin[l0], p1 = P.lm_pair_begin[l1];
-    const int nP = p1 - p0, nL = l1 - l0;
+    // the tile's pairs in the plan's thread order; q is the pair's index in
+    // landmark order (the layout of the per-pair LDS rows)
+    const int p0 = ta.x, nP = ta.y, l0 = ta.z, nL = ta.w;
+    const int q = (rec.z >> 8) & 255, pose = rec.z & 255, nobs = rec.z >> 16;
+    const int slot = rec.w, o0 = rec.x, lm = rec.y;
+    const int j = lm - l0;
+    int4 nta = ta;
+    if (t + 1 < t1) nta = trec[2 * (t + 1)];
 
     // ---- phase 1: per pair: W, V, g at the current state and W^T dp
     if (tid < nP) {
-      const int gp = p0 + tid;
-      const int lm = P.pair_lm[gp];
-      const int pose = P.pair_pose[gp];
-      const int slot = sFree[pose];
-      sPS[tid] = slot;
-      sPL[tid] = lm - l0;
       const double* Rt = sPose + 12 * pose;
       const double* pt = points + 3 * (lm - W.point_off);
       double xb[3];
@@ -1336,8 +1326,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
         for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
       PairAcc<Real> A;
       pair_zero(A);
-      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
-      for (int o = o0; o < o1; ++o) {
+      for (int o = o0; o < o0 + nobs; ++o) {
         const double* C = sCam + 16 * P.obs_cam[o];
         const double wo = K.w ? (double)K.w[o] : 1.0;
         const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
@@ -1353,21 +1342,21 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
           wtd[c] = (Real)v;
         }
       }
-      for (int k = 0; k < 6; ++k) sPV[12 * tid + k] = A.V[k];
-      for (int k = 0; k < 3; ++k) sPV[12 * tid + 6 + k] = A.gl[k];
-      for (int k = 0; k < 3; ++k) sPV[12 * tid + 9 + k] = wtd[k];
+      for (int k = 0; k < 6; ++k) sPV[12 * q + k] = A.V[k];
+      for (int k = 0; k < 3; ++k) sPV[12 * q + 6 + k] = A.gl[k];
+      for (int k = 0; k < 3; ++k) sPV[12 * q + 9 + k] = wtd[k];
     }
     __syncthreads();
 
     // ---- phase 2: per landmark: dl = V*^-1 (c_l - sum W^T dp)
     if (tid < nL) {
-      const int lm = l0 + tid;
-      const int q0 = P.lm_pair_begin[lm] - p0, q1 = P.lm_pair_begin[lm + 1] - p0;
+      const int lmt = l0 + tid;
+      const int q0 = P.lm_pair_begin[lmt] - p0, q1 = P.lm_pair_begin[lmt + 1] - p0;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0}, s3[3] = {0, 0, 0};
-      for (int q = q0; q < q1; ++q) {
-        for (int k = 0; k < 6; ++k) V[k] += sPV[12 * q + k];
-        for (int k = 0; k < 3; ++k) g[k] += sPV[12 * q + 6 + k];
-        for (int k = 0; k < 3; ++k) s3[k] += sPV[12 * q + 9 + k];
+      for (int qq = q0; qq < q1; ++qq) {
+        for (int k = 0; k < 6; ++k) V[k] += sPV[12 * qq + k];
+        for (int k = 0; k < 3; ++k) g[k] += sPV[12 * qq + 6 + k];
+        for (int k = 0; k < 3; ++k) s3[k] += sPV[12 * qq + 9 + k];
       }
       Real c[3];
       if (!ADJ) {
@@ -1375,15 +1364,15 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
         for (int k = 0; k < 3; ++k) c[k] = -g[k] - s3[k];
       } else {
         for (int k = 0; k < 3; ++k)
-          c[k] = (U.grad_points ? (Real)U.grad_points[3 * lm + k] : (Real)0) - s3[k];
+          c[k] = (U.grad_points ? (Real)U.grad_points[3 * lmt + k] : (Real)0) - s3[k];
       }
       LDL3<Real> F;
       ldl3(V, !ADJ, F);
       Real x[3];
       ldl3_solve(F, c, x);
-      const double* pt = points + 3 * (lm - W.point_off);
+      const double* pt = points + 3 * (lmt - W.point_off);
       if (!ADJ) {
-        double* cp = cpoints + 3 * (lm - W.point_off);
+        double* cp = cpoints + 3 * (lmt - W.point_off);
         for (int k = 0; k < 3; ++k) {
           const double v = pt[k] + (double)x[k];
           sLP[3 * tid + k] = v;
@@ -1393,35 +1382,33 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
         for (int k = 0; k < 3; ++k) sLP[3 * tid + k] = (double)x[k];
       }
     }
+    // next tile's pair records (its tile record has arrived by now)
+    int4 nrec = make_int4(0, 0, 0, -1);
+    if (t + 1 < t1 && tid < nta.y) nrec = prec[nta.x + tid];
     __syncthreads();
 
     // ---- phase 3: per pair: candidate cost (LM) / per-observation gradients (ADJ)
     if (tid < nP) {
-      const int gp = p0 + tid;
-      const int pose = P.pair_pose[gp];
-      const int j = sPL[tid];
-      const int o0 = P.pair_obs_begin[gp], o1 = P.pair_obs_begin[gp + 1];
       if (!ADJ) {
         const double* Rt = sPoseC + 12 * pose;
         const double* pt = sLP + 3 * j;
         double xb[3];
         for (int a = 0; a < 3; ++a)
           xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
-        for (int o = o0; o < o1; ++o) {
+        for (int o = o0; o < o0 + nobs; ++o) {
           const double* C = sCam + 16 * P.obs_cam[o];
           const double X = C[4] * xb[0] + C[5] * xb[1] + C[6] * xb[2] + C[13];
           const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
           const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
           if (!(Z > S.min_depth)) sFlag[0] = 1;
-          const double r0 = C[0] * X / Z - (double)K.du[o];
-          const double r1 = C[1] * Y / Z - (double)K.dv[o];
+          const double iz = 1.0 / Z;
+          const double r0 = C[0] * X * iz - (double)K.du[o];
+          const double r1 = C[1] * Y * iz - (double)K.dv[o];
           double rho, d1, d2;
           huber(r0 * r0 + r1 * r1, S.huber_delta, rho, d1, d2);
           cost += (K.w ? (double)K.w[o] : 1.0) * rho;
         }
       } else {
-        const int lm = P.pair_lm[gp];
-        const int slot = sPS[tid];
         const double* Rt = sPose + 12 * pose;
         const double* pt = points + 3 * (lm - W.point_off);
         double xb[3];
@@ -1441,7 +1428,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
         pc[2] = ap[3] * xb[1] - ap[4] * xb[0];
         double v3[3];
         for (int a = 0; a < 3; ++a) v3[a] = ap[a] + pc[a] + Ral[a];
-        for (int o = o0; o < o1; ++o) {
+        for (int o = o0; o < o0 + nobs; ++o) {
           const double* C = sCam + 16 * P.obs_cam[o];
           const double wo = K.w ? (double)K.w[o] : 1.0;
           const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
@@ -1458,6 +1445,8 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
       }
     }
     __syncthreads();
+    ta = nta;
+    rec = nrec;
   }
   if (!ADJ) {
     const double tot = block_sum<TP>(cost, sRed);
@@ -1566,7 +1555,7 @@ size_t pass_a_lds(int np, int nc, int nf, int list_bytes) {
 template <typename Real, int TP>
 size_t pass_b_lds() {
   return (2 * ChunkLds::kPose + ChunkLds::kCam + kDpStride + 3 * TP + 16) * sizeof(double) +
-         (64 + 4 + 2 * TP) * sizeof(int) + (size_t)TP * (18 + 12) * sizeof(Real);
+         (64 + 4) * sizeof(int) + (size_t)TP * 12 * sizeof(Real);
 }
 
 // The reduce kernel's LDS: the reduced system of the largest window.
