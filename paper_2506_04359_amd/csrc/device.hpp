@@ -91,7 +91,7 @@ struct DevSettings {
 };
 
 constexpr int kDpStride = 192;
-constexpr int kSumSlice = 2048;   // entries of the summed system per workgroup of k_sum
+constexpr int kSumSlice = 1024;   // entries of the summed system per workgroup of k_sum
 constexpr int kSumSlices = (528 * kBS + 12 * 32 + kSumSlice - 1) / kSumSlice;
 
 // Dimensions of the window caches in LDS (largest in the launch).

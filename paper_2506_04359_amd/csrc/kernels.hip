@@ -959,8 +959,9 @@ __device__ __forceinline__ void upper_pair(int e, int n, int& i, int& j) {
 }
 
 // Sum of a window's chunk partials in FP64, in chunk order.  Grid: (window,
-// slice of kSumSlice entries); every thread keeps 8 entries and 16 loads in
-// flight, so the sum runs at memory speed instead of one workgroup per window.
+// slice of kSumSlice entries); every thread keeps 4 entries and reads four
+// chunks per step (16 loads in flight), so the sum runs at memory speed
+// instead of one workgroup per window.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_sum(DevPlan P, DevTiles T, DevWork<Real> K) {
   const int wi = blockIdx.x;
@@ -974,20 +975,22 @@ __global__ __launch_bounds__(256) void k_sum(DevPlan P, DevTiles T, DevWork<Real
 #pragma unroll
   for (int k = 0; k < E; ++k) acc[k] = 0.0;
   int c = W.chunk_begin;
-  for (; c + 1 < W.chunk_end; c += 2) {
-    const Real* a = K.part + T.chunk_part_off[c];
-    const Real* b = K.part + T.chunk_part_off[c + 1];
-    Real va[E], vb[E];
+  for (; c + 3 < W.chunk_end; c += 4) {
+    Real v[4][E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const int e = e0 + threadIdx.x + 256 * k;
-      va[k] = e < ne ? a[e] : (Real)0;
-      vb[k] = e < ne ? b[e] : (Real)0;
+    for (int j = 0; j < 4; ++j) {
+      const Real* a = K.part + T.chunk_part_off[c + j];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int e = e0 + threadIdx.x + 256 * k;
+        v[j][k] = e < ne ? a[e] : (Real)0;
+      }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) acc[k] += (double)va[k] + (double)vb[k];
+    for (int k = 0; k < E; ++k)
+      acc[k] += (((double)v[0][k] + (double)v[1][k]) + (double)v[2][k]) + (double)v[3][k];
   }
-  if (c < W.chunk_end) {
+  for (; c < W.chunk_end; ++c) {
     const Real* a = K.part + T.chunk_part_off[c];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -1020,12 +1023,26 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   const int c0 = W.chunk_begin, c1 = W.chunk_end;
   const int ne = nblk * kBS + 2 * nS;
   if (tid == 0) {
+    // chunk flags and costs, eight loads in flight, summed in chunk order
+    const bool need_cost = !ADJ && it == 0;
     int f = 0;
-    for (int c = c0; c < c1; ++c) f |= K.part_flag_a[c];
+    double F = 0.0;
+    for (int c = c0; c < c1; c += 8) {
+      int fl[8];
+      double cs[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        fl[b] = c + b < c1 ? K.part_flag_a[c + b] : 0;
+        cs[b] = need_cost && c + b < c1 ? K.part_cost_a[c + b] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        f |= fl[b];
+        F += cs[b];
+      }
+    }
     sFail[0] = f;
-    if (!ADJ && it == 0) {
-      double F = 0.0;
-      for (int c = c0; c < c1; ++c) F += K.part_cost_a[c];
+    if (need_cost) {
       F *= 0.5;
       st.cost = F;
       st.init_cost = F;
@@ -1033,8 +1050,22 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     }
   }
   {
+    // eight loads in flight per thread (the system is up to 160 KB)
     const double* src = K.ssum + W.sum_off;
-    for (int e = tid; e < ne; e += NT) sS[e] = src[e];
+    constexpr int B = 8;
+    for (int base = 0; base < ne; base += B * NT) {
+      double v[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int e = base + tid + b * NT;
+        v[b] = e < ne ? src[e] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int e = base + tid + b * NT;
+        if (e < ne) sS[e] = v[b];
+      }
+    }
   }
   __syncthreads();
   const double lam = st.lambda;
@@ -1480,9 +1511,19 @@ __global__ void k_accept(DevPlan P, DevWork<Real> K, DevUser U, DevSettings S, i
   } else {
     int depth = 0;
     double F = 0.0;
-    for (int c = W.chunk_begin; c < W.chunk_end; ++c) {
-      depth |= K.part_flag_b[c];
-      F += K.part_cost_b[c];
+    for (int c = W.chunk_begin; c < W.chunk_end; c += 8) {   // eight loads in flight, chunk order
+      int fl[8];
+      double cs[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        fl[b] = c + b < W.chunk_end ? K.part_flag_b[c + b] : 0;
+        cs[b] = c + b < W.chunk_end ? K.part_cost_b[c + b] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        depth |= fl[b];
+        F += cs[b];
+      }
     }
     if (depth) {
       tr.status = 2;
