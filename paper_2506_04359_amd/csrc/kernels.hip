@@ -922,24 +922,40 @@ __device__ __forceinline__ void exp_se3(const double* xi, double* T /*3x4*/) {
   }
 }
 
+// Value of a double in lane `src` (wave-uniform) to every lane, by readlane.
+__device__ __forceinline__ double wave_bcast(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Upper Cholesky of one symmetric 6x6 block spread over a wave: lane l < 36
 // holds entry (l / 6, l % 6).  Writes the upper triangle of R to D and 1 / R_pp
 // to inv; raises *fail on a non-positive or non-finite pivot.  Every lane of
-// the wave takes part (the pivots are broadcast by shuffles).
+// the wave takes part (pivots and pivot rows are broadcast by readlane).
 __device__ __forceinline__ void factor_diag(double a, double* D, double* inv, int* fail) {
   const int lane = threadIdx.x & 63;
   const int r = lane / 6, c = lane - 6 * (lane / 6);
 #pragma unroll
   for (int p = 0; p < 6; ++p) {
-    const double d = __shfl(a, 7 * p, 64);
+    const double d = wave_bcast(a, 7 * p);
     if (!(d > 0.0) || !isfinite(d)) {
       if (lane == 0) *fail = 1;
       return;
     }
-    const double s = sqrt(d), ir = 1.0 / s;
+    const double ir = rsqrt(d), s = d * ir;
     if (r == p) a = c == p ? s : a * ir;
-    const double rr = __shfl(a, 6 * p + r, 64);   // R[p][r]
-    const double rc = __shfl(a, 6 * p + c, 64);   // R[p][c]
+    // row p of R (its entries right of the pivot) to every lane
+    double rp[6];
+#pragma unroll
+    for (int x = p + 1; x < 6; ++x) rp[x] = wave_bcast(a, 6 * p + x);
+    double rr = 0.0, rc = 0.0;   // R[p][r], R[p][c]
+#pragma unroll
+    for (int x = p + 1; x < 6; ++x) {
+      if (r == x) rr = rp[x];
+      if (c == x) rc = rp[x];
+    }
     if (r > p && c > p) a -= rr * rc;
     if (lane == p) inv[p] = ir;
   }
@@ -1224,7 +1240,7 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
         const int row = 6 * k + i;
         const int sel = row >> 6;
         const double own = sel == 0 ? y0 : (sel == 1 ? y1 : y2);
-        double v = __shfl(own, row & 63, 64);
+        double v = wave_bcast(own, row & 63);
 #pragma unroll
         for (int m = i + 1; m < 6; ++m) v -= Dk[6 * i + m] * x[m];
         x[i] = v * sInv[row];
