@@ -42,11 +42,9 @@
  * to the device-resident ba_report of each window.
  *
  * Limits of this implementation (checked at plan creation):
- *   n_poses <= 64 per window, n_cams <= 32, free poses <= 32 per window.
- *   In BA_FP64 a window's reduced system and pose cache share the 160 KB of
- *   LDS: at most 29 free poses (with up to 40 poses in the window) or 28 free
- *   poses (up to 64 poses).  These two are reported by ba_workspace_size and
- *   the solve calls as BA_ERR_UNSUPPORTED;
+ *   n_poses <= 64 per window, n_cams <= 32, free poses <= 32 per window
+ *   (<= 29 in BA_FP64, whose reduced system takes the 160 KB of LDS; reported
+ *   by ba_workspace_size and the solve calls as BA_ERR_UNSUPPORTED),
  *   every landmark observed from >= 2 distinct (pose, camera) views,
  *   observations per landmark <= 4096, < 2^30 observations per batch.
  */

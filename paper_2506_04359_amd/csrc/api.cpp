@@ -23,7 +23,7 @@ namespace ba {
 
 // defined in kernels.hip
 template <typename Real, int TP>
-size_t pass_a_lds(int np, int nc, int nf, int list_bytes);
+size_t pass_a_lds(int np, int nc, int nf, int list_bytes, bool adj);
 template <typename Real, int TP>
 size_t pass_b_lds();
 size_t reduce_lds(int max_nf);
@@ -290,10 +290,10 @@ ba_status pick_config(const ba_batch_s* b, int precision, int* which) {
   auto fits = [&](int w) {
     const DeviceTables& t = b->tables[w];
     const size_t la = precision == BA_FP64
-                          ? (t.tp == kTileLarge ? pass_a_lds<double, kTileLarge>(b->max_np, b->max_nc, nf, t.list_bytes)
-                                                : pass_a_lds<double, kTileSmall>(b->max_np, b->max_nc, nf, t.list_bytes))
-                          : (t.tp == kTileLarge ? pass_a_lds<float, kTileLarge>(b->max_np, b->max_nc, nf, t.list_bytes)
-                                                : pass_a_lds<float, kTileSmall>(b->max_np, b->max_nc, nf, t.list_bytes));
+                          ? (t.tp == kTileLarge ? pass_a_lds<double, kTileLarge>(b->max_np, b->max_nc, nf, t.list_bytes, true)
+                                                : pass_a_lds<double, kTileSmall>(b->max_np, b->max_nc, nf, t.list_bytes, true))
+                          : (t.tp == kTileLarge ? pass_a_lds<float, kTileLarge>(b->max_np, b->max_nc, nf, t.list_bytes, true)
+                                                : pass_a_lds<float, kTileSmall>(b->max_np, b->max_nc, nf, t.list_bytes, true));
     const size_t lb = precision == BA_FP64
                           ? (t.tp == kTileLarge ? pass_b_lds<double, kTileLarge>() : pass_b_lds<double, kTileSmall>())
                           : (t.tp == kTileLarge ? pass_b_lds<float, kTileLarge>() : pass_b_lds<float, kTileSmall>());

@@ -531,6 +531,36 @@ constexpr int kPoseSums = 33;
 // Upper-triangle entry e (0..20) of a 6x6 block -> row-major offset r*6+c.
 __constant__ int kUpperOff[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
                                   21, 22, 23, 28, 29, 35};
+constexpr int kUpperOffC[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
+                                21, 22, 23, 28, 29, 35};
+
+// Adds component k of a pose's run sum into the partial: U - Z sigma Z^T
+// (upper triangle of the diagonal block), reduced rhs, diag(U) (LM only).
+template <typename Real, bool ADJ>
+__device__ __forceinline__ void pose_sum_add1(Real* sS, Real* sB, Real* sD, int nf, int s, int k,
+                                              Real x) {
+  if (k < 21) {
+    sS[kBS * blk_index(s, s, nf) + kUpperOff[k]] += x;
+  } else if (k < 27) {
+    sB[6 * s + (k - 21)] += x;
+  } else if (!ADJ) {
+    sD[6 * s + (k - 27)] += x;
+  }
+}
+
+template <typename Real, bool ADJ>
+__device__ __forceinline__ void pose_sums_add(Real* sS, Real* sB, Real* sD, int nf, int s,
+                                              const Real* v) {
+  Real* D = sS + kBS * blk_index(s, s, nf);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) D[kUpperOffC[k]] += v[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sB[6 * s + k] += v[21 + k];
+  if (!ADJ) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sD[6 * s + k] += v[27 + k];
+  }
+}
 
 // Stored row stride of a pair's Z_bar (6 rows of 3): padded to 4 in FP32 so a
 // row is one 16-byte LDS read; unpadded in FP64, where LDS is the constraint.
@@ -547,17 +577,19 @@ struct ListRegs {
   static constexpr int N = TP >= 256 ? 12 : 16;
 };
 
-// LDS carve of pass A.  Window caches and the reduced-system partial are sized
-// by the launch's largest window; the per-tile buffers by TP.
+// LDS carve of pass A.  The camera table and the reduced-system partial are
+// sized by the launch's largest window; the per-tile buffers by TP (a tile
+// holds at most TP / 2 landmarks).  Poses are read from memory, not cached.
+// The pair -> landmark map is kept only for the adjoint's Schur units.
 template <typename Real, int TP>
 struct PassALds {
   static constexpr int NW = TP / 64;
-  static size_t bytes(int np, int nc, int nf, int list_bytes) {
+  static size_t bytes(int nc, int nf, int list_bytes, bool adj) {
     const size_t nblk = (size_t)nf * (nf + 1) / 2;
-    const size_t region = std::max<size_t>((size_t)TP * 9 * sizeof(Real), (size_t)list_bytes);
-    return (size_t)(np * 12 + nc * 16 + 16) * sizeof(double) + (64 + TP + 4) * sizeof(int) +
-           (nblk * kBS + 12 * (size_t)nf + (size_t)NW * nf * kPoseSums) * sizeof(Real) + 16 +
-           (size_t)TP * (ZRow<Real>::S + 12) * sizeof(Real) + (region + 15) / 16 * 16;
+    return (size_t)(nc * 16 + 16) * sizeof(double) + (64 + (adj ? TP : 0) + 4 + 8) * sizeof(int) +
+           (nblk * kBS + 12 * (size_t)nf + (size_t)2 * NW * kPoseSums) * sizeof(Real) + 16 +
+           ((size_t)TP * ZRow<Real>::S + (size_t)(TP / 2) * 12) * sizeof(Real) + 16 +
+           ((size_t)list_bytes + 15) / 16 * 16;
   }
 };
 
@@ -580,26 +612,25 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
   const double* points = (cur ? K.points_b : U.points) + 3 * W.point_off;
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
 
-  double* sPose = reinterpret_cast<double*>(smem);            // np * 12
-  double* sCam = sPose + D.np * 12;                           // nc * 16
+  double* sCam = reinterpret_cast<double*>(smem);             // nc * 16
   double* sRed = sCam + D.nc * 16;                            // 16
   int* sFree = reinterpret_cast<int*>(sRed + 16);             // 64
-  int* sPL = sFree + 64;                                      // TP: pair -> tile-local landmark
-  int* sFlag = sPL + TP;                                      // 4
-  Real* sS = reinterpret_cast<Real*>(sFlag + 4);              // nblk * kBS
+  int* sPL = sFree + 64;                                      // TP (adjoint): pair -> tile-local landmark
+  int* sFlag = sPL + (ADJ ? TP : 0);                          // 4
+  int* sBndSlot = sFlag + 4;                                  // 8: slot of each edge run (or -1)
+  Real* sS = reinterpret_cast<Real*>(sBndSlot + 8);           // nblk * kBS
   Real* sB = sS + nblk * kBS;                                 // nS
   Real* sD = sB + nS;                                         // nS
-  Real* sUw = sD + nS;                                        // NW * nf * kPoseSums
+  Real* sBnd = sD + nS;                                       // 2 * NW * kPoseSums: edge-run sums
   // 16-byte aligned carve by offsets from the LDS base (integer casts of the
   // pointers would lose the LDS address space and turn every access into a
   // flat one)
-  const int oPZ = ((int)(reinterpret_cast<unsigned char*>(sUw + NW * nf * kPoseSums) - smem) + 15) & ~15;
+  const int oPZ = ((int)(reinterpret_cast<unsigned char*>(sBnd + 2 * NW * kPoseSums) - smem) + 15) & ~15;
   Real* sPZ = reinterpret_cast<Real*>(smem + oPZ);           // TP * kZS
-  Real* sLF = sPZ + TP * kZS;                                 // TP * 12
-  const int oReg = ((int)(reinterpret_cast<unsigned char*>(sLF + TP * 12) - smem) + 15) & ~15;
-  unsigned char* sReg = smem + oReg;
-  Real* sPV = reinterpret_cast<Real*>(sReg);                  // TP * 9 (phases 1-2)
-  uint32_t* sLst = reinterpret_cast<uint32_t*>(sReg);         // product lists (phase 4)
+  Real* sPV = sPZ;                                            // TP * 9: V, g (phases 1-2, before Z)
+  Real* sLF = sPZ + TP * kZS;                                 // TP / 2 * 12: landmark factors
+  const int oLst = ((int)(reinterpret_cast<unsigned char*>(sLF + (TP / 2) * 12) - smem) + 15) & ~15;
+  uint32_t* sLst = reinterpret_cast<uint32_t*>(smem + oLst);  // product lists (stored in phase 1)
 
   const int4* trec = reinterpret_cast<const int4*>(T.tile_rec);
   const int4* prec = reinterpret_cast<const int4*>(T.pair_rec);
@@ -612,8 +643,9 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     if (tid < ta.y) rec = prec[ta.x + tid];
   }
 
-  load_window(P, W, poses, sPose, sCam, sFree);
-  for (int k = tid; k < nblk * kBS + 2 * nS + NW * nf * kPoseSums; k += TP) sS[k] = (Real)0;
+  for (int k = tid; k < W.n_cams * 16; k += TP) sCam[k] = P.cam[16 * W.cam_off + k];
+  for (int k = tid; k < W.n_poses; k += TP) sFree[k] = P.free_slot[W.pose_off + k];
+  for (int k = tid; k < nblk * kBS + 2 * nS; k += TP) sS[k] = (Real)0;
   if (tid == 0) sFlag[0] = 0;
   __syncthreads();
 
@@ -633,12 +665,16 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     const int slot = tid < nP ? rec.w : -1;
     const int o0 = rec.x, lm = rec.y;
     double px = 0, py = 0, pz = 0, du0 = 0, dv0 = 0, wo0 = 1;
+    double Rt[12];
     int cam0 = 0;
     if (tid < nP) {
       const double* pt = points + 3 * (lm - W.point_off);
       px = pt[0];
       py = pt[1];
       pz = pt[2];
+      const double* pp = poses + 12 * pose;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) Rt[k] = pp[k];
       cam0 = P.obs_cam[o0];
       du0 = (double)K.du[o0];
       dv0 = (double)K.dv[o0];
@@ -663,8 +699,7 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     PairAcc<Real> A;
     pair_zero(A);
     if (tid < nP) {
-      sPL[q] = lm - l0;
-      const double* Rt = sPose + 12 * pose;
+      if (ADJ) sPL[q] = lm - l0;
       double xb[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -692,6 +727,16 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       for (int k = 0; k < 6; ++k) sPV[9 * q + k] = A.V[k];
 #pragma unroll
       for (int k = 0; k < 3; ++k) sPV[9 * q + 6 + k] = A.gl[k];
+    }
+    // this tile's product lists (the previous tile's phase 4 has ended)
+    if (lregs) {
+#pragma unroll
+      for (int k = 0; k < LR; ++k) {
+        const int i = tid + k * TP;
+        if (i < nwords) sLst[i] = lwv[k];
+      }
+    } else {
+      for (int i = tid; i < nwords; i += TP) sLst[i] = T.lists[lw0 + i];
     }
     __syncthreads();
 
@@ -731,16 +776,6 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
       }
     }
     __syncthreads();
-    // the V region now holds this tile's product list
-    if (lregs) {
-#pragma unroll
-      for (int k = 0; k < LR; ++k) {
-        const int i = tid + k * TP;
-        if (i < nwords) sLst[i] = lwv[k];
-      }
-    } else {
-      for (int i = tid; i < nwords; i += TP) sLst[i] = T.lists[lw0 + i];
-    }
     // next tile's pair records (its tile record has arrived by now)
     int4 nrec = make_int4(0, 0, 0, -1);
     if (t + 1 < t1 && tid < nta.y) nrec = prec[nta.x + tid];
@@ -751,7 +786,7 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     // damping; then per-pose sums over adjacent lanes, added once per run
     Real v[kPoseSums];
     if (slot >= 0) {
-      const Real* f = sLF + 12 * sPL[q];
+      const Real* f = sLF + 12 * (lm - l0);
       LDL3<Real> F;
       F.l10 = f[0];
       F.l20 = f[1];
@@ -790,14 +825,42 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     }
     run_sums<Real, kPoseSums>(v, slot);
     {
+      // The last lane of each run holds the run's sum.  A run inside the wave
+      // is the only one of its pose in the tile (pairs are ordered by pose):
+      // it adds into the partial directly.  The runs holding lane 0 or lane 63
+      // may continue in the neighbouring waves: they go to this wave's two
+      // edge slots, folded in phase 4.
       const int next = __shfl_down(slot, 1, 64);
-      if (slot >= 0 && (lane == 63 || next != slot)) {
-        Real* dst = sUw + (wave * nf + slot) * kPoseSums;
+      const int slot0 = __builtin_amdgcn_readlane(slot, 0);
+      const int slot63 = __builtin_amdgcn_readlane(slot, 63);
+      const bool tail = slot >= 0 && (lane == 63 || next != slot);
+      if (lane == 0) {
+        sBndSlot[2 * wave] = slot0 >= 0 ? slot0 : -1;
+        sBndSlot[2 * wave + 1] = (slot63 >= 0 && slot63 != slot0) ? slot63 : -1;
+      }
+      if (tail) {
+        if (slot == slot0 || lane == 63) {
+          Real* dst = sBnd + (2 * wave + (slot == slot0 ? 0 : 1)) * kPoseSums;
 #pragma unroll
-        for (int k = 0; k < kPoseSums; ++k) dst[k] += v[k];
+          for (int k = 0; k < kPoseSums; ++k) dst[k] = v[k];
+        } else {
+          pose_sums_add<Real, ADJ>(sS, sB, sD, nf, slot, v);
+        }
       }
     }
     __syncthreads();
+    // edge runs of the waves, in wave order, one thread per component (the
+    // targets are diagonal blocks, rhs and diag(U); phase 4 below writes only
+    // off-diagonal blocks).  The last wave does it: it gets the shortest Schur
+    // units of every round.
+    if (tid >= TP - kPoseSums) {
+      const int k = tid - (TP - kPoseSums);
+#pragma unroll
+      for (int b = 0; b < 2 * NW; ++b) {
+        const int sb = sBndSlot[b];
+        if (sb >= 0) pose_sum_add1<Real, ADJ>(sS, sB, sD, nf, sb, k, sBnd[b * kPoseSums + k]);
+      }
+    }
 
     // ---- phase 4: Schur blocks.  Unit (segment, rows r0..r0+kRowsPerUnit-1)
     // owns those rows of one off-diagonal target block for this tile: it sums
@@ -856,24 +919,7 @@ __global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Re
     rec = nrec;
   }
 
-  // ---- fold the per-wave pose sums into the partial: U - Z sigma Z^T (upper
-  // triangle of the diagonal blocks), rhs, diag(U)
-  for (int e = tid; e < nf * kPoseSums; e += TP) {
-    const int s = e / kPoseSums, k = e % kPoseSums;
-    Real sum = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) sum += sUw[(w * nf + s) * kPoseSums + k];
-    if (k < 21) {
-      sS[kBS * blk_index(s, s, nf) + kUpperOff[k]] += sum;
-    } else if (k < 27) {
-      sB[6 * s + (k - 21)] += sum;
-    } else if (!ADJ) {
-      sD[6 * s + (k - 27)] += sum;
-    }
-  }
-  __syncthreads();
-
-  // ---- chunk partial out
+  // ---- chunk partial out (the last tile's phase 4 ended with a barrier)
   Real* part = K.part + T.chunk_part_off[chunk];
   for (int k = tid; k < nblk * kBS + 2 * nS; k += TP) part[k] = sS[k];
   const double tot = block_sum<TP>(cost, sRed);
@@ -1605,8 +1651,9 @@ __global__ void k_finalize(DevPlan P, DevWork<Real> K, DevUser U, int need_cost)
 // ---------------------------------------------------------------------------
 
 template <typename Real, int TP>
-size_t pass_a_lds(int np, int nc, int nf, int list_bytes) {
-  return PassALds<Real, TP>::bytes(np, nc, nf, list_bytes);
+size_t pass_a_lds(int np, int nc, int nf, int list_bytes, bool adj) {
+  (void)np;
+  return PassALds<Real, TP>::bytes(nc, nf, list_bytes, adj);
 }
 
 template <typename Real, int TP>
@@ -1641,7 +1688,7 @@ void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
   for (int c = 0; c < kClasses; ++c) {
     const int n = A.cls_begin[c + 1] - A.cls_begin[c];
     if (n <= 0) continue;
-    const size_t lds = pass_a_lds<Real, TP>(A.dims.np, A.dims.nc, A.cls_nf[c], A.list_bytes);
+    const size_t lds = pass_a_lds<Real, TP>(A.dims.np, A.dims.nc, A.cls_nf[c], A.list_bytes, ADJ);
     hipLaunchKernelGGL((k_pass_a<Real, TP, ADJ>), dim3(n), dim3(TP), lds, (hipStream_t)A.stream,
                        A.plan, A.tiles, K, A.user, A.settings, it, A.cls_begin[c], A.dims);
   }
@@ -1736,10 +1783,10 @@ hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* 
 }
 
 // explicit instantiations used by the ABI layer
-template size_t pass_a_lds<double, 64>(int, int, int, int);
-template size_t pass_a_lds<double, 256>(int, int, int, int);
-template size_t pass_a_lds<float, 64>(int, int, int, int);
-template size_t pass_a_lds<float, 256>(int, int, int, int);
+template size_t pass_a_lds<double, 64>(int, int, int, int, bool);
+template size_t pass_a_lds<double, 256>(int, int, int, int, bool);
+template size_t pass_a_lds<float, 64>(int, int, int, int, bool);
+template size_t pass_a_lds<float, 256>(int, int, int, int, bool);
 template size_t pass_b_lds<double, 64>();
 template size_t pass_b_lds<double, 256>();
 template size_t pass_b_lds<float, 64>();

@@ -179,7 +179,7 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
   int32_t lm_base = 0, pair_base = 0, obs_base = 0;
   for (size_t wi = 0; wi < wins.size(); ++wi) {
     const HostWindow& w = *wins[wi];
-    // tiles: whole landmarks, at most tp pairs and tp landmarks
+    // tiles: whole landmarks, at most tp pairs and tp / 2 landmarks
     std::vector<int32_t> tiles;      // window-local landmark starts
     std::vector<int64_t> tile_obs;   // observations per tile
     int32_t j = 0;
@@ -188,7 +188,7 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
       int32_t pairs = 0;
       while (j < w.n_points) {
         const int32_t pj = w.lm_pair_begin[j + 1] - w.lm_pair_begin[j];
-        if (j > start && (pairs + pj > tp || j - start >= tp)) break;
+        if (j > start && (pairs + pj > tp || j - start >= tp / 2)) break;
         pairs += pj;
         ++j;
       }

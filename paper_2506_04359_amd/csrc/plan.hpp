@@ -30,8 +30,10 @@ constexpr int kMaxObsPerLandmark = 4096;
 constexpr int kTileSmall = 64;       // pairs per tile, small-LDS configuration
 constexpr int kTileLarge = 256;      // pairs per tile, large configuration
 constexpr int kBS = 37;              // stored stride of a 6x6 block (odd: spreads LDS banks)
-constexpr int kClasses = 4;          // size classes of chunks: n_free <= 8, 16, 24, 32
-constexpr int kClassNf[kClasses] = {8, 16, 24, 32};
+constexpr int kClasses = 4;          // size classes of chunks (limits below)
+// Largest free-pose count of each size class of pass A.  With 256-pair tiles
+// and FP32 blocks, windows of up to 23 free poses fit two workgroups per CU.
+constexpr int kClassNf[kClasses] = {8, 16, 23, 32};
 
 struct HostWindow {
   int32_t n_poses = 0, n_points = 0, n_cams = 0, n_free = 0;

@@ -1,10 +1,9 @@
 """GPU parity at the library's size limits, at the benchmark's full launch
 shape, and on degenerate windows.
 
-* the largest reduced systems: 29 free poses in FP64 mode (28 in a window of
-  64 poses) and 32 in mixed mode, in windows of up to 64 poses (the pose-cache
-  limit), every landmark seen by every keyframe that sees it (long tracks: up
-  to 32 free pairs per landmark);
+* the largest reduced systems: 29 free poses in FP64 mode and 32 in mixed
+  mode, in windows of up to 64 poses, every landmark seen by every keyframe
+  that sees it (long tracks: up to 32 free pairs per landmark);
 * the full 256-window batch at 2048 observations per work item (the launch
   shape the benchmark times): every report, and sampled windows against the
   FP64 oracle;
@@ -36,7 +35,7 @@ def _fp64_replay_parity(w, s, g):
     return ref
 
 
-@pytest.mark.parametrize("n_kf,fixed,n_free", [(30, (0,), 29), (40, tuple(range(11)), 29),
+@pytest.mark.parametrize("n_kf,fixed,n_free", [(30, (0,), 29), (64, tuple(range(35)), 29),
                                                (64, tuple(range(36)), 28)])
 def test_fp64_largest_reduced_system(n_kf, fixed, n_free):
     import paper_2506_04359_amd as ba
@@ -50,9 +49,9 @@ def test_fp64_largest_reduced_system(n_kf, fixed, n_free):
     assert ref.final_cost < 0.1 * ref.trace[0]["cost"]
 
 
-def test_fp64_beyond_lds_is_unsupported_and_mixed_is_not():
+def test_fp64_beyond_29_free_poses_is_unsupported_and_mixed_is_not():
     import paper_2506_04359_amd as ba
-    w = bagen.tiny_window(seed=63, n_kf=64, n_lm=60, fixed=tuple(range(35)))
+    w = bagen.tiny_window(seed=63, n_kf=64, n_lm=60, fixed=tuple(range(34)))
     W = ba.Window.from_problem(w)
     with pytest.raises(ba.BAError) as e:
         W.workspace_size(ba.Settings(max_iters=1, precision=ba.BA_FP64))
