@@ -593,8 +593,10 @@ struct PassALds {
   }
 };
 
+// FP32: at least two waves per SIMD (the register budget that LDS allows);
+// FP64 runs one workgroup per CU anyway.
 template <typename Real, int TP, bool ADJ>
-__global__ __launch_bounds__(TP) void k_pass_a(DevPlan P, DevTiles T, DevWork<Real> K,
+__global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevPlan P, DevTiles T, DevWork<Real> K,
                                                DevUser U, DevSettings S, int it, int cls_begin,
                                                LdsDims D) {
   extern __shared__ __align__(16) unsigned char smem[];
