@@ -306,12 +306,21 @@ struct LDL3 {
   Real sg[3];    // sign(d_k)
 };
 
+// Reciprocal and reciprocal square root: the hardware approximations in FP32
+// (about 1 ulp; the FP32 blocks carry far larger rounding already), IEEE in
+// FP64, whose results are compared with the oracle at 1e-9.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+
 template <typename Real>
 __device__ __forceinline__ bool ldl3(const Real* V, bool spd, LDL3<Real>& F) {
   const Real d0 = V[0];
-  const Real l10 = V[1] / d0, l20 = V[2] / d0;
+  const Real r0 = recip(d0);
+  const Real l10 = V[1] * r0, l20 = V[2] * r0;
   const Real d1 = V[3] - l10 * l10 * d0;
-  const Real l21 = (V[4] - l20 * l10 * d0) / d1;
+  const Real l21 = (V[4] - l20 * l10 * d0) * recip(d1);
   const Real d2 = V[5] - l20 * l20 * d0 - l21 * l21 * d1;
   F.l10 = l10;
   F.l20 = l20;
@@ -323,7 +332,7 @@ __device__ __forceinline__ bool ldl3(const Real* V, bool spd, LDL3<Real>& F) {
     const bool good = spd ? (d[k] > (Real)0) : (d[k] != (Real)0);
     ok = ok && good && isfinite((double)d[k]);
     const Real ad = fabs(d[k]);
-    F.isd[k] = (Real)1 / sqrt(ad);
+    F.isd[k] = rsqrt_r(ad);
     F.sg[k] = d[k] < (Real)0 ? (Real)-1 : (Real)1;
   }
   return ok && isfinite((double)l10) && isfinite((double)l20) && isfinite((double)l21);
@@ -746,6 +755,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     if (tid < nL) {
       const int lmg = l0 + tid;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
+#pragma unroll 4
       for (int qq = lq0; qq < lq1; ++qq) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) V[k] += sPV[9 * qq + k];
@@ -1448,6 +1458,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
       const int lmt = l0 + tid;
       const int q0 = P.lm_pair_begin[lmt] - p0, q1 = P.lm_pair_begin[lmt + 1] - p0;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0}, s3[3] = {0, 0, 0};
+#pragma unroll 4
       for (int qq = q0; qq < q1; ++qq) {
         for (int k = 0; k < 6; ++k) V[k] += sPV[12 * qq + k];
         for (int k = 0; k < 3; ++k) g[k] += sPV[12 * qq + 6 + k];
