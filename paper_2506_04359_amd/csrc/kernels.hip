@@ -660,6 +660,24 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   if (tid == 0) sFlag[0] = 0;
   __syncthreads();
 
+  // a pair's point and first observation: fetched for the next tile during
+  // the current tile's Schur phase, so their memory latency is hidden
+  double px = 0, py = 0, pz = 0;
+  Real du0 = 0, dv0 = 0, wo0 = 1;
+  int cam0 = 0;
+  auto fetch_pair = [&](const int4& r, double& x, double& y, double& z, Real& du, Real& dv, Real& wo,
+                        int& cam) {
+    const double* pt = points + 3 * (r.y - W.point_off);
+    x = pt[0];
+    y = pt[1];
+    z = pt[2];
+    cam = P.obs_cam[r.x];
+    du = K.du[r.x];
+    dv = K.dv[r.x];
+    wo = K.w ? K.w[r.x] : (Real)1;
+  };
+  if (t0 < t1 && tid < ta.y) fetch_pair(rec, px, py, pz, du0, dv0, wo0, cam0);
+
   double cost = 0.0;
   for (int t = t0; t < t1; ++t) {
     const int p0 = ta.x, nP = ta.y, l0 = ta.z, nL = ta.w;
@@ -671,25 +689,16 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
       nta = trec[2 * (t + 1)];
       ntb = trec[2 * (t + 1) + 1];
     }
-    // this tile's pair data: point and first observation, and its list words
+    // this tile's pair: its pose (point and first observation are here
+    // already), and the tile's list words
     const int q = (rec.z >> 8) & 255, pose = rec.z & 255, nobs = rec.z >> 16;
     const int slot = tid < nP ? rec.w : -1;
     const int o0 = rec.x, lm = rec.y;
-    double px = 0, py = 0, pz = 0, du0 = 0, dv0 = 0, wo0 = 1;
     double Rt[12];
-    int cam0 = 0;
     if (tid < nP) {
-      const double* pt = points + 3 * (lm - W.point_off);
-      px = pt[0];
-      py = pt[1];
-      pz = pt[2];
       const double* pp = poses + 12 * pose;
 #pragma unroll
       for (int k = 0; k < 12; ++k) Rt[k] = pp[k];
-      cam0 = P.obs_cam[o0];
-      du0 = (double)K.du[o0];
-      dv0 = (double)K.dv[o0];
-      if (K.w) wo0 = (double)K.w[o0];
     }
     int lq0 = 0, lq1 = 0;
     if (tid < nL) {
@@ -722,7 +731,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
         for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
       {
         const double* C = sCam + 16 * cam0;
-        const Lin<Real> L = linearise<Real>(xb, C, du0, dv0, wo0, S.huber_delta);
+        const Lin<Real> L = linearise<Real>(xb, C, (double)du0, (double)dv0, (double)wo0, S.huber_delta);
         cost += L.rho_w;
         pair_add<Real, ADJ>(A, L, Rp, slot >= 0, C);
       }
@@ -874,6 +883,12 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
       }
     }
 
+    // next tile's pair data, in flight during the Schur units
+    double npx = 0, npy = 0, npz = 0;
+    Real ndu = 0, ndv = 0, nwo = 1;
+    int ncam = 0;
+    if (t + 1 < t1 && tid < nta.y) fetch_pair(nrec, npx, npy, npz, ndu, ndv, nwo, ncam);
+
     // ---- phase 4: Schur blocks.  Unit (segment, rows r0..r0+kRowsPerUnit-1)
     // owns those rows of one off-diagonal target block for this tile: it sums
     // -Z_a[r] sigma Z_c^T over the segment's products in registers and
@@ -929,6 +944,13 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     ta = nta;
     tb = ntb;
     rec = nrec;
+    px = npx;
+    py = npy;
+    pz = npz;
+    du0 = ndu;
+    dv0 = ndv;
+    wo0 = nwo;
+    cam0 = ncam;
   }
 
   // ---- chunk partial out (the last tile's phase 4 ended with a barrier)
