@@ -24,6 +24,10 @@ Workloads (sizes as stated for each):
   3  256 mono windows of uneven size (5-30 keyframes, 500-8000 landmarks)
   4  32-camera rig, 10 rig poses on a circle, 20000 landmarks, ~300k observations
   5  64 mono windows, 10 keyframes, 2000 landmarks, every visible frame observed
+
+Motion-only frames (``make_pnp_batch``): many independent frames, each a pose
+observing fixed map landmarks with a stereo pair or the 32-camera rig,
+optionally against a map frame shifted by a known transform.
 """
 from __future__ import annotations
 
@@ -413,3 +417,178 @@ def tiny_window(seed: int = 0, n_kf: int = 3, n_lm: int = 12, stereo: bool = Fal
                      tracks=(op, oj, ok), sigma=noise, outlier_frac=outlier_frac,
                      fixed=list(fixed), max_iters=max_iters, mixed=False,
                      name=f"tiny-{n_kf}kf-{n_lm}lm{'-stereo' if stereo else ''}")
+
+
+# ---------------------------------------------------------------------------
+# motion-only frames (pose refinement against fixed landmarks)
+# ---------------------------------------------------------------------------
+
+PNP_WORKLOADS = {
+    "pnp-4096x-stereo-300lm": dict(n_frames=4096, kind="stereo", n_lm=300),
+    "pnp-512x-rig32-400lm": dict(n_frames=512, kind="rig", n_lm=400),
+}
+
+
+@dataclasses.dataclass
+class PnPBatch:
+    """Independent frames sharing one camera rig; each frame's observations are
+    a contiguous range [frame_obs_begin[f], frame_obs_begin[f + 1])."""
+
+    intrinsics: np.ndarray        # (C, 4)
+    extrinsics: np.ndarray        # (C, 3, 4)
+    image_size: np.ndarray        # (C, 2)
+    points: np.ndarray            # (M, 3) fixed landmarks, world frame
+    poses_gt: np.ndarray          # (F, 3, 4) base-from-world (or base-from-map)
+    poses_init: np.ndarray        # (F, 3, 4)
+    frame_obs_begin: np.ndarray   # (F + 1,) int32
+    obs_point: np.ndarray         # (n,) int32
+    obs_cam: np.ndarray           # (n,) int32
+    obs_uv: np.ndarray            # (n, 2)
+    obs_w: np.ndarray             # (n,)
+    outlier: np.ndarray           # (n,) bool
+    map_from_world: Optional[np.ndarray] = None   # (F, 3, 4) or None
+    max_iters: int = 10
+    huber_delta: float = 1.0
+    lambda_init: float = 1e-3
+    name: str = ""
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.poses_gt.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_point.shape[0])
+
+    def frame_slice(self, f: int) -> slice:
+        return slice(int(self.frame_obs_begin[f]), int(self.frame_obs_begin[f + 1]))
+
+
+def _compose(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """3x4 transforms: A * B."""
+    return np.concatenate([A[:, :3] @ B[:, :3], (A[:, :3] @ B[:, 3] + A[:, 3])[:, None]], axis=1)
+
+
+def _inverse(A: np.ndarray) -> np.ndarray:
+    R = A[:, :3].T
+    return np.concatenate([R, (-R @ A[:, 3])[:, None]], axis=1)
+
+
+def _stereo_rig():
+    K = np.array([718.0, 718.0, 607.0, 185.0])
+    size = np.array([1241.0, 376.0])
+    ext = np.zeros((2, 3, 4))
+    ext[:, :, :3] = np.eye(3)
+    ext[1, :, 3] = [-0.54, 0.0, 0.0]
+    return np.stack([K, K]), ext, np.stack([size, size])
+
+
+def _ring_rig(rng, n_cam=32):
+    """Cameras on a 0.3 m sphere facing outward with random roll (the rig of
+    workload 4)."""
+    K = np.array([400.0, 400.0, 320.0, 240.0])
+    size = np.array([640.0, 480.0])
+    ext = np.zeros((n_cam, 3, 4))
+    for k in range(n_cam):
+        z = _random_unit(rng)
+        a = _random_unit(rng)
+        x = np.cross(a, z)
+        x /= np.linalg.norm(x)
+        y = np.cross(z, x)
+        R_bc = np.stack([x, y, z], axis=1) @ _rot_axis(np.array([0.0, 0.0, 1.0]), rng.uniform(0, 2 * math.pi))
+        ext[k, :, :3] = R_bc.T
+        ext[k, :, 3] = -R_bc.T @ (0.3 * z)
+    return np.tile(K, (n_cam, 1)), ext, np.tile(size, (n_cam, 1))
+
+
+def make_pnp_batch(n_frames: int, kind: str = "stereo", n_lm: int = 300, seed: int = 7000,
+                   sigma: float = 0.7, outlier_frac: float = 0.02, map_frame: bool = False,
+                   pose_rot: float = 0.02, pose_trans: float = 0.05, max_iters: int = 10,
+                   name: str = "") -> PnPBatch:
+    """Frames with random poses; each sees ``n_lm`` landmarks of its own.
+
+    stereo: the KITTI-like pair; every landmark is seen by both cameras (anchor
+    pixel uniform in the left image, depth log-uniform in 3-60 m).  rig: the
+    32-camera sphere rig; landmarks in a 12-15 m shell, observed by every camera
+    that sees them (at least one).  Pixel noise N(0, sigma^2), a fraction of
+    observations replaced by uniform pixels, initial pose = ground truth rotated
+    by ``pose_rot`` rad and shifted by ``pose_trans`` m.  With ``map_frame`` each
+    frame gets a random T^mw and its ground truth is T^bm = T^bw (T^mw)^-1."""
+    rng = np.random.default_rng(seed)
+    if kind == "stereo":
+        intr, ext, size = _stereo_rig()
+    else:
+        intr, ext, size = _ring_rig(rng)
+    n_cam = intr.shape[0]
+    pts_all, poses, begin, op, ok = [], [], [0], [], []
+    for f in range(n_frames):
+        yaw = rng.uniform(-math.pi, math.pi)
+        R_wb = _rot_y(yaw) @ _rot_axis(_random_unit(rng), rng.uniform(0.0, 0.1))
+        centre = rng.uniform(-50.0, 50.0, 3) * np.array([1.0, 0.1, 1.0])
+        pose = _pose_from_cam_to_world(R_wb, centre)
+        pts = np.zeros((0, 3))
+        vis = np.zeros((0, n_cam), bool)
+        while pts.shape[0] < n_lm:
+            m = 2 * (n_lm - pts.shape[0]) + 16
+            if kind == "stereo":
+                K = intr[0]
+                u = rng.uniform(0, size[0, 0], m)
+                v = rng.uniform(0, size[0, 1], m)
+                d = np.exp(rng.uniform(math.log(3.0), math.log(60.0), m))
+                xc = np.stack([(u - K[2]) / K[0] * d, (v - K[3]) / K[1] * d, d], axis=1)
+                cand = (xc - pose[:, 3]) @ pose[:, :3]
+            else:
+                cand = (_random_unit(rng, m) * rng.uniform(12.0, 15.0, m)[:, None] - pose[:, 3]) @ pose[:, :3]
+            cv = np.stack([_visible(intr[k], size[k], _to_cam(pose, ext[k], cand)) for k in range(n_cam)],
+                          axis=1)
+            keep = cv.all(axis=1) if kind == "stereo" else cv.any(axis=1)
+            pts = np.concatenate([pts, cand[keep]])[:n_lm]
+            vis = np.concatenate([vis, cv[keep]])[:n_lm]
+        obs = [(j, np.nonzero(vis[j])[0].tolist()) for j in range(n_lm)]
+        pts = list(pts)
+        base = len(pts_all)
+        pts_all.extend(pts)
+        for j, cams in obs:
+            for k in cams:
+                op.append(base + j)
+                ok.append(k)
+        begin.append(len(op))
+        poses.append(pose)
+    points = np.asarray(pts_all)
+    poses = np.stack(poses)
+    op = np.asarray(op, np.int32)
+    ok = np.asarray(ok, np.int32)
+    begin = np.asarray(begin, np.int32)
+    uv = np.empty((op.shape[0], 2))
+    for f in range(n_frames):
+        sl = slice(begin[f], begin[f + 1])
+        xb = points[op[sl]] @ poses[f, :, :3].T + poses[f, :, 3]
+        xc = np.einsum("nab,nb->na", ext[ok[sl], :, :3], xb) + ext[ok[sl], :, 3]
+        K = intr[ok[sl]]
+        uv[sl] = np.stack([K[:, 0] * xc[:, 0] / xc[:, 2] + K[:, 2], K[:, 1] * xc[:, 1] / xc[:, 2] + K[:, 3]],
+                          axis=1)
+    uv += rng.normal(scale=sigma, size=uv.shape)
+    outl = rng.random(op.shape[0]) < outlier_frac
+    uv[outl, 0] = rng.random(int(outl.sum())) * size[ok[outl], 0]
+    uv[outl, 1] = rng.random(int(outl.sum())) * size[ok[outl], 1]
+    mfw = None
+    gt = poses
+    if map_frame:
+        mfw = np.stack([_pose_from_cam_to_world(_rot_axis(_random_unit(rng), rng.uniform(0, 0.5)),
+                                                rng.uniform(-5, 5, 3)) for _ in range(n_frames)])
+        gt = np.stack([_compose(poses[f], _inverse(mfw[f])) for f in range(n_frames)])
+    init = _perturb_poses(rng, gt, np.zeros(n_frames, np.uint8), pose_rot, pose_trans)
+    # observations of each frame in a random order
+    for f in range(n_frames):
+        sl = slice(begin[f], begin[f + 1])
+        order = begin[f] + rng.permutation(begin[f + 1] - begin[f])
+        op[sl], ok[sl], uv[sl], outl[sl] = op[order], ok[order], uv[order], outl[order]
+    return PnPBatch(intrinsics=intr, extrinsics=ext, image_size=size, points=points, poses_gt=gt,
+                    poses_init=init, frame_obs_begin=begin, obs_point=op, obs_cam=ok, obs_uv=uv,
+                    obs_w=np.ones(op.shape[0]), outlier=outl, map_from_world=mfw,
+                    max_iters=max_iters, name=name or f"pnp-{n_frames}x-{kind}-{n_lm}lm")
+
+
+def make_pnp_workload(name: str, seed: int = 7000) -> PnPBatch:
+    return make_pnp_batch(seed=seed, name=name, **PNP_WORKLOADS[name])
+
