@@ -15,6 +15,9 @@ Printed as one JSON line:
                      speed-up of the batched mixed solve over it
   adjoint            64 windows of 10 keyframes / 2000 landmarks, forward solve
                      then the implicit-function adjoint: observations per second
+  pnp                motion-only refinement of 4096 stereo frames (300 landmarks
+                     each) and of 512 frames of the 32-camera rig: frames and
+                     LM attempts per second
   rms_check          final RMS of sampled windows against the FP64 oracle (1e-3 px)
   roofline           the linearise + Schur kernel (pass A) against the FP32 ALU peak
   cpu_baseline       the FP64 oracle on the host cores, on a bounded sample
@@ -84,7 +87,7 @@ def cpu_baseline(sample):
 
 def kernels_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.hpp"):
+    for f in ("kernels.hip", "device.hpp", "geometry.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2506_04359_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -113,6 +116,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-pnp", action="store_true", help="skip the motion-only frames")
     ap.add_argument("--chunk-obs", type=int, default=None,
                     help="fixed observations per work item instead of the autotuned value")
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -295,6 +299,43 @@ def main():
                           "windows_per_s": 64 / (ms_adj / 1e3),
                           "finite": bool(torch.isfinite(guv).all().item())}
         log(f"adjoint: {ms_adj:.3f} ms for {nobs_a} observations")
+
+    # motion-only frames (stereo PnP refinement and the 32-camera rig)
+    if not args.no_pnp:
+        out["pnp"] = {}
+        for name in ("pnp-4096x-stereo-300lm", "pnp-512x-rig32-400lm"):
+            pb = bagen.make_pnp_workload(name)
+            rig = ba.Rig(pb.intrinsics, pb.extrinsics.reshape(-1, 12))
+            sp = ba.Settings(max_iters=pb.max_iters, precision=ba.BA_MIXED, lambda_init=pb.lambda_init,
+                             huber_delta=pb.huber_delta)
+            tt = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+            PP0 = tt(pb.poses_init, torch.float64)
+            PP = PP0.clone()
+            fb, pts = tt(pb.frame_obs_begin, torch.int32), tt(pb.points, torch.float64)
+            op, oc, ouv = tt(pb.obs_point, torch.int32), tt(pb.obs_cam, torch.int32), tt(pb.obs_uv, torch.float64)
+            prep = torch.zeros(48 * pb.n_frames, dtype=torch.uint8, device=dev)
+            for _ in range(2):
+                PP.copy_(PP0)
+                ba.pnp_solve(rig, sp, fb, PP, pts, op, ouv, obs_cam=oc, reports=prep)
+            torch.cuda.synchronize()
+            b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b0.record()
+            for _ in range(args.steps):
+                PP.copy_(PP0)
+                ba.pnp_solve(rig, sp, fb, PP, pts, op, ouv, obs_cam=oc, reports=prep)
+            b1.record()
+            torch.cuda.synchronize()
+            ms_p = b0.elapsed_time(b1) / args.steps
+            pr = ba.parse_reports(prep)[: pb.n_frames]
+            out["pnp"][name] = {"frames": pb.n_frames, "observations": pb.n_obs,
+                                "lm_attempts_per_frame": pb.max_iters, "ms_per_call": ms_p,
+                                "frames_per_s": pb.n_frames / (ms_p / 1e3),
+                                "lm_iters_per_s": pb.n_frames * pb.max_iters / (ms_p / 1e3),
+                                "obs_jacobians_per_s": float(np.sum(np.diff(pb.frame_obs_begin)
+                                                                    * (1 + pr["accepted"]))) / (ms_p / 1e3),
+                                "all_reduced": bool(np.all(pr["final_cost"] < pr["initial_cost"]))}
+            log(f"{name}: {ms_p:.3f} ms for {pb.n_frames} frames ({pb.n_obs} observations)")
+            del rig
 
     # oracle on the host: bounded sample, also the RMS check of those windows
     sample = list(range(min(args.cpu_sample, N_WINDOWS)))

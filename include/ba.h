@@ -103,7 +103,7 @@ typedef struct {
   int32_t accepted;       /* accepted attempts */
   int32_t chol_failures;  /* attempts rejected by a non-positive pivot */
   int32_t depth_rejects;  /* attempts rejected by min_depth */
-  int32_t status;         /* 0 = ok, 1 = non-finite input cost */
+  int32_t status;         /* 0 = ok, 1 = non-finite input cost, 2 = bad frame indices (motion-only) */
   int32_t reserved;
 } ba_report;
 
@@ -219,6 +219,53 @@ ba_status ba_set_launch(ba_batch b, int32_t chunk_obs);
 ba_status ba_profile_stages(ba_batch b, const ba_settings* s, double* poses, double* points,
                             const double* obs_uv, const double* obs_w, void* workspace,
                             size_t ws_bytes, ba_report* reports, void* stream, double* stage_ms);
+
+/* ---------------------------------------------------------------------------
+ * Motion-only bundle adjustment (paper Sec. 2.2: the frame pose estimated from
+ * 2D observations of landmarks taken from the local map, Eq. 4 for a stereo
+ * pair, Eq. 6 for a multi-camera rig; Eq. 14, the loop-closure relative pose
+ * against landmarks moved into a map frame by a known T^mw).  Each frame's pose
+ * T minimises 1/2 sum_o w_o rho(|pi(T_cb_k T M p_j) - o|^2) over its own
+ * observations, with the landmarks p_j FIXED (M = T^mw, or identity); the same
+ * Huber kernel, left perturbation and LM schedule as ba_solve.
+ * ------------------------------------------------------------------------- */
+
+typedef struct ba_rig_s* ba_rig;   /* a camera rig resident on one device */
+
+/* Upload a rig to the current device.
+ *   intrinsics : HOST, n_cams x 4 (fx, fy, cx, cy), finite, fx, fy > 0
+ *   extrinsics : HOST, n_cams x 12 camera-from-base [R | t]; NULL -> identity
+ * 1 <= n_cams <= 32.  Errors: INVALID_ARG (bad values), UNSUPPORTED (> 32
+ * cameras), OOM / HIP.  The library owns the handle; ba_rig_destroy frees it. */
+ba_status ba_rig_create(int32_t n_cams, const double* intrinsics, const double* extrinsics,
+                        ba_rig* out);
+void ba_rig_destroy(ba_rig rig);
+
+/* Refine n_frames independent poses: exactly s->max_iters LM attempts each.
+ * Every array is DEVICE memory on the rig's device:
+ *   frame_obs_begin : n_frames + 1 int32; frame f owns observations
+ *                     [frame_obs_begin[f], frame_obs_begin[f + 1]) (non-decreasing,
+ *                     within [0, n_obs])
+ *   poses           : n_frames x 12 [R | t], row-major, in/out (base-from-world,
+ *                     or base-from-map when frame_transform is given)
+ *   points          : n_points x 3 landmarks (world frame), read only
+ *   obs_point       : n_obs int32 in [0, n_points)
+ *   obs_cam         : n_obs int32 in [0, n_cams); NULL -> camera 0
+ *   obs_uv          : n_obs x 2 pixels
+ *   obs_w           : n_obs weights; NULL -> all 1
+ *   frame_transform : n_frames x 12 T^mw applied to the landmarks; NULL -> none
+ *   reports         : n_frames ba_report; NULL -> not written
+ *   traces          : n_frames x max_iters ba_iter_trace (frame-major); may be NULL
+ * s->precision: BA_MIXED accumulates the 6x6 blocks in FP32 per lane (FP64 sums
+ * across lanes, FP64 Cholesky, acceptance and pose); BA_FP64 throughout.
+ * Host checks return INVALID_ARG / UNSUPPORTED before any device work.  A frame
+ * whose observation range or indices are out of range is left unchanged with
+ * report status 2.  Allocates nothing and does not synchronise (capturable). */
+ba_status ba_pnp_solve(ba_rig rig, const ba_settings* s, int32_t n_frames, int64_t n_obs,
+                       int64_t n_points, const int32_t* frame_obs_begin, double* poses,
+                       const double* points, const int32_t* obs_point, const int32_t* obs_cam,
+                       const double* obs_uv, const double* obs_w, const double* frame_transform,
+                       ba_report* reports, ba_iter_trace* traces, void* stream);
 
 const char* ba_status_string(ba_status s);
 const char* ba_last_error(void);

@@ -19,12 +19,14 @@ from ._binding import (  # noqa: F401
     BA_OK,
     BAError,
     Batch,
+    Rig,
     Settings,
     Window,
     adjoint,
     lib,
     parse_reports,
     parse_traces,
+    pnp_solve,
     solve,
     solve_batched,
 )

@@ -82,12 +82,17 @@ def lib():
         L.ba_set_launch.argtypes = [vp, i32]
         L.ba_profile_stages.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
                                         vp, ctypes.POINTER(ctypes.c_double)]
+        L.ba_rig_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
+        L.ba_rig_destroy.argtypes = [vp]
+        L.ba_pnp_solve.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i64, vp, vp, vp, vp, vp,
+                                   vp, vp, vp, vp, vp, vp]
         L.ba_status_string.argtypes = [i32]
         L.ba_status_string.restype = ctypes.c_char_p
         L.ba_last_error.restype = ctypes.c_char_p
         for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
                   "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_batched",
-                  "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages"):
+                  "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
+                  "ba_rig_create", "ba_pnp_solve"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -315,3 +320,45 @@ def parse_reports(reports) -> np.ndarray:
 
 def parse_traces(traces, n_windows, max_iters) -> np.ndarray:
     return np.frombuffer(traces.cpu().numpy().tobytes(), dtype=TRACE_DTYPE).reshape(n_windows, max_iters)
+
+
+class Rig:
+    """A camera rig resident on the current device (for motion-only solves)."""
+
+    def __init__(self, intrinsics, extrinsics=None):
+        K = _host(intrinsics, np.float64).reshape(-1, 4)
+        E = None if extrinsics is None else _host(extrinsics, np.float64).reshape(-1, 12)
+        self.n_cams = K.shape[0]
+        self._h = ctypes.c_void_p()
+        _check(lib().ba_rig_create(self.n_cams, K.ctypes.data_as(ctypes.c_void_p),
+                                   None if E is None else E.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ba_rig_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pnp_solve(rig: Rig, settings: Settings, frame_obs_begin, poses, points, obs_point, obs_uv,
+              obs_cam=None, obs_w=None, frame_transform=None, reports=None, traces=None,
+              stream=None):
+    """In-place motion-only solve of every frame (device tensors: int32 index
+    arrays, float64 values).  Returns (report bytes tensor, trace bytes or None)."""
+    import torch
+    n_frames = frame_obs_begin.numel() - 1
+    if reports is None:
+        reports = torch.zeros(REPORT_DTYPE.itemsize * max(n_frames, 1), dtype=torch.uint8,
+                              device=poses.device)
+    _check(lib().ba_pnp_solve(rig._h, ctypes.byref(settings.c()), n_frames, obs_point.numel(),
+                              points.shape[0], _ptr(frame_obs_begin), _ptr(poses), _ptr(points),
+                              _ptr(obs_point), _ptr(obs_cam), _ptr(obs_uv), _ptr(obs_w),
+                              _ptr(frame_transform), _ptr(reports), _ptr(traces), _stream(stream)))
+    return reports, traces
+

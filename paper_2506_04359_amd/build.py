@@ -35,6 +35,8 @@ def build(verbose: bool = False) -> str:
     steps = [
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "kernels.hip"),
                                                           "-o", os.path.join(obj, "kernels.o")],
+        [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "pnp.hip"),
+                                                          "-o", os.path.join(obj, "pnp.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "api.cpp"),
                                                           "-o", os.path.join(obj, "api.o")],
         ["g++"] + COMMON + ["-c", os.path.join(CSRC, "plan.cpp"), "-o", os.path.join(obj, "plan.o")],
@@ -45,7 +47,8 @@ def build(verbose: bool = False) -> str:
             print(out)
     tmp = OUT + ".tmp"
     _run([HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp,
-                                   os.path.join(obj, "kernels.o"), os.path.join(obj, "api.o"),
+                                   os.path.join(obj, "kernels.o"), os.path.join(obj, "pnp.o"),
+                                   os.path.join(obj, "api.o"),
                                    os.path.join(obj, "plan.o")])
     os.replace(tmp, OUT)
     return OUT

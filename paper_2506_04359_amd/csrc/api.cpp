@@ -18,6 +18,7 @@
 #include "../../include/ba.h"
 #include "device.hpp"
 #include "plan.hpp"
+#include "pnp.hpp"
 
 namespace ba {
 
@@ -479,6 +480,84 @@ const char* ba_status_string(ba_status s) {
 }
 
 const char* ba_last_error(void) { return g_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// motion-only solves
+// ---------------------------------------------------------------------------
+
+struct ba_rig_s {
+  int n_cams = 0;
+  int device = 0;
+  double* cams = nullptr;   // device, n_cams * 16
+  ~ba_rig_s() {
+    if (cams) (void)hipFree(cams);
+  }
+};
+
+ba_status ba_rig_create(int32_t n_cams, const double* intrinsics, const double* extrinsics,
+                        ba_rig* out) {
+  if (!out) return set_error(BA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_cams < 1 || !intrinsics) return set_error(BA_ERR_INVALID_ARG, "n_cams < 1 or intrinsics is NULL");
+  if (n_cams > kMaxCams) return set_error(BA_ERR_UNSUPPORTED, "more than 32 cameras in a rig");
+  std::vector<double> cam;
+  const std::string m = pack_cameras(n_cams, intrinsics, extrinsics, cam);
+  if (!m.empty()) return set_error(BA_ERR_INVALID_ARG, m);
+  std::unique_ptr<ba_rig_s> r(new ba_rig_s);
+  r->n_cams = n_cams;
+  hipError_t e = hipGetDevice(&r->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipMalloc(&r->cams, cam.size() * sizeof(double));
+  if (e != hipSuccess) {
+    r->cams = nullptr;
+    return set_error(BA_ERR_OOM, "rig: hipMalloc failed");
+  }
+  e = hipMemcpy(r->cams, cam.data(), cam.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "rig upload");
+  *out = r.release();
+  return BA_OK;
+}
+
+void ba_rig_destroy(ba_rig rig) { delete rig; }
+
+ba_status ba_pnp_solve(ba_rig rig, const ba_settings* s, int32_t n_frames, int64_t n_obs,
+                       int64_t n_points, const int32_t* frame_obs_begin, double* poses,
+                       const double* points, const int32_t* obs_point, const int32_t* obs_cam,
+                       const double* obs_uv, const double* obs_w, const double* frame_transform,
+                       ba_report* reports, ba_iter_trace* traces, void* stream) {
+  if (!rig) return set_error(BA_ERR_INVALID_ARG, "rig is NULL");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  if (n_frames < 0 || n_obs < 0 || n_points < 0) return set_error(BA_ERR_INVALID_ARG, "negative size");
+  if (n_obs > (int64_t)INT32_MAX) return set_error(BA_ERR_UNSUPPORTED, "too many observations");
+  if (n_frames == 0) return BA_OK;
+  if (!frame_obs_begin || !poses || (n_points > 0 && !points) ||
+      (n_obs > 0 && (!obs_point || !obs_uv)))
+    return set_error(BA_ERR_INVALID_ARG, "NULL device array");
+  hipError_t e = hipSetDevice(rig->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  PnpArgs A;
+  A.cams = rig->cams;
+  A.n_cams = rig->n_cams;
+  A.n_frames = n_frames;
+  A.n_obs = n_obs;
+  A.n_points = n_points;
+  A.frame_obs_begin = frame_obs_begin;
+  A.poses = poses;
+  A.points = points;
+  A.obs_point = obs_point;
+  A.obs_cam = obs_cam;
+  A.obs_uv = obs_uv;
+  A.obs_w = obs_w;
+  A.frame_transform = frame_transform;
+  A.reports = reports;
+  A.traces = traces;
+  A.settings = dev_settings(s);
+  A.stream = stream;
+  e = s->precision == BA_FP64 ? run_pnp<double>(A) : run_pnp<float>(A);
+  if (e != hipSuccess) return hip_fail(e, "motion-only launch");
+  return BA_OK;
+}
 
 ba_status ba_window_create(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
                            const int32_t* obs_pose, const int32_t* obs_point,

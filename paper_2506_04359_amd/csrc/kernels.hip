@@ -13,6 +13,7 @@
 //              landmark (V* = L D L^T, Z = W L^-T |D|^-1/2) and accumulate the
 //              chunk's private partial of S = U* - sum Z Z^T and of the reduced
 //              right-hand side in LDS
+//   sum        per window: the chunk partials added in FP64 in chunk order
 //   reduce     per window: sum the chunk partials in FP64 in a fixed order,
 //              damp, blocked Cholesky (6x6 blocks) of S, two triangular solves,
 //              candidate poses T' = Exp(dp) T
@@ -22,8 +23,9 @@
 //
 // The observation stream is coalesced SoA (du, dv, w) in landmark-major order.
 // Within a workgroup, a tile of at most TP pairs is handled one thread per pair
-// (linearisation), one thread per landmark (3x3 elimination) and a flat loop
-// over the landmark's upper pose-pair blocks (Schur products, LDS atomics).
+// (linearisation, the pair's own Schur term, DPP sums per pose), one thread per
+// landmark (3x3 elimination) and one thread per (off-diagonal target block,
+// three rows) for the Schur products listed by the plan (no atomics).
 // Every kernel of the adjoint (ADJ = true) reuses the same passes with the exact
 // Hessian, lambda = 0 and the loss cotangent as right-hand side.
 #include <hip/hip_runtime.h>
@@ -32,6 +34,7 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "geometry.hpp"
 
 namespace ba {
 
@@ -47,73 +50,9 @@ __device__ __forceinline__ int xcd_chunk(int b, int G) {
   return x * q + (x < r ? x : r) + k;
 }
 
-__device__ __forceinline__ void huber(double s, double delta, double& rho, double& d1,
-                                      double& d2) {
-  if (delta > 0.0 && delta < 1e300 && s > delta * delta) {
-    const double sq = sqrt(s);
-    rho = 2.0 * delta * sq - delta * delta;
-    d1 = delta / sq;
-    d2 = -0.5 * delta / (s * sq);
-  } else {
-    rho = s;
-    d1 = 1.0;
-    d2 = 0.0;
-  }
-}
-
 __device__ __forceinline__ int blk_index(int i, int j, int nf) {
   // upper block (i <= j) of an nf x nf block matrix, row-major over the triangle
   return i * nf - (i * (i - 1)) / 2 + (j - i);
-}
-
-// Linearisation of one observation at (pose R, t | point p).
-template <typename Real>
-struct Lin {
-  double rho_w;     // w * rho(s)
-  double d1, d2;    // rho'(s), rho''(s)
-  double wo;        // observation weight
-  double X, Y, Z;   // camera-frame point
-  Real r[2];        // residual pi(x_c) - o
-  Real a0[3], a1[3];  // rows of A R_c (A = d pi / d x_c)
-  Real xb[3];       // base-frame point
-};
-
-template <typename Real>
-__device__ __forceinline__ Lin<Real> linearise(const double* __restrict__ xb, const double* C,
-                                               double du, double dv, double wo, double delta) {
-  Lin<Real> L;
-  const double X = C[4] * xb[0] + C[5] * xb[1] + C[6] * xb[2] + C[13];
-  const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
-  const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
-  const double iz = 1.0 / Z;
-  const double xz = X * iz, yz = Y * iz;
-  const double r0 = C[0] * xz - du, r1 = C[1] * yz - dv;
-  const double s = r0 * r0 + r1 * r1;
-  double rho, d1, d2;
-  huber(s, delta, rho, d1, d2);
-  L.rho_w = wo * rho;
-  L.d1 = d1;
-  L.d2 = d2;
-  L.wo = wo;
-  L.X = X;
-  L.Y = Y;
-  L.Z = Z;
-  L.r[0] = (Real)r0;
-  L.r[1] = (Real)r1;
-  const double fi = C[0] * iz, gi = C[1] * iz;
-  for (int c = 0; c < 3; ++c) {
-    L.a0[c] = (Real)(fi * (C[4 + c] - xz * C[10 + c]));
-    L.a1[c] = (Real)(gi * (C[7 + c] - yz * C[10 + c]));
-    L.xb[c] = (Real)xb[c];
-  }
-  return L;
-}
-
-template <typename Real>
-__device__ __forceinline__ void cross3(const Real* a, const Real* b, Real* c) {
-  c[0] = a[1] * b[2] - a[2] * b[1];
-  c[1] = a[2] * b[0] - a[0] * b[2];
-  c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
 // Block accumulators of one pose-landmark pair.
@@ -478,25 +417,6 @@ __global__ void k_pack(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U) {
 // ---------------------------------------------------------------------------
 // pass A: linearise + per-landmark elimination + chunk partial of S
 // ---------------------------------------------------------------------------
-
-// Lane shift by DPP (row_shr:n within rows of 16 lanes, row_bcast:15 / :31
-// across rows) of a 32- or 64-bit value; lanes outside ROWMASK or without a
-// source lane read `old`.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ int dpp_i(int old, int x) {
-  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_r(float x) {
-  return __int_as_float(dpp_i<CTRL, ROWMASK>(0, __float_as_int(x)));
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_r(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = dpp_i<CTRL, ROWMASK>(0, (int)(b & 0xffffffffll));
-  const int hi = dpp_i<CTRL, ROWMASK>(0, (int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // One step of the segmented scan: v += (value of the source lane) where the
 // source lane carries the same key.
@@ -967,48 +887,6 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
 // reduce + blocked Cholesky of S + candidate poses (one workgroup per window)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void exp_se3(const double* xi, double* T /*3x4*/) {
-  const double rx = xi[0], ry = xi[1], rz = xi[2];
-  const double px = xi[3], py = xi[4], pz = xi[5];
-  const double th2 = px * px + py * py + pz * pz;
-  const double th = sqrt(th2);
-  double A, B, Cc;
-  if (th < 1e-4) {
-    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-    Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
-  } else {
-    A = sin(th) / th;
-    const double s = sin(0.5 * th);
-    B = 2.0 * s * s / th2;
-    Cc = (th - sin(th)) / (th2 * th);
-  }
-  const double K[9] = {0, -pz, py, pz, 0, -px, -py, px, 0};
-  double K2[9];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      K2[3 * a + b] = K[3 * a] * K[b] + K[3 * a + 1] * K[3 + b] + K[3 * a + 2] * K[6 + b];
-  double R[9], J[9];
-  for (int k = 0; k < 9; ++k) {
-    const double I = (k % 4 == 0) ? 1.0 : 0.0;
-    R[k] = I + A * K[k] + B * K2[k];
-    J[k] = I + B * K[k] + Cc * K2[k];
-  }
-  for (int a = 0; a < 3; ++a) {
-    T[4 * a] = R[3 * a];
-    T[4 * a + 1] = R[3 * a + 1];
-    T[4 * a + 2] = R[3 * a + 2];
-    T[4 * a + 3] = J[3 * a] * rx + J[3 * a + 1] * ry + J[3 * a + 2] * rz;
-  }
-}
-
-// Value of a double in lane `src` (wave-uniform) to every lane, by readlane.
-__device__ __forceinline__ double wave_bcast(double x, int src) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Upper Cholesky of one symmetric 6x6 block spread over a wave: lane l < 36
 // holds entry (l / 6, l % 6).  Writes the upper triangle of R to D and 1 / R_pp

@@ -30,6 +30,33 @@ bool rotation_ok(const double* R) {
 
 }  // namespace
 
+std::string pack_cameras(int32_t n_cams, const double* intrinsics, const double* extrinsics,
+                         std::vector<double>& cam) {
+  cam.assign((size_t)n_cams * 16, 0.0);
+  for (int k = 0; k < n_cams; ++k) {
+    const double* K = intrinsics + 4 * k;
+    for (int c = 0; c < 4; ++c)
+      if (!std::isfinite(K[c])) return "non-finite intrinsics";
+    if (!(K[0] > 0 && K[1] > 0)) return "focal lengths must be positive";
+    double* C = cam.data() + 16 * k;
+    for (int c = 0; c < 4; ++c) C[c] = K[c];
+    if (extrinsics) {
+      const double* E = extrinsics + 12 * k;
+      for (int c = 0; c < 12; ++c)
+        if (!std::isfinite(E[c])) return "non-finite extrinsics";
+      const double R[9] = {E[0], E[1], E[2], E[4], E[5], E[6], E[8], E[9], E[10]};
+      if (!rotation_ok(R)) return "extrinsic rotation is not a rotation";
+      for (int c = 0; c < 9; ++c) C[4 + c] = R[c];
+      C[13] = E[3];
+      C[14] = E[7];
+      C[15] = E[11];
+    } else {
+      C[4] = C[8] = C[12] = 1.0;
+    }
+  }
+  return "";
+}
+
 std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
                          const int32_t* obs_pose, const int32_t* obs_point,
                          const int32_t* obs_cam, const uint8_t* pose_fixed,
@@ -60,27 +87,9 @@ std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int6
     if (!w.fixed[i]) w.free_slot[i] = w.n_free++;
   if (w.n_free > kMaxFree) return fail(code, -5, "more than 32 free poses in a window");
 
-  w.cam.assign((size_t)n_cams * 16, 0.0);
-  for (int k = 0; k < n_cams; ++k) {
-    const double* K = intrinsics + 4 * k;
-    for (int c = 0; c < 4; ++c)
-      if (!std::isfinite(K[c])) return fail(code, -1, "non-finite intrinsics");
-    if (!(K[0] > 0 && K[1] > 0)) return fail(code, -1, "focal lengths must be positive");
-    double* C = w.cam.data() + 16 * k;
-    for (int c = 0; c < 4; ++c) C[c] = K[c];
-    if (extrinsics) {
-      const double* E = extrinsics + 12 * k;
-      for (int c = 0; c < 12; ++c)
-        if (!std::isfinite(E[c])) return fail(code, -1, "non-finite extrinsics");
-      const double R[9] = {E[0], E[1], E[2], E[4], E[5], E[6], E[8], E[9], E[10]};
-      if (!rotation_ok(R)) return fail(code, -1, "extrinsic rotation is not a rotation");
-      for (int c = 0; c < 9; ++c) C[4 + c] = R[c];
-      C[13] = E[3];
-      C[14] = E[7];
-      C[15] = E[11];
-    } else {
-      C[4] = C[8] = C[12] = 1.0;
-    }
+  {
+    const std::string m = pack_cameras(n_cams, intrinsics, extrinsics, w.cam);
+    if (!m.empty()) return fail(code, -1, m);
   }
 
   for (int64_t o = 0; o < n_obs; ++o) {

@@ -56,6 +56,12 @@ struct HostWindow {
 
 // Validate and build.  Returns an empty string on success, else the error.
 // code_out: 0 ok, -1 invalid argument, -5 unsupported structure.
+// Camera records (fx fy cx cy, R_cb row-major, t_cb) of a rig after checking
+// the intrinsics (finite, fx, fy > 0) and extrinsics (finite, R a rotation;
+// NULL: identity).  Returns an error message, empty on success.
+std::string pack_cameras(int32_t n_cams, const double* intrinsics, const double* extrinsics,
+                         std::vector<double>& cam);
+
 std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int64_t n_obs,
                          const int32_t* obs_pose, const int32_t* obs_point,
                          const int32_t* obs_cam, const uint8_t* pose_fixed,

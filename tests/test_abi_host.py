@@ -150,3 +150,42 @@ def test_window_without_landmarks_plans_to_nothing():
                   host_only=True)
     i = W.info()
     assert i["n_obs"] == 0 and i["n_pairs"] == 0 and i["n_points"] == 0 and i["n_free"] == 2
+
+
+@pytest.mark.parametrize("n_cams,K,frag", [
+    (0, [[400.0, 400.0, 320.0, 240.0]], "n_cams"),
+    (33, [[400.0, 400.0, 320.0, 240.0]] * 33, "32 cameras"),
+    (1, [[400.0, np.nan, 320.0, 240.0]], "non-finite"),
+    (1, [[-400.0, 400.0, 320.0, 240.0]], "focal"),
+])
+def test_rig_validation_errors(n_cams, K, frag):
+    import ctypes
+    import paper_2506_04359_amd as ba
+    L = ba.lib()
+    Kh = np.ascontiguousarray(np.asarray(K, float))
+    h = ctypes.c_void_p()
+    st = L.ba_rig_create(n_cams, Kh.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h))
+    assert st in (-1, -5)
+    assert frag in L.ba_last_error().decode()
+
+
+def test_rig_extrinsic_must_be_a_rotation():
+    import ctypes
+    import paper_2506_04359_amd as ba
+    L = ba.lib()
+    K = np.array([[400.0, 400.0, 320.0, 240.0]])
+    E = np.array([[2.0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]])
+    h = ctypes.c_void_p()
+    st = L.ba_rig_create(1, K.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
+                         ctypes.byref(h))
+    assert st == -1 and "rotation" in L.ba_last_error().decode()
+
+
+def test_pnp_solve_argument_errors():
+    import ctypes
+    import paper_2506_04359_amd as ba
+    L = ba.lib()
+    s = ba.Settings().c()
+    assert L.ba_pnp_solve(None, ctypes.byref(s), 1, 0, 0, None, None, None, None, None, None, None,
+                          None, None, None, None) == -1
+    assert "rig" in L.ba_last_error().decode()
