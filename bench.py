@@ -20,6 +20,7 @@ Printed as one JSON line:
                      LM attempts per second
   rms_check          final RMS of sampled windows against the FP64 oracle (1e-3 px)
   roofline           the linearise + Schur kernel (pass A) against the FP32 ALU peak
+                     (pnp.*.roofline: the motion-only kernel against the FP64 peak)
   cpu_baseline       the FP64 oracle on the host cores, on a bounded sample
 """
 import argparse
@@ -36,6 +37,11 @@ if ROOT not in sys.path:
 
 METRIC = "LM iters/s & obs-Jacobians/s, batched+adjoint vs plain FP64, at oracle RMS"
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
+PEAK_VALU_FP64 = 78.6        # MI355X FP64 vector peak (also the FP32 rate without packed FP32)
+# motion-only pass, per observation: x_b = X p (18), x_c (18), projection and
+# residual (9), s (3), w rho and the cost sum (2), the rows of A R_c (20),
+# w rho' (1), the two cross products (18), w J rows (12), U (21 x 4), g (6 x 4)
+PNP_FLOPS_PER_OBS_PASS = 209
 N_WINDOWS = 256
 ITERS = 15
 
@@ -318,22 +324,35 @@ def main():
                 PP.copy_(PP0)
                 ba.pnp_solve(rig, sp, fb, PP, pts, op, ouv, obs_cam=oc, reports=prep)
             torch.cuda.synchronize()
-            b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            b0.record()
+            # one event pair per call on the launch stream; the pose restore
+            # between calls is outside the timed spans
+            evs = []
             for _ in range(args.steps):
                 PP.copy_(PP0)
+                b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                b0.record()
                 ba.pnp_solve(rig, sp, fb, PP, pts, op, ouv, obs_cam=oc, reports=prep)
-            b1.record()
+                b1.record()
+                evs.append((b0, b1))
             torch.cuda.synchronize()
-            ms_p = b0.elapsed_time(b1) / args.steps
+            ms_p = sum(a.elapsed_time(b) for a, b in evs) / args.steps
             pr = ba.parse_reports(prep)[: pb.n_frames]
+            n_f = np.diff(pb.frame_obs_begin).astype(np.float64)
+            # every pass linearises: the first, then one per attempt whose
+            # Cholesky succeeded
+            passes = 1 + pr["iters"].astype(np.float64) - pr["chol_failures"]
+            flops = float(np.sum(n_f * passes)) * PNP_FLOPS_PER_OBS_PASS
             out["pnp"][name] = {"frames": pb.n_frames, "observations": pb.n_obs,
                                 "lm_attempts_per_frame": pb.max_iters, "ms_per_call": ms_p,
                                 "frames_per_s": pb.n_frames / (ms_p / 1e3),
                                 "lm_iters_per_s": pb.n_frames * pb.max_iters / (ms_p / 1e3),
-                                "obs_jacobians_per_s": float(np.sum(np.diff(pb.frame_obs_begin)
-                                                                    * (1 + pr["accepted"]))) / (ms_p / 1e3),
-                                "all_reduced": bool(np.all(pr["final_cost"] < pr["initial_cost"]))}
+                                "obs_jacobians_per_s": float(np.sum(n_f * (1 + pr["accepted"]))) / (ms_p / 1e3),
+                                "all_reduced": bool(np.all(pr["final_cost"] < pr["initial_cost"])),
+                                "roofline": {"bound": "alu", "achieved": flops / (ms_p * 1e-3) / 1e12,
+                                             "peak": PEAK_VALU_FP64, "unit": "TFLOP/s",
+                                             "frac": flops / (ms_p * 1e-3) / 1e12 / PEAK_VALU_FP64,
+                                             "traffic": None, "kernel": "k_pnp",
+                                             "flops_per_launch": flops, "avg_launch_ms": ms_p}}
             log(f"{name}: {ms_p:.3f} ms for {pb.n_frames} frames ({pb.n_obs} observations)")
             del rig
 

@@ -241,6 +241,13 @@ ba_status ba_rig_create(int32_t n_cams, const double* intrinsics, const double* 
                         ba_rig* out);
 void ba_rig_destroy(ba_rig rig);
 
+/* Waves of 64 lanes that share one frame in ba_pnp_solve on this rig: 1, 2 or
+ * 4, or 0 (the default) to choose from the frame count and the mean
+ * observations per frame.  Several waves per frame split its observations and
+ * add their sums in a fixed order, so results differ from one wave per frame
+ * only by rounding.  Errors: INVALID_ARG (NULL rig or another value). */
+ba_status ba_rig_set_waves_per_frame(ba_rig rig, int32_t waves_per_frame);
+
 /* Refine n_frames independent poses: exactly s->max_iters LM attempts each.
  * Every array is DEVICE memory on the rig's device:
  *   frame_obs_begin : n_frames + 1 int32; frame f owns observations

@@ -84,6 +84,7 @@ def lib():
                                         vp, ctypes.POINTER(ctypes.c_double)]
         L.ba_rig_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.ba_rig_destroy.argtypes = [vp]
+        L.ba_rig_set_waves_per_frame.argtypes = [vp, i32]
         L.ba_pnp_solve.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i64, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp, vp]
         L.ba_status_string.argtypes = [i32]
@@ -92,7 +93,7 @@ def lib():
         for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
                   "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_batched",
                   "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
-                  "ba_rig_create", "ba_pnp_solve"):
+                  "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -333,6 +334,10 @@ class Rig:
         _check(lib().ba_rig_create(self.n_cams, K.ctypes.data_as(ctypes.c_void_p),
                                    None if E is None else E.ctypes.data_as(ctypes.c_void_p),
                                    ctypes.byref(self._h)))
+
+    def set_waves_per_frame(self, waves_per_frame: int):
+        """1, 2 or 4 waves share each frame; 0 chooses from the launch shape."""
+        _check(lib().ba_rig_set_waves_per_frame(self._h, int(waves_per_frame)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

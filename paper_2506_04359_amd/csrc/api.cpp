@@ -489,6 +489,7 @@ struct ba_rig_s {
   int n_cams = 0;
   int device = 0;
   double* cams = nullptr;   // device, n_cams * 16
+  int waves_per_frame = 0;  // 0: chosen per launch
   ~ba_rig_s() {
     if (cams) (void)hipFree(cams);
   }
@@ -519,6 +520,14 @@ ba_status ba_rig_create(int32_t n_cams, const double* intrinsics, const double* 
 }
 
 void ba_rig_destroy(ba_rig rig) { delete rig; }
+
+ba_status ba_rig_set_waves_per_frame(ba_rig rig, int32_t waves_per_frame) {
+  if (!rig) return set_error(BA_ERR_INVALID_ARG, "rig is NULL");
+  if (waves_per_frame != 0 && waves_per_frame != 1 && waves_per_frame != 2 && waves_per_frame != 4)
+    return set_error(BA_ERR_INVALID_ARG, "waves per frame must be 0, 1, 2 or 4");
+  rig->waves_per_frame = waves_per_frame;
+  return BA_OK;
+}
 
 ba_status ba_pnp_solve(ba_rig rig, const ba_settings* s, int32_t n_frames, int64_t n_obs,
                        int64_t n_points, const int32_t* frame_obs_begin, double* poses,
@@ -553,6 +562,7 @@ ba_status ba_pnp_solve(ba_rig rig, const ba_settings* s, int32_t n_frames, int64
   A.reports = reports;
   A.traces = traces;
   A.settings = dev_settings(s);
+  A.waves_per_frame = rig->waves_per_frame ? rig->waves_per_frame : pnp_waves_per_frame(n_frames, n_obs);
   A.stream = stream;
   e = s->precision == BA_FP64 ? run_pnp<double>(A) : run_pnp<float>(A);
   if (e != hipSuccess) return hip_fail(e, "motion-only launch");

@@ -25,8 +25,12 @@ struct PnpArgs {
   ba_report* reports;              // n_frames or NULL
   ba_iter_trace* traces;           // n_frames * max_iters or NULL
   DevSettings settings;
+  int waves_per_frame;             // 1, 2 or 4
   void* stream;
 };
+
+// Waves per frame for a launch of n_frames frames and n_obs observations.
+int pnp_waves_per_frame(int n_frames, long long n_obs);
 
 template <typename Real>
 hipError_t run_pnp(const PnpArgs& A);

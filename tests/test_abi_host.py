@@ -189,3 +189,10 @@ def test_pnp_solve_argument_errors():
     assert L.ba_pnp_solve(None, ctypes.byref(s), 1, 0, 0, None, None, None, None, None, None, None,
                           None, None, None, None) == -1
     assert "rig" in L.ba_last_error().decode()
+
+
+def test_rig_waves_per_frame_needs_a_rig():
+    import paper_2506_04359_amd as ba
+    L = ba.lib()
+    assert L.ba_rig_set_waves_per_frame(None, 1) == -1
+    assert "rig" in L.ba_last_error().decode()

@@ -31,11 +31,12 @@ def _frame(b, f):
                         map_from_world=None if b.map_from_world is None else b.map_from_world[f])
 
 
-def _gpu(b, s, obs_w=None, obs_point=None, frame_begin=None, with_trace=True):
+def _gpu(b, s, obs_w=None, obs_point=None, frame_begin=None, with_trace=True, wpf=0):
     import torch
     import paper_2506_04359_amd as ba
     dev = torch.device("cuda:0")
     rig = ba.Rig(b.intrinsics, b.extrinsics.reshape(-1, 12))
+    rig.set_waves_per_frame(wpf)
     t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     P = t(b.poses_init, torch.float64)
     fb = t(b.frame_obs_begin if frame_begin is None else frame_begin, torch.int32)
@@ -86,12 +87,14 @@ def _check_fp64(b, s, g, obs_w=None):
         assert np.abs(P - ref.pose).max() <= TOL64 * max(1.0, np.abs(ref.pose).max()), f
 
 
-@pytest.mark.parametrize("kind,map_frame", [("stereo", False), ("rig", False), ("stereo", True)])
-def test_fp64_frames_match_oracle(kind, map_frame):
+@pytest.mark.parametrize("kind,map_frame,wpf", [("stereo", False, 1), ("rig", False, 1), ("stereo", True, 1),
+                                                ("stereo", False, 2), ("rig", False, 4), ("stereo", True, 4)])
+def test_fp64_frames_match_oracle(kind, map_frame, wpf):
+    """Frames of 1-2 wave-widths of observations (ragged last pass per lane)."""
     import paper_2506_04359_amd as ba
     b = bagen.make_pnp_batch(9, kind, 60, seed=21, outlier_frac=0.05, map_frame=map_frame)
     s = ba.Settings(max_iters=12, precision=ba.BA_FP64)
-    _check_fp64(b, s, _gpu(b, s))
+    _check_fp64(b, s, _gpu(b, s, wpf=wpf))
 
 
 def test_fp64_weights_and_least_squares():
@@ -104,7 +107,8 @@ def test_fp64_weights_and_least_squares():
     _check_fp64(b, s_ls, _gpu(b, s_ls))
 
 
-def test_degenerate_frames():
+@pytest.mark.parametrize("wpf", [1, 4])
+def test_degenerate_frames(wpf):
     """An empty frame, a frame with an out-of-range landmark index and a depth
     guard that rejects everything: poses unchanged, the other frames solved."""
     import paper_2506_04359_amd as ba
@@ -116,14 +120,14 @@ def test_degenerate_frames():
     sl3 = b.frame_slice(3)
     op[sl3.start] = b.points.shape[0] + 5     # out of range in frame 3
     s = ba.Settings(max_iters=8, precision=ba.BA_FP64)
-    g = _gpu(b, s, obs_point=op, frame_begin=fb)
+    g = _gpu(b, s, obs_point=op, frame_begin=fb, wpf=wpf)
     assert np.array_equal(g["poses"][1], b.poses_init[1])
     assert g["reports"][1]["accepted"] == 0 and g["reports"][1]["final_cost"] == 0.0
     assert g["reports"][3]["status"] == 2 and np.array_equal(g["poses"][3], b.poses_init[3])
     ref = pnp.pnp_solve(b.poses_init[0], _frame(b, 0), _osettings(s))
     assert np.abs(g["poses"][0] - ref.pose).max() < 1e-9 * max(1.0, np.abs(ref.pose).max())
     s_d = ba.Settings(max_iters=3, precision=ba.BA_FP64, min_depth=1e6)
-    g = _gpu(b, s_d)
+    g = _gpu(b, s_d, wpf=wpf)
     assert np.array_equal(g["poses"], b.poses_init)
     assert np.all(g["reports"]["depth_rejects"] == 3)
 
@@ -144,11 +148,14 @@ def test_mixed_benchmark_workload_sampled():
         assert abs(r["final_cost"][f] - ref.final_cost) <= 1e-4 * ref.final_cost, f
 
 
-def test_mixed_rig_workload_sampled():
+@pytest.mark.parametrize("wpf", [0, 1, 2])
+def test_mixed_rig_workload_sampled(wpf):
+    """64 frames of the 32-camera rig (about 1300 observations each); 0 picks
+    four waves per frame for this shape."""
     import paper_2506_04359_amd as ba
     b = bagen.make_pnp_batch(64, "rig", 400, seed=24)
     s = ba.Settings(max_iters=10, precision=ba.BA_MIXED)
-    g = _gpu(b, s, with_trace=False)
+    g = _gpu(b, s, with_trace=False, wpf=wpf)
     for f in (0, 31, 63):
         ref = pnp.pnp_solve(b.poses_init[f], _frame(b, f), _osettings(s))
         ang, dt = _pose_err(g["poses"][f], ref.pose)
