@@ -13,15 +13,32 @@
 
 namespace ba {
 
+// 1/x and 1/sqrt(x) in FP64: the hardware estimates refined by two Newton
+// steps each (a few ulp for finite normal x; not correctly rounded).
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double h = fma(-x * r, r, 1.0);   // r <- r + r (1 - x r^2) / 2
+  r = fma(0.5 * r, h, r);
+  h = fma(-x * r, r, 1.0);
+  return fma(0.5 * r, h, r);
+}
+
 // Huber kernel on s = |r|^2: rho, rho', rho''.  delta <= 0 or inf: plain least
 // squares.  s == delta^2 takes the inlier branch.
 __device__ __forceinline__ void huber(double s, double delta, double& rho, double& d1,
                                       double& d2) {
   if (delta > 0.0 && delta < 1e300 && s > delta * delta) {
-    const double sq = sqrt(s);
-    rho = 2.0 * delta * sq - delta * delta;
-    d1 = delta / sq;
-    d2 = -0.5 * delta / (s * sq);
+    const double ir = rsqrt_nr(s);   // 1 / sqrt(s)
+    rho = 2.0 * delta * (s * ir) - delta * delta;
+    d1 = delta * ir;
+    d2 = -0.5 * delta * ir * ir * ir;
   } else {
     rho = s;
     d1 = 1.0;
@@ -48,7 +65,7 @@ __device__ __forceinline__ Lin<Real> linearise(const double* __restrict__ xb, co
   const double X = C[4] * xb[0] + C[5] * xb[1] + C[6] * xb[2] + C[13];
   const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
   const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
-  const double iz = 1.0 / Z;
+  const double iz = recip_nr(Z);
   const double xz = X * iz, yz = Y * iz;
   const double r0 = C[0] * xz - du, r1 = C[1] * yz - dv;
   const double s = r0 * r0 + r1 * r1;
@@ -106,19 +123,32 @@ __device__ __forceinline__ double wave_bcast(double x, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// SE(3) exponential of xi = (rho, phi) as a 3x4 [R | t] (Taylor coefficients
-// below theta = 1e-4).
+// SE(3) exponential of xi = (rho, phi) as a 3x4 [R | t].  The coefficients
+// A = sin(th)/th, B = (1 - cos th)/th^2, C = (th - sin th)/th^3 come from
+// their power series in th^2 below th = 1 (nine terms: the first omitted one
+// is under 1e-17, and the series has no cancellation), and from the closed
+// forms above it.
 __device__ __forceinline__ void exp_se3(const double* xi, double* T /*3x4*/) {
   const double rx = xi[0], ry = xi[1], rz = xi[2];
   const double px = xi[3], py = xi[4], pz = xi[5];
   const double th2 = px * px + py * py + pz * pz;
-  const double th = sqrt(th2);
   double A, B, Cc;
-  if (th < 1e-4) {
-    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-    Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  if (th2 < 1.0) {
+    // A = 1 - t/(2*3) (1 - t/(4*5) (...)), B = (1 - t/(3*4) (...)) / 2,
+    // C = (1 - t/(4*5) (...)) / 6, t = th^2
+    double a = 1.0, b = 1.0, c = 1.0;
+#pragma unroll
+    for (int k = 8; k >= 0; --k) {
+      const double n = 2.0 * k;
+      a = fma(-th2 * (1.0 / ((n + 2.0) * (n + 3.0))), a, 1.0);
+      b = fma(-th2 * (1.0 / ((n + 3.0) * (n + 4.0))), b, 1.0);
+      c = fma(-th2 * (1.0 / ((n + 4.0) * (n + 5.0))), c, 1.0);
+    }
+    A = a;
+    B = 0.5 * b;
+    Cc = c / 6.0;
   } else {
+    const double th = sqrt(th2);
     A = sin(th) / th;
     const double s = sin(0.5 * th);
     B = 2.0 * s * s / th2;

@@ -140,7 +140,7 @@ __device__ __forceinline__ void pair_add(PairAcc<Real>& A, const Lin<Real>& L, c
     const Real w2 = (Real)(2.0 * L.wo * L.d2);
     // w rho' sum_k r_k Hess(r_k) = w rho' (B^T Q B + M(a)),  B = [I, -[x_b]x, R_i]
     const double X = L.X, Y = L.Y;
-    const double iz = 1.0 / L.Z;
+    const double iz = recip_nr(L.Z);
     const Real pxz = (Real)(-(double)L.r[0] * C[0] * iz * iz);
     const Real pyz = (Real)(-(double)L.r[1] * C[1] * iz * iz);
     const Real pzz = (Real)(2.0 * ((double)L.r[0] * C[0] * X + (double)L.r[1] * C[1] * Y) * iz * iz * iz);
@@ -1407,7 +1407,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
           const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
           const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
           if (!(Z > S.min_depth)) sFlag[0] = 1;
-          const double iz = 1.0 / Z;
+          const double iz = recip_nr(Z);
           const double r0 = C[0] * X * iz - (double)K.du[o];
           const double r1 = C[1] * Y * iz - (double)K.dv[o];
           double rho, d1, d2;

@@ -146,21 +146,20 @@ __device__ __forceinline__ bool solve6(double* R /*21, overwritten*/, const doub
     const double d = R[idx(k, k)];
     R[idx(k, k)] = d + lam * (d > 1e-9 ? d : 1e-9);
   }
+  double ir[6];   // 1 / R_aa
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
     double d = R[idx(a, a)];
 #pragma unroll
     for (int m = 0; m < a; ++m) d -= R[idx(m, a)] * R[idx(m, a)];
     if (!(d > 0.0) || !isfinite(d)) return false;
-    const double ra = sqrt(d);
-    R[idx(a, a)] = ra;
-    const double ir = 1.0 / ra;
+    ir[a] = rsqrt_nr(d);
 #pragma unroll
     for (int c = a + 1; c < 6; ++c) {
       double v = R[idx(a, c)];
 #pragma unroll
       for (int m = 0; m < a; ++m) v -= R[idx(m, a)] * R[idx(m, c)];
-      R[idx(a, c)] = v * ir;
+      R[idx(a, c)] = v * ir[a];
     }
   }
   double y[6];
@@ -169,14 +168,14 @@ __device__ __forceinline__ bool solve6(double* R /*21, overwritten*/, const doub
     double v = -g[a];
 #pragma unroll
     for (int m = 0; m < a; ++m) v -= R[idx(m, a)] * y[m];
-    y[a] = v / R[idx(a, a)];
+    y[a] = v * ir[a];
   }
 #pragma unroll
   for (int a = 5; a >= 0; --a) {   // R x = y
     double v = y[a];
 #pragma unroll
     for (int m = a + 1; m < 6; ++m) v -= R[idx(a, m)] * x[m];
-    x[a] = v / R[idx(a, a)];
+    x[a] = v * ir[a];
   }
 #pragma unroll
   for (int a = 0; a < 6; ++a)
@@ -305,11 +304,11 @@ __global__ __launch_bounds__(pnp_threads<WPF>()) void k_pnp(PnpArgs A) {
         }
         int e = 0;
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
+        for (int r = 0; r < 6; ++r) {   // two fused multiply-adds per entry
           const Real wj0 = w1 * J[0][r], wj1 = w1 * J[1][r];
 #pragma unroll
-          for (int cc = r; cc < 6; ++cc, ++e) U[e] += wj0 * J[0][cc] + wj1 * J[1][cc];
-          g[r] += wj0 * L.r[0] + wj1 * L.r[1];
+          for (int cc = r; cc < 6; ++cc, ++e) U[e] = fma(wj1, J[1][cc], fma(wj0, J[0][cc], U[e]));
+          g[r] = fma(wj1, L.r[1], fma(wj0, L.r[0], g[r]));
         }
         cur = nxt;
         ob = oc;
