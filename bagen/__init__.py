@@ -592,3 +592,70 @@ def make_pnp_batch(n_frames: int, kind: str = "stereo", n_lm: int = 300, seed: i
 def make_pnp_workload(name: str, seed: int = 7000) -> PnPBatch:
     return make_pnp_batch(seed=seed, name=name, **PNP_WORKLOADS[name])
 
+
+
+# ---------------------------------------------------------------------------
+# triangulation batches: the landmarks of windows, re-estimated from their
+# observations with every pose held at its ground truth
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class TriBatch:
+    """Landmarks with landmark-major (CSR) observations; poses fixed.  All
+    windows share one rig (same intrinsics and extrinsics)."""
+
+    intrinsics: np.ndarray        # (C, 4)
+    extrinsics: np.ndarray        # (C, 3, 4)
+    poses: np.ndarray             # (N, 3, 4) base-from-world (ground truth)
+    points_gt: np.ndarray         # (M, 3)
+    point_obs_begin: np.ndarray   # (M + 1,) int32
+    obs_pose: np.ndarray          # (n,) int32
+    obs_cam: np.ndarray           # (n,) int32
+    obs_uv: np.ndarray            # (n, 2)
+    obs_w: np.ndarray             # (n,)
+    max_iters: int = 10
+    huber_delta: float = 1.0
+    lambda_init: float = 1e-3
+    name: str = ""
+
+    @property
+    def n_points(self):
+        return int(self.points_gt.shape[0])
+
+    @property
+    def n_obs(self):
+        return int(self.obs_pose.shape[0])
+
+    @property
+    def n_poses(self):
+        return int(self.poses.shape[0])
+
+    def point_slice(self, j):
+        return slice(int(self.point_obs_begin[j]), int(self.point_obs_begin[j + 1]))
+
+
+def make_tri_batch(windows: List[Window], max_iters: int = 10, name: str = "") -> TriBatch:
+    """Every landmark of the given windows (one rig), observations grouped by
+    landmark in window order, poses at ground truth."""
+    K, E = windows[0].intrinsics, windows[0].extrinsics
+    for w in windows:
+        if not (np.array_equal(w.intrinsics, K) and np.array_equal(w.extrinsics, E)):
+            raise ValueError("windows of a triangulation batch share one rig")
+    poses, pts, begin, op, oc, uv, ow = [], [], [0], [], [], [], []
+    pose_base = 0
+    for w in windows:
+        order = np.argsort(w.obs_point, kind="stable")
+        counts = np.bincount(w.obs_point, minlength=w.points_gt.shape[0])
+        op.append(w.obs_pose[order] + pose_base)
+        oc.append(w.obs_cam[order])
+        uv.append(w.obs_uv[order])
+        ow.append(w.obs_w[order])
+        begin.extend((begin[-1] + np.cumsum(counts)).tolist())
+        poses.append(w.poses_gt)
+        pts.append(w.points_gt)
+        pose_base += w.poses_gt.shape[0]
+    return TriBatch(intrinsics=K, extrinsics=E, poses=np.concatenate(poses), points_gt=np.concatenate(pts),
+                    point_obs_begin=np.asarray(begin, np.int32),
+                    obs_pose=np.concatenate(op).astype(np.int32), obs_cam=np.concatenate(oc).astype(np.int32),
+                    obs_uv=np.concatenate(uv), obs_w=np.concatenate(ow), max_iters=max_iters,
+                    huber_delta=windows[0].huber_delta, lambda_init=windows[0].lambda_init, name=name)

@@ -16,10 +16,11 @@ What it computes (paper: Sec. 2.2, "3D module", Eq. 2 and Eq. 3):
   * the implicit-function adjoint of the converged solution with respect to the
     2D keypoints and the observation weights (``adjoint``).
 
-The paper leaves the solver's details open; the readings taken here (Huber
+The paper leaves the solver's details open; the readings taken here are a Huber
 robust kernel on the pixel residual, Marquardt diagonal damping with x10 / /10,
-left SE(3) perturbation, strict-decrease acceptance, fixed attempt count) are
-listed in the design doc together with the pins that fix each function.
+the left SE(3) perturbation, strict-decrease acceptance and a fixed attempt
+count.  Each function is pinned by tests against values fixed by the paper or by
+the mathematics (closed forms, finite differences, library solvers, brute force).
 """
 from .se3 import skew, exp_so3, left_jacobian_so3, exp_se3, retract_pose, rotation_angle
 from .model import Problem, transform, residuals, jacobians, huber, cost
