@@ -18,9 +18,12 @@ Printed as one JSON line:
   pnp                motion-only refinement of 4096 stereo frames (300 landmarks
                      each) and of 512 frames of the 32-camera rig: frames and
                      LM attempts per second
+  triangulation      every landmark of the 256 windows re-triangulated from its
+                     observations (poses at ground truth): landmarks per second
   rms_check          final RMS of sampled windows against the FP64 oracle (1e-3 px)
   roofline           the linearise + Schur kernel (pass A) against the FP32 ALU peak
-                     (pnp.*.roofline: the motion-only kernel against the FP64 peak)
+                     (pnp.*.roofline, triangulation.roofline: the motion-only and
+                     triangulation kernels against the FP64 peak)
   cpu_baseline       the FP64 oracle on the host cores, on a bounded sample
 """
 import argparse
@@ -42,6 +45,13 @@ PEAK_VALU_FP64 = 78.6        # MI355X FP64 vector peak (also the FP32 rate witho
 # residual (9), s (3), w rho and the cost sum (2), the rows of A R_c (20),
 # w rho' (1), the two cross products (18), w J rows (12), U (21 x 4), g (6 x 4)
 PNP_FLOPS_PER_OBS_PASS = 209
+# triangulation, per observation: a pass x_b (18), x_c (18), projection and
+# residual (9), s (3), w rho and the sum (2), rows of A R_c (20), J rows A R_c R_i
+# (30), w rho' (1), w J (6), V (6 x 4), g (3 x 4); the ray start once: R_cw (45),
+# t_cw (18), normalised pixel (4), ray direction and centre (33), normalisation
+# (9), d.c (5), M and b (30)
+TRI_FLOPS_PER_OBS_PASS = 143
+TRI_FLOPS_PER_OBS_START = 144
 N_WINDOWS = 256
 ITERS = 15
 
@@ -123,6 +133,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-pnp", action="store_true", help="skip the motion-only frames")
+    ap.add_argument("--no-tri", action="store_true", help="skip the triangulation leg")
     ap.add_argument("--chunk-obs", type=int, default=None,
                     help="fixed observations per work item instead of the autotuned value")
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -355,6 +366,46 @@ def main():
                                              "flops_per_launch": flops, "avg_launch_ms": ms_p}}
             log(f"{name}: {ms_p:.3f} ms for {pb.n_frames} frames ({pb.n_obs} observations)")
             del rig
+
+    # triangulation of every landmark of the 256 windows from its observations,
+    # poses at ground truth
+    if not args.no_tri:
+        tb = bagen.make_tri_batch(ws, max_iters=10)
+        rig = ba.Rig(tb.intrinsics, tb.extrinsics.reshape(-1, 12))
+        st = ba.Settings(max_iters=tb.max_iters, precision=ba.BA_MIXED, lambda_init=tb.lambda_init,
+                         huber_delta=tb.huber_delta)
+        tt = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        targs = (tt(tb.point_obs_begin, torch.int32), tt(tb.poses.reshape(-1, 12), torch.float64),
+                 tt(tb.obs_pose, torch.int32), tt(tb.obs_uv, torch.float64))
+        tpts = torch.empty((tb.n_points, 3), dtype=torch.float64, device=dev)
+        toc = tt(tb.obs_cam, torch.int32)
+        trep = torch.zeros(48 * tb.n_points, dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            ba.triangulate(rig, st, *targs, tpts, obs_cam=toc, reports=trep)
+        torch.cuda.synchronize()
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b0.record()
+        for _ in range(args.steps):
+            ba.triangulate(rig, st, *targs, tpts, obs_cam=toc, reports=trep)
+        b1.record()
+        torch.cuda.synchronize()
+        ms_t = b0.elapsed_time(b1) / args.steps
+        tr_ = ba.parse_reports(trep)[: tb.n_points]
+        n_l = np.diff(tb.point_obs_begin).astype(np.float64)
+        ok = tr_["status"] == 0
+        passes = np.where(ok, 1 + tr_["iters"].astype(np.float64) - tr_["chol_failures"], 0.0)
+        flops = float(np.sum(n_l * (passes * TRI_FLOPS_PER_OBS_PASS + TRI_FLOPS_PER_OBS_START)))
+        out["triangulation"] = {
+            "workload": "tri-256x-mono-uneven", "landmarks": tb.n_points, "observations": tb.n_obs,
+            "lm_attempts_per_landmark": tb.max_iters, "ms_per_call": ms_t,
+            "landmarks_per_s": tb.n_points / (ms_t / 1e3), "obs_per_s": tb.n_obs / (ms_t / 1e3),
+            "refined_fraction": float(ok.mean()),
+            "roofline": {"bound": "alu", "achieved": flops / (ms_t * 1e-3) / 1e12, "peak": PEAK_VALU_FP64,
+                         "unit": "TFLOP/s", "frac": flops / (ms_t * 1e-3) / 1e12 / PEAK_VALU_FP64,
+                         "traffic": None, "kernel": "k_tri", "flops_per_launch": flops,
+                         "avg_launch_ms": ms_t}}
+        log(f"triangulation: {ms_t:.3f} ms for {tb.n_points} landmarks ({tb.n_obs} observations)")
+        del rig
 
     # oracle on the host: bounded sample, also the RMS check of those windows
     sample = list(range(min(args.cpu_sample, N_WINDOWS)))

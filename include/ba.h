@@ -103,7 +103,8 @@ typedef struct {
   int32_t accepted;       /* accepted attempts */
   int32_t chol_failures;  /* attempts rejected by a non-positive pivot */
   int32_t depth_rejects;  /* attempts rejected by min_depth */
-  int32_t status;         /* 0 = ok, 1 = non-finite input cost, 2 = bad frame indices (motion-only) */
+  int32_t status;         /* 0 = ok, 1 = non-finite input cost, 2 = bad indices (motion-only,
+                             triangulation), 3 / 4: see ba_triangulate */
   int32_t reserved;
 } ba_report;
 
@@ -273,6 +274,45 @@ ba_status ba_pnp_solve(ba_rig rig, const ba_settings* s, int32_t n_frames, int64
                        const double* points, const int32_t* obs_point, const int32_t* obs_cam,
                        const double* obs_uv, const double* obs_w, const double* frame_transform,
                        ba_report* reports, ba_iter_trace* traces, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Multi-view triangulation (paper Sec. 2.2, 3D module: new landmarks are
+ * triangulated from the multi-view observations of a keyframe before they
+ * enter the local map).  Each landmark j is estimated from its own
+ * observations with the poses FIXED: first the weighted least-squares
+ * intersection of the viewing rays, (sum_o w_o (I - d_o d_o^T)) p0 =
+ * sum_o w_o (I - d_o d_o^T) c_o (c_o the camera centre, d_o the unit ray through
+ * the pixel, world frame), then exactly s->max_iters LM attempts on
+ * 1/2 sum_o w_o rho(|pi(T_cb_k T_bw_i p) - o|^2) over p alone, with the Huber
+ * kernel, damping, depth guard and acceptance of ba_solve.
+ * ------------------------------------------------------------------------- */
+
+/* Every array is DEVICE memory on the rig's device:
+ *   point_obs_begin : n_points + 1 int32; landmark j owns observations
+ *                     [point_obs_begin[j], point_obs_begin[j + 1]) (within [0, n_obs])
+ *   poses           : n_poses x 12 [R | t] base-from-world, row-major, read only
+ *   obs_pose        : n_obs int32 in [0, n_poses)
+ *   obs_cam         : n_obs int32 in [0, n_cams); NULL -> camera 0
+ *   obs_uv          : n_obs x 2 pixels
+ *   obs_w           : n_obs weights; NULL -> all 1
+ *   points          : n_points x 3, written: the refined landmark (status 0), the
+ *                     unrefined ray intersection (status 4), NaN (status 2, 3)
+ *   reports         : n_points ba_report or NULL; status 0 ok, 1 non-finite
+ *                     start cost, 2 observation range or index out of range,
+ *                     3 degenerate (fewer than two observations, or a Cholesky
+ *                     pivot of the ray system <= 1e-10 times its trace), 4 the
+ *                     start is at depth <= min_depth in one of its views
+ *                     (costs NaN and no attempts for 2-4)
+ *   traces          : n_points x max_iters ba_iter_trace (landmark-major) or NULL
+ * s->precision: BA_MIXED accumulates V and g in FP32 (FP64 transform, residual,
+ * cost, Cholesky and point); BA_FP64 throughout.  Host checks return
+ * INVALID_ARG / UNSUPPORTED before any device work.  Allocates nothing and does
+ * not synchronise (capturable). */
+ba_status ba_triangulate(ba_rig rig, const ba_settings* s, int32_t n_points, int64_t n_obs,
+                         int32_t n_poses, const int32_t* point_obs_begin, const double* poses,
+                         const int32_t* obs_pose, const int32_t* obs_cam, const double* obs_uv,
+                         const double* obs_w, double* points, ba_report* reports,
+                         ba_iter_trace* traces, void* stream);
 
 const char* ba_status_string(ba_status s);
 const char* ba_last_error(void);

@@ -27,6 +27,7 @@ from ._binding import (  # noqa: F401
     parse_reports,
     parse_traces,
     pnp_solve,
+    triangulate,
     solve,
     solve_batched,
 )

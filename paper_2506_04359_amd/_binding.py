@@ -85,6 +85,8 @@ def lib():
         L.ba_rig_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.ba_rig_destroy.argtypes = [vp]
         L.ba_rig_set_waves_per_frame.argtypes = [vp, i32]
+        L.ba_triangulate.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i32, vp, vp, vp, vp, vp, vp,
+                                     vp, vp, vp, vp]
         L.ba_pnp_solve.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i64, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp, vp]
         L.ba_status_string.argtypes = [i32]
@@ -93,7 +95,7 @@ def lib():
         for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
                   "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_batched",
                   "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
-                  "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve"):
+                  "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -367,3 +369,19 @@ def pnp_solve(rig: Rig, settings: Settings, frame_obs_begin, poses, points, obs_
                               _ptr(frame_transform), _ptr(reports), _ptr(traces), _stream(stream)))
     return reports, traces
 
+
+def triangulate(rig: Rig, settings: Settings, point_obs_begin, poses, obs_pose, obs_uv, points,
+                obs_cam=None, obs_w=None, reports=None, traces=None, stream=None):
+    """Triangulate every landmark from its observations with the poses fixed
+    (device tensors: int32 index arrays, float64 values; ``points`` is written).
+    Returns (report bytes tensor, trace bytes or None)."""
+    import torch
+    n_points = point_obs_begin.numel() - 1
+    if reports is None:
+        reports = torch.zeros(REPORT_DTYPE.itemsize * max(n_points, 1), dtype=torch.uint8,
+                              device=points.device)
+    _check(lib().ba_triangulate(rig._h, ctypes.byref(settings.c()), n_points, obs_pose.numel(),
+                                poses.shape[0], _ptr(point_obs_begin), _ptr(poses), _ptr(obs_pose),
+                                _ptr(obs_cam), _ptr(obs_uv), _ptr(obs_w), _ptr(points), _ptr(reports),
+                                _ptr(traces), _stream(stream)))
+    return reports, traces

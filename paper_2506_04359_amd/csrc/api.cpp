@@ -19,6 +19,7 @@
 #include "device.hpp"
 #include "plan.hpp"
 #include "pnp.hpp"
+#include "tri.hpp"
 
 namespace ba {
 
@@ -566,6 +567,43 @@ ba_status ba_pnp_solve(ba_rig rig, const ba_settings* s, int32_t n_frames, int64
   A.stream = stream;
   e = s->precision == BA_FP64 ? run_pnp<double>(A) : run_pnp<float>(A);
   if (e != hipSuccess) return hip_fail(e, "motion-only launch");
+  return BA_OK;
+}
+
+ba_status ba_triangulate(ba_rig rig, const ba_settings* s, int32_t n_points, int64_t n_obs,
+                         int32_t n_poses, const int32_t* point_obs_begin, const double* poses,
+                         const int32_t* obs_pose, const int32_t* obs_cam, const double* obs_uv,
+                         const double* obs_w, double* points, ba_report* reports,
+                         ba_iter_trace* traces, void* stream) {
+  if (!rig) return set_error(BA_ERR_INVALID_ARG, "rig is NULL");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  if (n_points < 0 || n_obs < 0 || n_poses < 0) return set_error(BA_ERR_INVALID_ARG, "negative size");
+  if (n_obs > (int64_t)INT32_MAX) return set_error(BA_ERR_UNSUPPORTED, "too many observations");
+  if (n_points == 0) return BA_OK;
+  if (!point_obs_begin || !points || (n_poses > 0 && !poses) || (n_obs > 0 && (!obs_pose || !obs_uv)))
+    return set_error(BA_ERR_INVALID_ARG, "NULL device array");
+  hipError_t e = hipSetDevice(rig->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  TriArgs A;
+  A.cams = rig->cams;
+  A.n_cams = rig->n_cams;
+  A.n_points = n_points;
+  A.n_poses = n_poses;
+  A.n_obs = n_obs;
+  A.point_obs_begin = point_obs_begin;
+  A.poses = poses;
+  A.obs_pose = obs_pose;
+  A.obs_cam = obs_cam;
+  A.obs_uv = obs_uv;
+  A.obs_w = obs_w;
+  A.points = points;
+  A.reports = reports;
+  A.traces = traces;
+  A.settings = dev_settings(s);
+  A.stream = stream;
+  e = s->precision == BA_FP64 ? run_triangulate<double>(A) : run_triangulate<float>(A);
+  if (e != hipSuccess) return hip_fail(e, "triangulation launch");
   return BA_OK;
 }
 

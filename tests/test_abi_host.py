@@ -196,3 +196,13 @@ def test_rig_waves_per_frame_needs_a_rig():
     L = ba.lib()
     assert L.ba_rig_set_waves_per_frame(None, 1) == -1
     assert "rig" in L.ba_last_error().decode()
+
+
+def test_triangulate_argument_errors():
+    import ctypes
+    import paper_2506_04359_amd as ba
+    L = ba.lib()
+    s = ba.Settings().c()
+    assert L.ba_triangulate(None, ctypes.byref(s), 1, 0, 0, None, None, None, None, None, None, None,
+                            None, None, None) == -1
+    assert "rig" in L.ba_last_error().decode()
