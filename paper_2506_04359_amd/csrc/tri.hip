@@ -3,7 +3,9 @@
 // landmarks are triangulated from the multi-view observations of a keyframe
 // before they enter the local map).
 //
-// One lane per landmark; the landmark's observations are a contiguous range.
+// One lane per landmark (a workgroup's landmarks ordered by observation count
+// across its lanes); the landmark's observations are a contiguous range.  When
+// the poses a workgroup reads span at most 128 indices they are copied to LDS.
 //   start     the weighted least-squares intersection of the viewing rays,
 //             (sum w (I - d d^T)) p0 = sum w (I - d d^T) c, by a 3x3 FP64
 //             Cholesky; fewer than two views or a pivot <= 1e-10 trace marks
@@ -28,6 +30,7 @@
 namespace ba {
 
 constexpr int kTriThreads = 256;
+constexpr int kTriPoseCache = 128;   // poses a workgroup keeps in LDS
 
 // Cholesky solve of a 3x3 SPD system stored as (00, 01, 02, 11, 12, 22):
 // x = A^-1 b.  False on a pivot <= floor or a non-finite one.
@@ -52,15 +55,23 @@ __device__ __forceinline__ bool solve3(const double* A, const double* b, double 
   return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
 }
 
+// absent camera indices / weights read one constant entry (stride 0); global
+// memory (not constant) keeps those loads global rather than flat
+__device__ int kTriCamZero = 0;
+__device__ double kTriWeightOne = 1.0;
+
+// Ray start and LM refinement of landmark j (observations [o0, o1), indices
+// already checked).  Pose i is read at P + 12 (i - pbase): the workgroup's
+// LDS copy or the caller's array.
 template <typename Real>
-__global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
-  __shared__ double sCam[kMaxCams * 16];
-  for (int k = threadIdx.x; k < A.n_cams * 16; k += blockDim.x) sCam[k] = A.cams[k];
-  __syncthreads();
-  const int j = blockIdx.x * kTriThreads + threadIdx.x;
-  if (j >= A.n_points) return;
+__device__ __forceinline__ void tri_landmark(const TriArgs& A, int j, long long o0, long long o1,
+                                             const double* sCam, const double* P, int pbase) {
   const DevSettings S = A.settings;
   const double kNaN = __builtin_nan("");
+  const int* cp = A.obs_cam ? A.obs_cam : &kTriCamZero;
+  const long long cstep = A.obs_cam ? 1 : 0;
+  const double* wp = A.obs_w ? A.obs_w : &kTriWeightOne;
+  const long long wstep = A.obs_w ? 1 : 0;
   auto finish = [&](int status, const double* p) {
     A.points[3 * (long long)j] = p ? p[0] : kNaN;
     A.points[3 * (long long)j + 1] = p ? p[1] : kNaN;
@@ -79,49 +90,63 @@ __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
       A.reports[j] = r;
     }
   };
-
-  const long long o0 = A.point_obs_begin[j], o1 = A.point_obs_begin[j + 1];
-  if (!(0 <= o0 && o0 <= o1 && o1 <= A.n_obs)) return finish(2, nullptr);
-  for (long long o = o0; o < o1; ++o) {
-    const int i = A.obs_pose[o], c = A.obs_cam ? A.obs_cam[o] : 0;
-    if (i < 0 || i >= A.n_poses || c < 0 || c >= A.n_cams) return finish(2, nullptr);
-  }
   if (o1 - o0 < 2) return finish(3, nullptr);
+
+  // One observation: pose index, camera, pixel, weight.  The loops below load
+  // observation o + 1 while observation o is computed.
+  struct Ob {
+    int i, c;
+    double u, v, w;
+  };
+  auto load = [&](long long o) {
+    Ob b;
+    b.i = A.obs_pose[o];
+    b.c = cp[o * cstep];
+    b.u = A.obs_uv[2 * o];
+    b.v = A.obs_uv[2 * o + 1];
+    b.w = wp[o * wstep];
+    return b;
+  };
 
   // start: least-squares intersection of the viewing rays
   double M[6] = {0, 0, 0, 0, 0, 0}, mb[3] = {0, 0, 0};
-  for (long long o = o0; o < o1; ++o) {
-    const double* T = A.poses + 12 * (long long)A.obs_pose[o];
-    const double* C = sCam + 16 * (A.obs_cam ? A.obs_cam[o] : 0);
-    const double w = A.obs_w ? A.obs_w[o] : 1.0;
-    double Rcw[9], tcw[3];
+  {
+    Ob cur = load(o0);
+    for (long long o = o0; o < o1; ++o) {
+      const Ob nxt = load(o + 1 < o1 ? o + 1 : o);
+      const double* T = P + 12 * (cur.i - pbase);
+      const double* C = sCam + 16 * cur.c;
+      double Rcw[9], tcw[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+      for (int a = 0; a < 3; ++a) {
 #pragma unroll
-      for (int b = 0; b < 3; ++b)
-        Rcw[3 * a + b] = C[4 + 3 * a] * T[b] + C[5 + 3 * a] * T[4 + b] + C[6 + 3 * a] * T[8 + b];
-      tcw[a] = C[4 + 3 * a] * T[3] + C[5 + 3 * a] * T[7] + C[6 + 3 * a] * T[11] + C[13 + a];
+        for (int b = 0; b < 3; ++b)
+          Rcw[3 * a + b] = C[4 + 3 * a] * T[b] + C[5 + 3 * a] * T[4 + b] + C[6 + 3 * a] * T[8 + b];
+        tcw[a] = C[4 + 3 * a] * T[3] + C[5 + 3 * a] * T[7] + C[6 + 3 * a] * T[11] + C[13 + a];
+      }
+      const double v[3] = {(cur.u - C[2]) / C[0], (cur.v - C[3]) / C[1], 1.0};
+      double d[3], ctr[3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {   // world direction R_cw^T v and centre -R_cw^T t_cw
+        d[b] = Rcw[b] * v[0] + Rcw[3 + b] * v[1] + Rcw[6 + b] * v[2];
+        ctr[b] = -(Rcw[b] * tcw[0] + Rcw[3 + b] * tcw[1] + Rcw[6 + b] * tcw[2]);
+      }
+      const double in = rsqrt_nr(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      d[0] *= in;
+      d[1] *= in;
+      d[2] *= in;
+      const double dc = d[0] * ctr[0] + d[1] * ctr[1] + d[2] * ctr[2];
+      const double w = cur.w;
+      M[0] += w * (1.0 - d[0] * d[0]);
+      M[1] -= w * d[0] * d[1];
+      M[2] -= w * d[0] * d[2];
+      M[3] += w * (1.0 - d[1] * d[1]);
+      M[4] -= w * d[1] * d[2];
+      M[5] += w * (1.0 - d[2] * d[2]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mb[a] += w * (ctr[a] - d[a] * dc);
+      cur = nxt;
     }
-    const double v[3] = {(A.obs_uv[2 * o] - C[2]) / C[0], (A.obs_uv[2 * o + 1] - C[3]) / C[1], 1.0};
-    double d[3], ctr[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {   // world direction R_cw^T v and centre -R_cw^T t_cw
-      d[b] = Rcw[b] * v[0] + Rcw[3 + b] * v[1] + Rcw[6 + b] * v[2];
-      ctr[b] = -(Rcw[b] * tcw[0] + Rcw[3 + b] * tcw[1] + Rcw[6 + b] * tcw[2]);
-    }
-    const double in = rsqrt_nr(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    d[0] *= in;
-    d[1] *= in;
-    d[2] *= in;
-    const double dc = d[0] * ctr[0] + d[1] * ctr[1] + d[2] * ctr[2];
-    M[0] += w * (1.0 - d[0] * d[0]);
-    M[1] -= w * d[0] * d[1];
-    M[2] -= w * d[0] * d[2];
-    M[3] += w * (1.0 - d[1] * d[1]);
-    M[4] -= w * d[1] * d[2];
-    M[5] += w * (1.0 - d[2] * d[2]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) mb[a] += w * (ctr[a] - d[a] * dc);
   }
   double p[3];
   if (!solve3(M, mb, 1e-10 * (M[0] + M[3] + M[5]), p)) return finish(3, nullptr);
@@ -135,15 +160,15 @@ __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
     for (int k = 0; k < 3; ++k) g[k] = 0;
     F = 0.0;
     nbad = 0;
+    Ob cur = load(o0);
     for (long long o = o0; o < o1; ++o) {
-      const double* T = A.poses + 12 * (long long)A.obs_pose[o];
-      const double* C = sCam + 16 * (A.obs_cam ? A.obs_cam[o] : 0);
-      const double w = A.obs_w ? A.obs_w[o] : 1.0;
+      const Ob nxt = load(o + 1 < o1 ? o + 1 : o);
+      const double* T = P + 12 * (cur.i - pbase);
+      const double* C = sCam + 16 * cur.c;
       double xb[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) xb[a] = T[4 * a] * q[0] + T[4 * a + 1] * q[1] + T[4 * a + 2] * q[2] + T[4 * a + 3];
-      const Lin<Real> L = linearise<Real>(xb, C, A.obs_uv[2 * o] - C[2], A.obs_uv[2 * o + 1] - C[3], w,
-                                          S.huber_delta);
+      const Lin<Real> L = linearise<Real>(xb, C, cur.u - C[2], cur.v - C[3], cur.w, S.huber_delta);
       nbad += (L.Z > S.min_depth) ? 0 : 1;
       F += L.rho_w;
       // J rows = (rows of A R_c) R_i
@@ -162,6 +187,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
         for (int c = r; c < 3; ++c, ++e) V[e] = fma(wj1, J1[c], fma(wj0, J0[c], V[e]));
         g[r] = fma(wj1, L.r[1], fma(wj0, L.r[0], g[r]));
       }
+      cur = nxt;
     }
     F *= 0.5;
   };
@@ -234,6 +260,103 @@ __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
     r.reserved = 0;
     A.reports[j] = r;
   }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
+  __shared__ double sCam[kMaxCams * 16];
+  __shared__ double sPose[kTriPoseCache * 12];
+  __shared__ int sCount[kTriThreads];
+  __shared__ int sOrder[kTriThreads];
+  __shared__ int sRange[2][kTriThreads / 64];
+  for (int k = threadIdx.x; k < A.n_cams * 16; k += blockDim.x) sCam[k] = A.cams[k];
+  // Lanes take the workgroup's landmarks in order of observation count (ties
+  // by index), so that the lanes of a wave run loops of similar length.
+  {
+    const int jj = blockIdx.x * kTriThreads + threadIdx.x;
+    long long n = 1ll << 30;   // past the end: sorted last
+    if (jj < A.n_points) {
+      n = (long long)A.point_obs_begin[jj + 1] - A.point_obs_begin[jj];
+      n = n < 0 ? 0 : (n > (1ll << 29) ? (1ll << 29) : n);
+    }
+    sCount[threadIdx.x] = (int)n;
+    __syncthreads();
+    int rank = 0;
+    for (int k = 0; k < kTriThreads; ++k) {
+      const int c = sCount[k];
+      rank += (c < (int)n || (c == (int)n && k < (int)threadIdx.x)) ? 1 : 0;
+    }
+    sOrder[rank] = threadIdx.x;
+    __syncthreads();
+  }
+  const int j = blockIdx.x * kTriThreads + sOrder[threadIdx.x];
+
+  // structure checks, and the range of pose indices the workgroup reads
+  int status = 0, pmin = 0x7fffffff, pmax = -1;
+  long long o0 = 0, o1 = 0;
+  if (j < A.n_points) {
+    o0 = A.point_obs_begin[j];
+    o1 = A.point_obs_begin[j + 1];
+    if (!(0 <= o0 && o0 <= o1 && o1 <= A.n_obs)) {
+      status = 2;
+    } else {
+      for (long long o = o0; o < o1; ++o) {
+        const int i = A.obs_pose[o], c = A.obs_cam ? A.obs_cam[o] : 0;
+        if (i < 0 || i >= A.n_poses || c < 0 || c >= A.n_cams) status = 2;
+        pmin = i < pmin ? i : pmin;
+        pmax = i > pmax ? i : pmax;
+      }
+    }
+    if (status) pmin = 0x7fffffff, pmax = -1;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int a = __shfl_xor(pmin, m), b = __shfl_xor(pmax, m);
+    pmin = a < pmin ? a : pmin;
+    pmax = b > pmax ? b : pmax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sRange[0][threadIdx.x >> 6] = pmin;
+    sRange[1][threadIdx.x >> 6] = pmax;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kTriThreads / 64; ++w) {
+    pmin = sRange[0][w] < pmin ? sRange[0][w] : pmin;
+    pmax = sRange[1][w] > pmax ? sRange[1][w] : pmax;
+  }
+  // every index was checked against n_poses, so [pmin, pmax] is in range
+  const bool cached = pmax >= pmin && pmax - pmin < kTriPoseCache;
+  if (cached) {
+    const int n = 12 * (pmax - pmin + 1);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) sPose[k] = A.poses[12 * (long long)pmin + k];
+  }
+  __syncthreads();
+  if (j >= A.n_points) return;
+  if (status) {
+    const double kNaN = __builtin_nan("");
+    A.points[3 * (long long)j] = kNaN;
+    A.points[3 * (long long)j + 1] = kNaN;
+    A.points[3 * (long long)j + 2] = kNaN;
+    if (A.reports) {
+      ba_report r;
+      r.initial_cost = kNaN;
+      r.final_cost = kNaN;
+      r.final_lambda = A.settings.lambda_init;
+      r.iters = 0;
+      r.accepted = 0;
+      r.chol_failures = 0;
+      r.depth_rejects = 0;
+      r.status = 2;
+      r.reserved = 0;
+      A.reports[j] = r;
+    }
+    return;
+  }
+  if (cached)
+    tri_landmark<Real>(A, j, o0, o1, sCam, sPose, pmin);
+  else
+    tri_landmark<Real>(A, j, o0, o1, sCam, A.poses, 0);
 }
 
 template <typename Real>
