@@ -659,3 +659,110 @@ def make_tri_batch(windows: List[Window], max_iters: int = 10, name: str = "") -
                     obs_pose=np.concatenate(op).astype(np.int32), obs_cam=np.concatenate(oc).astype(np.int32),
                     obs_uv=np.concatenate(uv), obs_w=np.concatenate(ow), max_iters=max_iters,
                     huber_delta=windows[0].huber_delta, lambda_init=windows[0].lambda_init, name=name)
+
+
+# ---------------------------------------------------------------------------
+# pose graphs: a helical multi-lap trajectory with odometry and loop-closure
+# edges
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PoseGraphData:
+    poses_gt: np.ndarray      # (N, 3, 4) world-from-base
+    poses_init: np.ndarray    # (N, 3, 4) dead reckoning from the noisy odometry
+    edge_i: np.ndarray        # (E,) int32
+    edge_j: np.ndarray        # (E,) int32
+    deltas: np.ndarray        # (E, 3, 4) measured T_i^-1 T_j
+    edge_w: np.ndarray        # (E,)
+    pose_fixed: np.ndarray    # (N,) uint8
+    loop: np.ndarray          # (E,) bool, True for loop-closure edges
+    max_iters: int = 10
+    lambda_init: float = 1e-3
+    name: str = ""
+
+    @property
+    def n_poses(self):
+        return int(self.poses_gt.shape[0])
+
+    @property
+    def n_edges(self):
+        return int(self.edge_i.shape[0])
+
+
+def _se3_exp_small(xi):
+    """Exp of (rho, phi) (generator only; uses the rotation-vector formula)."""
+    phi = np.asarray(xi[3:], float)
+    th = float(np.linalg.norm(phi))
+    K = np.array([[0.0, -phi[2], phi[1]], [phi[2], 0.0, -phi[0]], [-phi[1], phi[0], 0.0]])
+    if th < 1e-8:
+        R, V = np.eye(3) + K, np.eye(3) + 0.5 * K
+    else:
+        R = np.eye(3) + math.sin(th) / th * K + (1 - math.cos(th)) / th ** 2 * K @ K
+        V = np.eye(3) + (1 - math.cos(th)) / th ** 2 * K + (th - math.sin(th)) / th ** 3 * K @ K
+    return np.concatenate([R, (V @ np.asarray(xi[:3], float))[:, None]], axis=1)
+
+
+def make_pose_graph(laps: int = 3, per_lap: int = 500, radius: float = 10.0, rise: float = 0.5,
+                    sigma_rot: float = 0.002, sigma_trans: float = 0.01, loop_prob: float = 0.5,
+                    seed: int = 9000, max_iters: int = 10, name: str = "") -> PoseGraphData:
+    """A helix of ``laps`` turns (radius ``radius`` m, ``rise`` m per turn) with
+    ``per_lap`` keyframes per turn, heading along the track.  Odometry edges join
+    consecutive keyframes; each keyframe after the first turn gets loop
+    closures to the keyframes at the same place one turn earlier (offsets -1, 0,
+    +1, each kept with probability ``loop_prob``).  Every measured delta is the
+    true one times Exp of N(0, sigma^2) noise (per component, rotation and
+    translation); the initial poses are dead reckoning from pose 0 along the
+    noisy odometry.  Pose 0 is fixed."""
+    rng = np.random.default_rng(seed)
+    n = laps * per_lap
+    gt = np.zeros((n, 3, 4))
+    for k in range(n):
+        a = 2 * math.pi * k / per_lap
+        c = np.array([radius * math.cos(a), rise * k / per_lap, radius * math.sin(a)])
+        # base x along the track, y up
+        fwd = np.array([-math.sin(a), 0.0, math.cos(a)])
+        up = np.array([0.0, 1.0, 0.0])
+        side = np.cross(fwd, up)
+        R = np.stack([fwd, up, side], axis=1)
+        gt[k, :, :3] = R
+        gt[k, :, 3] = c
+    inv = lambda T: np.concatenate([T[:, :3].T, (-T[:, :3].T @ T[:, 3])[:, None]], axis=1)
+    comp = lambda A, B: np.concatenate([A[:, :3] @ B[:, :3], (A[:, :3] @ B[:, 3] + A[:, 3])[:, None]], axis=1)
+
+    def measure(i, j):
+        D = comp(inv(gt[i]), gt[j])
+        xi = np.concatenate([rng.normal(0, sigma_trans, 3), rng.normal(0, sigma_rot, 3)])
+        return comp(_se3_exp_small(xi), D)
+
+    ei, ej, ds, lp = [], [], [], []
+    for k in range(n - 1):
+        ei.append(k)
+        ej.append(k + 1)
+        ds.append(measure(k, k + 1))
+        lp.append(False)
+    for k in range(per_lap, n):
+        for off in (-1, 0, 1):
+            j0 = k - per_lap + off
+            if 0 <= j0 < k - 1 and rng.uniform() < loop_prob:
+                ei.append(j0)
+                ej.append(k)
+                ds.append(measure(j0, k))
+                lp.append(True)
+    init = np.zeros_like(gt)
+    init[0] = gt[0]
+    for k in range(n - 1):
+        init[k + 1] = comp(init[k], ds[k])
+    fixed = np.zeros(n, np.uint8)
+    fixed[0] = 1
+    return PoseGraphData(poses_gt=gt, poses_init=init, edge_i=np.asarray(ei, np.int32),
+                         edge_j=np.asarray(ej, np.int32), deltas=np.asarray(ds), edge_w=np.ones(len(ei)),
+                         pose_fixed=fixed, loop=np.asarray(lp), max_iters=max_iters, name=name)
+
+
+PGO_WORKLOADS = {
+    "pgo-helix-3x500": dict(laps=3, per_lap=500),
+}
+
+
+def make_pgo_workload(name: str, seed: int = 9000) -> PoseGraphData:
+    return make_pose_graph(seed=seed, name=name, **PGO_WORKLOADS[name])
