@@ -20,6 +20,8 @@ Printed as one JSON line:
                      LM attempts per second
   triangulation      every landmark of the 256 windows re-triangulated from its
                      observations (poses at ground truth): landmarks per second
+  pgo                pose-graph optimisation of a 1500-pose, 2988-edge helix
+                     (odometry and loop closures): LM attempts per second
   rms_check          final RMS of sampled windows against the FP64 oracle (1e-3 px)
   roofline           the linearise + Schur kernel (pass A) against the FP32 ALU peak
                      (pnp.*.roofline, triangulation.roofline: the motion-only and
@@ -134,6 +136,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-pnp", action="store_true", help="skip the motion-only frames")
     ap.add_argument("--no-tri", action="store_true", help="skip the triangulation leg")
+    ap.add_argument("--no-pgo", action="store_true", help="skip the pose-graph leg")
     ap.add_argument("--chunk-obs", type=int, default=None,
                     help="fixed observations per work item instead of the autotuned value")
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -406,6 +409,45 @@ def main():
                          "avg_launch_ms": ms_t}}
         log(f"triangulation: {ms_t:.3f} ms for {tb.n_points} landmarks ({tb.n_obs} observations)")
         del rig
+
+    # pose-graph optimisation of the 1500-pose helix
+    if not args.no_pgo:
+        pg = bagen.make_pgo_workload("pgo-helix-3x500")
+        graph = ba.Graph(pg.n_poses, pg.edge_i, pg.edge_j, pg.pose_fixed)
+        sg = ba.Settings(max_iters=pg.max_iters, precision=ba.BA_FP64, lambda_init=pg.lambda_init)
+        P0g = torch.tensor(pg.poses_init.reshape(-1, 12), dtype=torch.float64, device=dev)
+        Pg = P0g.clone()
+        Dg = torch.tensor(pg.deltas.reshape(-1, 12), dtype=torch.float64, device=dev)
+        wsz = graph.workspace_size()
+        wsg_raw = torch.empty(wsz + 256, dtype=torch.uint8, device=dev)
+        o = (-wsg_raw.data_ptr()) % 256
+        wsg = wsg_raw[o:o + wsz]
+        rg = torch.zeros(48, dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            Pg.copy_(P0g)
+            ba.pgo_solve(graph, sg, Pg, Dg, wsg, report=rg)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            Pg.copy_(P0g)
+            b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b0.record()
+            ba.pgo_solve(graph, sg, Pg, Dg, wsg, report=rg)
+            b1.record()
+            evs.append((b0, b1))
+        torch.cuda.synchronize()
+        ms_g = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+        rep_g = ba.parse_reports(rg)[0]
+        info = graph.info()
+        out["pgo"] = {"workload": "pgo-helix-3x500", "poses": pg.n_poses, "edges": pg.n_edges,
+                      "free_poses": info["n_free"], "factor_blocks": info["n_blocks"],
+                      "tree_levels": info["n_levels"], "lm_attempts": pg.max_iters, "ms_per_solve": ms_g,
+                      "lm_iters_per_s": pg.max_iters / (ms_g / 1e3),
+                      "edges_per_s": pg.n_edges * (1 + pg.max_iters) / (ms_g / 1e3),
+                      "initial_cost": float(rep_g["initial_cost"]), "final_cost": float(rep_g["final_cost"])}
+        log(f"pgo: {ms_g:.3f} ms per solve ({pg.n_poses} poses, {pg.n_edges} edges, "
+            f"{info['n_levels']} levels)")
+        del graph
 
     # oracle on the host: bounded sample, also the RMS check of those windows
     sample = list(range(min(args.cpu_sample, N_WINDOWS)))

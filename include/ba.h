@@ -314,6 +314,63 @@ ba_status ba_triangulate(ba_rig rig, const ba_settings* s, int32_t n_points, int
                          const double* obs_w, double* points, ba_report* reports,
                          ba_iter_trace* traces, void* stream);
 
+/* -------------------------------------------------------------------------
+ * Pose-graph optimisation (paper Sec. 2.3, Eq. 15): keyframe poses T_i
+ * (WORLD-from-base here, so that T_i^-1 T_j is the pose of base j in base i)
+ * minimise 1/2 sum_e w_e |Log(D_ij^-1 T_i^-1 T_j)|^2 over the graph's edges,
+ * with D_ij the measured pose deltas (integrated frontend predictions or loop
+ * closures) and Log the SE(3) logarithm, xi = (rho, phi).  Poses flagged fixed
+ * are held.  Exactly s->max_iters LM attempts with the damping, Cholesky-failure
+ * and strict-decrease rules of ba_solve (left perturbation T <- Exp(xi) T);
+ * the linear systems are solved by a sparse block Cholesky ordered by nested
+ * dissection.  Always FP64 (s->precision is ignored); huber_delta and
+ * min_depth do not apply.
+ * ------------------------------------------------------------------------- */
+
+typedef struct ba_graph_s* ba_graph;   /* a pose graph's structure on one device */
+
+/* Plan a graph: edge e joins poses edge_i[e] and edge_j[e] (HOST arrays, n_edges
+ * each, indices in [0, n_poses), edge_i != edge_j); pose_fixed: HOST, n_poses,
+ * NULL -> pose 0 fixed.  Orders the free poses, computes the factor's pattern
+ * and uploads the plan to the current device (flags BA_CREATE_HOST_ONLY: host
+ * plan only, for ba_graph_info / ba_graph_plan_array; such a handle cannot
+ * solve).  Errors: INVALID_ARG (bad indices, sizes or flags), OOM / HIP.  The
+ * library owns the handle; ba_graph_destroy frees it. */
+ba_status ba_graph_create(int32_t n_poses, int32_t n_edges, const int32_t* edge_i,
+                          const int32_t* edge_j, const uint8_t* pose_fixed, int32_t flags,
+                          ba_graph* out);
+
+/* Host view of one plan table (for inspection and tests; valid while the
+ * handle lives): which = 0 col_of_pose, 1 pose_of_col, 2 lev_ptr, 3 blk_ptr,
+ * 4 blk_row, 5 upd_ptr, 6 upd_a, 7 upd_b, 8 fwd_ptr, 9 fwd_blk, 10 fwd_col,
+ * 11 asm_ptr, 12 asm_edge, 13 rhs_ptr, 14 rhs_edge.  Columns are in
+ * elimination order grouped by level; a column's blocks are its diagonal block
+ * then its off-diagonal blocks by increasing row; block b of the update list
+ * of target t contributes L_{upd_a} L_{upd_b}^T; asm/rhs entries are 2 e + s
+ * (s = 1: subtracted).  Errors: INVALID_ARG. */
+ba_status ba_graph_plan_array(ba_graph g, int32_t which, const int32_t** data, int64_t* len);
+void ba_graph_destroy(ba_graph g);
+
+/* Free poses, levels of the elimination tree and 6x6 blocks of the factor (any
+ * output may be NULL).  Errors: INVALID_ARG (NULL graph). */
+ba_status ba_graph_info(ba_graph g, int32_t* n_free, int32_t* n_levels, int32_t* n_blocks);
+
+/* Workspace bytes ba_pgo_solve needs for this graph.  Errors: INVALID_ARG. */
+ba_status ba_graph_workspace_size(ba_graph g, size_t* bytes);
+
+/* Solve in place.  DEVICE arrays on the graph's device:
+ *   poses     : n_poses x 12 [R | t] world-from-base, row-major, in/out
+ *   deltas    : n_edges x 12 [R | t] measured D_ij (pose of base j in base i)
+ *   edge_w    : n_edges weights, or NULL (all 1)
+ *   workspace : >= ba_graph_workspace_size bytes, 256-byte aligned, caller-owned
+ *   report    : 1 ba_report or NULL; traces: max_iters ba_iter_trace or NULL
+ * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, STATE (host-only handle), HIP.
+ * Allocates nothing and does not synchronise (capturable); calls that share a
+ * workspace must be ordered on one stream. */
+ba_status ba_pgo_solve(ba_graph g, const ba_settings* s, double* poses, const double* deltas,
+                       const double* edge_w, void* workspace, size_t ws_bytes, ba_report* report,
+                       ba_iter_trace* traces, void* stream);
+
 const char* ba_status_string(ba_status s);
 const char* ba_last_error(void);
 

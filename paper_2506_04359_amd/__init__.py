@@ -28,6 +28,8 @@ from ._binding import (  # noqa: F401
     parse_traces,
     pnp_solve,
     triangulate,
+    Graph,
+    pgo_solve,
     solve,
     solve_batched,
 )

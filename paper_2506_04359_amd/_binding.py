@@ -85,6 +85,13 @@ def lib():
         L.ba_rig_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.ba_rig_destroy.argtypes = [vp]
         L.ba_rig_set_waves_per_frame.argtypes = [vp, i32]
+        L.ba_graph_create.argtypes = [i32, i32, vp, vp, vp, i32, ctypes.POINTER(vp)]
+        L.ba_graph_destroy.argtypes = [vp]
+        L.ba_graph_info.argtypes = [vp, vp, vp, vp]
+        L.ba_graph_plan_array.argtypes = [vp, i32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                          ctypes.POINTER(i64)]
+        L.ba_graph_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ba_pgo_solve.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, ctypes.c_size_t, vp, vp, vp]
         L.ba_triangulate.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i32, vp, vp, vp, vp, vp, vp,
                                      vp, vp, vp, vp]
         L.ba_pnp_solve.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i64, vp, vp, vp, vp, vp,
@@ -95,7 +102,8 @@ def lib():
         for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
                   "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_batched",
                   "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
-                  "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate"):
+                  "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate", "ba_graph_create", "ba_graph_info",
+                  "ba_graph_plan_array", "ba_graph_workspace_size", "ba_pgo_solve"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -385,3 +393,67 @@ def triangulate(rig: Rig, settings: Settings, point_obs_begin, poses, obs_pose, 
                                 _ptr(obs_cam), _ptr(obs_uv), _ptr(obs_w), _ptr(points), _ptr(reports),
                                 _ptr(traces), _stream(stream)))
     return reports, traces
+
+
+PLAN_TABLES = ("col_of_pose", "pose_of_col", "lev_ptr", "blk_ptr", "blk_row", "upd_ptr", "upd_a",
+               "upd_b", "fwd_ptr", "fwd_blk", "fwd_col", "asm_ptr", "asm_edge", "rhs_ptr", "rhs_edge")
+
+
+class Graph:
+    """A pose graph's structure (host arrays); planned for the current device
+    unless ``host_only``."""
+
+    def __init__(self, n_poses, edge_i, edge_j, pose_fixed=None, host_only=False):
+        ei = _host(edge_i, np.int32)
+        ej = _host(edge_j, np.int32)
+        fx = None if pose_fixed is None else _host(pose_fixed, np.uint8)
+        self.n_poses, self.n_edges = int(n_poses), int(ei.shape[0])
+        self._h = ctypes.c_void_p()
+        _check(lib().ba_graph_create(self.n_poses, self.n_edges, ei.ctypes.data_as(ctypes.c_void_p),
+                                     ej.ctypes.data_as(ctypes.c_void_p),
+                                     None if fx is None else fx.ctypes.data_as(ctypes.c_void_p),
+                                     BA_CREATE_HOST_ONLY if host_only else 0, ctypes.byref(self._h)))
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ba_graph_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(n_free=a.value, n_levels=b.value, n_blocks=c.value)
+
+    def plan(self):
+        """Every plan table as a numpy array (copies)."""
+        out = {}
+        for k, name in enumerate(PLAN_TABLES):
+            ptr = ctypes.POINTER(ctypes.c_int32)()
+            n = ctypes.c_int64()
+            _check(lib().ba_graph_plan_array(self._h, k, ctypes.byref(ptr), ctypes.byref(n)))
+            out[name] = np.ctypeslib.as_array(ptr, shape=(n.value,)).copy() if n.value else np.zeros(0, np.int32)
+        return out
+
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        _check(lib().ba_graph_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ba_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pgo_solve(graph: Graph, settings: Settings, poses, deltas, workspace, edge_w=None, report=None,
+              traces=None, stream=None):
+    """In-place pose-graph solve (device tensors, float64; ``workspace`` a uint8
+    tensor of at least ``graph.workspace_size()`` bytes).  Returns (report bytes
+    tensor, trace bytes or None)."""
+    import torch
+    if report is None:
+        report = torch.zeros(REPORT_DTYPE.itemsize, dtype=torch.uint8, device=poses.device)
+    _check(lib().ba_pgo_solve(graph._h, ctypes.byref(settings.c()), _ptr(poses), _ptr(deltas), _ptr(edge_w),
+                              _ptr(workspace), workspace.numel(), _ptr(report), _ptr(traces), _stream(stream)))
+    return report, traces

@@ -39,6 +39,10 @@ def build(verbose: bool = False) -> str:
                                                           "-o", os.path.join(obj, "pnp.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "tri.hip"),
                                                           "-o", os.path.join(obj, "tri.o")],
+        [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "pgo.hip"),
+                                                          "-o", os.path.join(obj, "pgo.o")],
+        [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "pgo_plan.cpp"),
+                                                          "-o", os.path.join(obj, "pgo_plan.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "api.cpp"),
                                                           "-o", os.path.join(obj, "api.o")],
         ["g++"] + COMMON + ["-c", os.path.join(CSRC, "plan.cpp"), "-o", os.path.join(obj, "plan.o")],
@@ -50,7 +54,8 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     _run([HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp,
                                    os.path.join(obj, "kernels.o"), os.path.join(obj, "pnp.o"),
-                                   os.path.join(obj, "tri.o"),
+                                   os.path.join(obj, "tri.o"), os.path.join(obj, "pgo.o"),
+                                   os.path.join(obj, "pgo_plan.o"),
                                    os.path.join(obj, "api.o"),
                                    os.path.join(obj, "plan.o")])
     os.replace(tmp, OUT)

@@ -20,6 +20,7 @@
 #include "plan.hpp"
 #include "pnp.hpp"
 #include "tri.hpp"
+#include "pgo.hpp"
 
 namespace ba {
 
@@ -604,6 +605,142 @@ ba_status ba_triangulate(ba_rig rig, const ba_settings* s, int32_t n_points, int
   A.stream = stream;
   e = s->precision == BA_FP64 ? run_triangulate<double>(A) : run_triangulate<float>(A);
   if (e != hipSuccess) return hip_fail(e, "triangulation launch");
+  return BA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pose-graph optimisation
+// ---------------------------------------------------------------------------
+
+struct ba_graph_s {
+  PgoPlan plan;
+  int device = 0;
+  void* mem = nullptr;
+  PgoDev dev{};
+  ~ba_graph_s() {
+    if (mem) (void)hipFree(mem);
+  }
+};
+
+ba_status ba_graph_create(int32_t n_poses, int32_t n_edges, const int32_t* edge_i,
+                          const int32_t* edge_j, const uint8_t* pose_fixed, int32_t flags,
+                          ba_graph* out) {
+  if (!out) return set_error(BA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (flags & ~BA_CREATE_HOST_ONLY) return set_error(BA_ERR_INVALID_ARG, "unknown flags");
+  std::unique_ptr<ba_graph_s> g(new (std::nothrow) ba_graph_s());
+  if (!g) return set_error(BA_ERR_OOM, "host allocation failed");
+  const std::string err = build_pgo_plan(n_poses, n_edges, edge_i, edge_j, pose_fixed, g->plan);
+  if (!err.empty()) return set_error(BA_ERR_INVALID_ARG, err);
+  const PgoPlan& P = g->plan;
+  if (flags & BA_CREATE_HOST_ONLY) {
+    *out = g.release();
+    return BA_OK;
+  }
+  Blob blob;
+  const size_t o_cop = blob.add(P.col_of_pose), o_poc = blob.add(P.pose_of_col),
+               o_lev = blob.add(P.lev_ptr), o_bp = blob.add(P.blk_ptr), o_br = blob.add(P.blk_row),
+               o_up = blob.add(P.upd_ptr), o_ua = blob.add(P.upd_a), o_ub = blob.add(P.upd_b),
+               o_fp = blob.add(P.fwd_ptr), o_fb = blob.add(P.fwd_blk), o_fc = blob.add(P.fwd_col),
+               o_ap = blob.add(P.asm_ptr), o_ae = blob.add(P.asm_edge), o_rp = blob.add(P.rhs_ptr),
+               o_re = blob.add(P.rhs_edge), o_ei = blob.add(P.edge_i), o_ej = blob.add(P.edge_j);
+  hipError_t e = hipGetDevice(&g->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipMalloc(&g->mem, blob.size);
+  if (e != hipSuccess) {
+    g->mem = nullptr;
+    return set_error(BA_ERR_OOM, "graph plan: hipMalloc failed");
+  }
+  for (auto& part : blob.parts)
+    if (!part.second.empty()) {
+      e = hipMemcpy((char*)g->mem + part.first, part.second.data(), part.second.size(),
+                    hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "graph plan upload");
+    }
+  auto at = [&](size_t off) { return (const int32_t*)((char*)g->mem + off); };
+  PgoDev& D = g->dev;
+  D.n_poses = P.n_poses;
+  D.n_edges = P.n_edges;
+  D.n_free = P.n_free;
+  D.n_levels = P.n_levels;
+  D.n_blocks = P.n_blocks();
+  D.col_of_pose = at(o_cop);
+  D.pose_of_col = at(o_poc);
+  D.lev_ptr = at(o_lev);
+  D.blk_ptr = at(o_bp);
+  D.blk_row = at(o_br);
+  D.upd_ptr = at(o_up);
+  D.upd_a = at(o_ua);
+  D.upd_b = at(o_ub);
+  D.fwd_ptr = at(o_fp);
+  D.fwd_blk = at(o_fb);
+  D.fwd_col = at(o_fc);
+  D.asm_ptr = at(o_ap);
+  D.asm_edge = at(o_ae);
+  D.rhs_ptr = at(o_rp);
+  D.rhs_edge = at(o_re);
+  D.edge_i = at(o_ei);
+  D.edge_j = at(o_ej);
+  *out = g.release();
+  return BA_OK;
+}
+
+void ba_graph_destroy(ba_graph g) { delete g; }
+
+ba_status ba_graph_info(ba_graph g, int32_t* n_free, int32_t* n_levels, int32_t* n_blocks) {
+  if (!g) return set_error(BA_ERR_INVALID_ARG, "graph is NULL");
+  if (n_free) *n_free = g->plan.n_free;
+  if (n_levels) *n_levels = g->plan.n_levels;
+  if (n_blocks) *n_blocks = g->plan.n_blocks();
+  return BA_OK;
+}
+
+ba_status ba_graph_plan_array(ba_graph g, int32_t which, const int32_t** data, int64_t* len) {
+  if (!g || !data || !len) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  const PgoPlan& P = g->plan;
+  const std::vector<int32_t>* v[] = {&P.col_of_pose, &P.pose_of_col, &P.lev_ptr, &P.blk_ptr,
+                                     &P.blk_row, &P.upd_ptr, &P.upd_a, &P.upd_b, &P.fwd_ptr,
+                                     &P.fwd_blk, &P.fwd_col, &P.asm_ptr, &P.asm_edge, &P.rhs_ptr,
+                                     &P.rhs_edge};
+  if (which < 0 || which >= (int)(sizeof(v) / sizeof(v[0])))
+    return set_error(BA_ERR_INVALID_ARG, "unknown plan table");
+  *data = v[which]->data();
+  *len = (int64_t)v[which]->size();
+  return BA_OK;
+}
+
+ba_status ba_graph_workspace_size(ba_graph g, size_t* bytes) {
+  if (!g || !bytes) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  *bytes = pgo_workspace_bytes(g->plan);
+  return BA_OK;
+}
+
+ba_status ba_pgo_solve(ba_graph g, const ba_settings* s, double* poses, const double* deltas,
+                       const double* edge_w, void* workspace, size_t ws_bytes, ba_report* report,
+                       ba_iter_trace* traces, void* stream) {
+  if (!g) return set_error(BA_ERR_INVALID_ARG, "graph is NULL");
+  if (!g->mem) return set_error(BA_ERR_STATE, "graph planned host-only");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  if (!poses || (g->plan.n_edges > 0 && !deltas)) return set_error(BA_ERR_INVALID_ARG, "NULL device array");
+  const size_t need = pgo_workspace_bytes(g->plan);
+  if (!workspace || ws_bytes < need)
+    return set_error(BA_ERR_WORKSPACE_TOO_SMALL, "workspace below ba_graph_workspace_size");
+  if (((uintptr_t)workspace) & 255) return set_error(BA_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  hipError_t e = hipSetDevice(g->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  PgoArgs A;
+  A.G = g->dev;
+  A.W = pgo_carve(g->plan, workspace);
+  A.poses = poses;
+  A.deltas = deltas;
+  A.edge_w = edge_w;
+  A.report = report;
+  A.traces = traces;
+  A.settings = dev_settings(s);
+  A.stream = stream;
+  e = run_pgo(A);
+  if (e != hipSuccess) return hip_fail(e, "pose-graph launch");
   return BA_OK;
 }
 

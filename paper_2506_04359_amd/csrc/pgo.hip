@@ -1,0 +1,493 @@
+// gfx950 pose-graph optimisation (paper Sec. 2.3, Eq. 15): LM over the
+// world-from-base poses T_i minimising 1/2 sum_e w_e |Log(D_ij^-1 T_i^-1 T_j)|^2.
+//
+// Per LM attempt two launches:
+//   k_pgo_edges  one thread per edge at the candidate poses: r = Log(E),
+//                E = D^-1 T_i^-1 T_j, B = J_l(r)^-1 Ad(D^-1 T_i^-1) (so dr/dxi_j
+//                = B, dr/dxi_i = -B for the left perturbation), and w B^T B,
+//                w B^T r, w |r|^2 into an edge buffer (two buffers: the current
+//                linearisation and the candidate's)
+//   k_pgo_step   one 1024-thread workgroup: the candidate's cost (fixed-order
+//                sum), accept iff it strictly drops, lambda; then the damped
+//                normal equations gathered from the current edge buffer into
+//                the blocks of the factor, the sparse block Cholesky level by
+//                level of the elimination tree (left-looking: each column
+//                gathers its updates, factors its diagonal block, solves its
+//                panel; forward substitution rides along), back substitution
+//                level by level, and the next candidate Exp(d_i) T_i.
+// Every sum has a fixed order and nothing uses atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device.hpp"
+#include "geometry.hpp"
+#include "pgo.hpp"
+
+namespace ba {
+
+constexpr int kPgoEdgeThreads = 256;
+constexpr int kPgoStepThreads = 1024;
+
+// 3x3 helpers (row-major)
+__device__ __forceinline__ void mm3(const double* A, const double* B, double* C) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) C[3 * a + b] = A[3 * a] * B[b] + A[3 * a + 1] * B[3 + b] + A[3 * a + 2] * B[6 + b];
+}
+__device__ __forceinline__ void skew3(const double* v, double* K) {
+  K[0] = 0.0; K[1] = -v[2]; K[2] = v[1];
+  K[3] = v[2]; K[4] = 0.0; K[5] = -v[0];
+  K[6] = -v[1]; K[7] = v[0]; K[8] = 0.0;
+}
+// C = A B for 3x4 transforms; inverse of a 3x4 transform
+__device__ __forceinline__ void tcompose(const double* A, const double* B, double* C) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) C[4 * a + b] = A[4 * a] * B[b] + A[4 * a + 1] * B[4 + b] + A[4 * a + 2] * B[8 + b];
+    C[4 * a + 3] = A[4 * a] * B[3] + A[4 * a + 1] * B[7] + A[4 * a + 2] * B[11] + A[4 * a + 3];
+  }
+}
+__device__ __forceinline__ void tinverse(const double* T, double* I) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) I[4 * a + b] = T[4 * b + a];
+    I[4 * a + 3] = -(T[a] * T[3] + T[4 + a] * T[7] + T[8 + a] * T[11]);
+  }
+}
+
+// Log of a rotation: phi with Exp(phi) = R.  theta = atan2(|v|, (tr R - 1) / 2)
+// with v the vee of the antisymmetric part (sin(theta) times the axis); the
+// axis from the symmetric part near theta = pi.
+__device__ __forceinline__ void log_so3(const double* T /*3x4*/, double* phi) {
+  const double v[3] = {0.5 * (T[9] - T[6]), 0.5 * (T[2] - T[8]), 0.5 * (T[4] - T[1])};
+  double c = 0.5 * (T[0] + T[5] + T[10] - 1.0);
+  c = fmin(1.0, fmax(-1.0, c));
+  const double s = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double th = atan2(s, c);
+  if (c > -0.999) {
+    // theta / sin(theta); series below theta = 1e-3
+    const double t2 = th * th;
+    const double f = th < 1e-3 ? 1.0 + t2 * (1.0 / 6.0 + t2 * (7.0 / 360.0)) : th / s;
+    phi[0] = f * v[0];
+    phi[1] = f * v[1];
+    phi[2] = f * v[2];
+    return;
+  }
+  // (R + R^T) / 2 = c I + (1 - c) a a^T
+  const double Md[3] = {T[0] - c, T[5] - c, T[10] - c};
+  int k = 0;
+  if (Md[1] > Md[k]) k = 1;
+  if (Md[2] > Md[k]) k = 2;
+  const double ic = 1.0 / (1.0 - c);
+  double a[3];
+  a[k] = sqrt(fmax(Md[k] * ic, 0.0));
+  const double ia = 1.0 / a[k];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    if (m != k) a[m] = 0.5 * (T[4 * m + k] + T[4 * k + m]) * ic * ia;
+  const double sg = (a[0] * v[0] + a[1] * v[1] + a[2] * v[2]) < 0.0 ? -1.0 : 1.0;
+  phi[0] = sg * th * a[0];
+  phi[1] = sg * th * a[1];
+  phi[2] = sg * th * a[2];
+}
+
+// Inverse of the SO(3) left Jacobian: I - K/2 + d K^2, d = 1/th^2 -
+// cot(th/2) / (2 th) (series below th = 0.1).
+__device__ __forceinline__ void jl_inv_so3(const double* phi, double* Ji) {
+  const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  double d;
+  if (t2 < 1e-2) {
+    d = 1.0 / 12.0 + t2 * (1.0 / 720.0 + t2 * (1.0 / 30240.0 + t2 * (1.0 / 1209600.0)));
+  } else {
+    const double th = sqrt(t2);
+    d = 1.0 / t2 - cos(0.5 * th) / (sin(0.5 * th) * 2.0 * th);
+  }
+  double K[9], K2[9];
+  skew3(phi, K);
+  mm3(K, K, K2);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = ((k % 4 == 0) ? 1.0 : 0.0) - 0.5 * K[k] + d * K2[k];
+}
+
+// Top-right block Q of the SE(3) left Jacobian J_l(rho, phi) =
+// sum_n ad^n / (n+1)!: with ad^n = [[K^n, X_n], [0, K^n]], X_{n+1} = K X_n +
+// P K^n (P = rho^), Q = sum_{n >= 1} X_n / (n+1)!; summed until the bound
+// th^n n |rho| / (n+1)! is below 1e-18 (at most 40 terms).
+__device__ __forceinline__ void jl_q_se3(const double* rho, const double* phi, double* Q) {
+  double K[9], P[9], Kn[9], X[9], t1[9], t2[9];
+  skew3(phi, K);
+  skew3(rho, P);
+  const double th = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+  const double nr = sqrt(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Kn[k] = (k % 4 == 0) ? 1.0 : 0.0;   // K^0
+    X[k] = 0.0;                          // X_0
+    Q[k] = 0.0;
+  }
+  double fact = 1.0;    // (n+1)!
+  double thn = 1.0;     // th^n
+  for (int n = 0; n < 40; ++n) {
+    // X_{n+1} = K X_n + P K^n, K^{n+1} = K K^n
+    mm3(K, X, t1);
+    mm3(P, Kn, t2);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] = t1[k] + t2[k];
+    mm3(K, Kn, t1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Kn[k] = t1[k];
+    fact *= (double)(n + 2);   // (n+2)!
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Q[k] += X[k] / fact;
+    thn *= th;
+    if (thn * (n + 1) * nr / fact < 1e-18 && n >= 1) break;
+  }
+}
+
+__global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_edges(PgoArgs A, int init) {
+  const int e = blockIdx.x * kPgoEdgeThreads + threadIdx.x;
+  if (e >= A.G.n_edges) return;
+  const int cur = A.W.istate[0];
+  double* out = A.W.edge[init ? 0 : 1 - cur] + 28 * (long long)e;
+  const double* P = init ? A.poses : A.W.cand;
+  const double* Ti = P + 12 * (long long)A.G.edge_i[e];
+  const double* Tj = P + 12 * (long long)A.G.edge_j[e];
+  const double* D = A.deltas + 12 * (long long)e;
+  const double w = A.edge_w ? A.edge_w[e] : 1.0;
+  double Di[12], Tii[12], X[12], E[12];
+  tinverse(D, Di);
+  tinverse(Ti, Tii);
+  tcompose(Di, Tii, X);   // D^-1 T_i^-1
+  tcompose(X, Tj, E);     // D^-1 T_i^-1 T_j
+  // r = Log(E) = (J^-1 t, phi)
+  double phi[3], Ji[9], r[6];
+  log_so3(E, phi);
+  jl_inv_so3(phi, Ji);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r[a] = Ji[3 * a] * E[3] + Ji[3 * a + 1] * E[7] + Ji[3 * a + 2] * E[11];
+  r[3] = phi[0];
+  r[4] = phi[1];
+  r[5] = phi[2];
+  // B = J_l(r)^-1 Ad(X) = [[M, N], [0, M]]: M = J^-1 R_X, N = J^-1 (t_X^ R_X - Q M)
+  double Q[9], R[9], M[9], tX[9], K1[9], QM[9], N[9], tmp[9];
+  jl_q_se3(r, phi, Q);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) R[3 * a + b] = X[4 * a + b];
+  mm3(Ji, R, M);
+  const double tv[3] = {X[3], X[7], X[11]};
+  skew3(tv, tX);
+  mm3(tX, R, K1);
+  mm3(Q, M, QM);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) tmp[k] = K1[k] - QM[k];
+  mm3(Ji, tmp, N);
+  // B (6x6) explicitly, then w B^T B (upper), w B^T r, w |r|^2
+  double B[36];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      B[6 * a + b] = M[3 * a + b];
+      B[6 * a + 3 + b] = N[3 * a + b];
+      B[6 * (a + 3) + b] = 0.0;
+      B[6 * (a + 3) + 3 + b] = M[3 * a + b];
+    }
+  int k = 0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = a; b < 6; ++b, ++k) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) v += B[6 * m + a] * B[6 * m + b];
+      out[k] = w * v;
+    }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v += B[6 * m + a] * r[m];
+    out[21 + a] = w * v;
+  }
+  double rr = 0.0;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) rr += r[m] * r[m];
+  out[27] = w * rr;
+}
+
+// upper-triangle index of (a, b) in a 6x6 symmetric block
+__device__ __forceinline__ int up6(int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return 6 * lo - lo * (lo - 1) / 2 + hi - lo;
+}
+
+__global__ __launch_bounds__(kPgoStepThreads) void k_pgo_step(PgoArgs A, int mode, int it, int prepare) {
+  __shared__ double sRed[kPgoStepThreads];
+  __shared__ int sFail;
+  const int tid = threadIdx.x;
+  const PgoDev& G = A.G;
+  const PgoWork& W = A.W;
+  const DevSettings S = A.settings;
+  double* st = W.state;      // 0 F, 1 lambda, 2 F0
+  int32_t* ist = W.istate;   // 0 current buffer, 1 candidate valid, 2 accepted, 3 chol failures
+  const double kNaN = __builtin_nan("");
+
+  // cost of the buffer just evaluated, summed in a fixed order
+  const int cur0 = mode == 0 ? 0 : ist[0];
+  const int ev = mode == 0 ? 0 : 1 - cur0;
+  {
+    double s = 0.0;
+    for (int e = tid; e < G.n_edges; e += kPgoStepThreads) s += W.edge[ev][28 * (long long)e + 27];
+    sRed[tid] = s;
+    __syncthreads();
+    for (int h = kPgoStepThreads / 2; h > 0; h >>= 1) {
+      if (tid < h) sRed[tid] += sRed[tid + h];
+      __syncthreads();
+    }
+  }
+  const double Fe = 0.5 * sRed[0];
+  __syncthreads();
+  int cur = cur0;
+  double F, lam;
+  if (mode == 0) {
+    F = Fe;
+    lam = S.lambda_init;
+    if (tid == 0) {
+      st[0] = F;
+      st[1] = lam;
+      st[2] = F;
+      ist[0] = 0;
+      ist[2] = 0;
+      ist[3] = 0;
+    }
+  } else {
+    F = st[0];
+    lam = st[1];
+    const bool valid = ist[1] != 0;
+    const bool accept = valid && Fe < F;
+    if (tid == 0 && A.traces) {
+      ba_iter_trace tr;
+      tr.cost = F;
+      tr.lambda = lam;
+      tr.cand_cost = valid ? Fe : kNaN;
+      tr.status = valid ? 0 : 1;
+      tr.accepted = accept ? 1 : 0;
+      A.traces[it] = tr;
+    }
+    if (accept) {
+      for (int k = tid; k < 12 * G.n_poses; k += kPgoStepThreads) A.poses[k] = W.cand[k];
+      cur = 1 - cur0;
+      F = Fe;
+    }
+    lam = accept ? fmax(lam / S.lambda_down, S.lambda_min) : fmin(lam * S.lambda_up, S.lambda_max);
+    if (tid == 0) {
+      st[0] = F;
+      st[1] = lam;
+      ist[0] = cur;
+      if (accept) ist[2] += 1;
+    }
+  }
+  if (!prepare) {
+    if (tid == 0 && A.report) {
+      ba_report r;
+      r.initial_cost = st[2];
+      r.final_cost = F;
+      r.final_lambda = lam;
+      r.iters = S.max_iters;
+      r.accepted = ist[2];
+      r.chol_failures = ist[3];
+      r.depth_rejects = 0;
+      r.status = isfinite(st[2]) ? 0 : 1;
+      r.reserved = 0;
+      *A.report = r;
+    }
+    return;
+  }
+  if (tid == 0) sFail = 0;
+
+  // damped normal equations gathered into the factor's blocks, -g into y
+  const double* EB = W.edge[cur];
+  const int nb = G.n_blocks;
+  for (int t = tid; t < nb * 36; t += kPgoStepThreads) {
+    const int b = t / 36, e = t % 36, a = e / 6, c = e % 6;
+    const int ui = up6(a, c);
+    double v = 0.0;
+    for (int q = G.asm_ptr[b]; q < G.asm_ptr[b + 1]; ++q) {
+      const int ce = G.asm_edge[q];
+      const double x = EB[28 * (long long)(ce >> 1) + ui];
+      v += (ce & 1) ? -x : x;
+    }
+    // a diagonal block is the first of its column
+    const int col = G.blk_row[b];
+    if (a == c && G.blk_ptr[col] == b) v += lam * fmax(v, 1e-9);
+    W.L[36 * (long long)b + e] = v;
+  }
+  for (int t = tid; t < G.n_free * 6; t += kPgoStepThreads) {
+    const int c = t / 6, a = t % 6;
+    double v = 0.0;
+    for (int q = G.rhs_ptr[c]; q < G.rhs_ptr[c + 1]; ++q) {
+      const int ce = G.rhs_edge[q];
+      const double x = EB[28 * (long long)(ce >> 1) + 21 + a];
+      v += (ce & 1) ? -x : x;
+    }
+    W.y[t] = v;
+  }
+  __syncthreads();
+
+  // factor and forward substitution, level by level
+  for (int l = 0; l < G.n_levels; ++l) {
+    const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+    const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+    // gather the updates of the level's blocks and right-hand sides
+    const int nbt = (b1 - b0) * 36;
+    for (int t = tid; t < nbt + (c1 - c0) * 6; t += kPgoStepThreads) {
+      if (t < nbt) {
+        const int b = b0 + t / 36, e = t % 36, a = e / 6, c = e % 6;
+        double v = W.L[36 * (long long)b + e];
+        for (int u = G.upd_ptr[b]; u < G.upd_ptr[b + 1]; ++u) {
+          const double* La = W.L + 36 * (long long)G.upd_a[u] + 6 * a;
+          const double* Lb = W.L + 36 * (long long)G.upd_b[u] + 6 * c;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) v -= La[m] * Lb[m];
+        }
+        W.L[36 * (long long)b + e] = v;
+      } else {
+        const int q = t - nbt, c = c0 + q / 6, a = q % 6;
+        double v = W.y[6 * c + a];
+        for (int f = G.fwd_ptr[c]; f < G.fwd_ptr[c + 1]; ++f) {
+          const double* Lf = W.L + 36 * (long long)G.fwd_blk[f] + 6 * a;
+          const double* yk = W.y + 6 * G.fwd_col[f];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) v -= Lf[m] * yk[m];
+        }
+        W.y[6 * c + a] = v;
+      }
+    }
+    __syncthreads();
+    // diagonal blocks (lower Cholesky in place) and the forward step
+    for (int c = c0 + tid; c < c1; c += kPgoStepThreads) {
+      double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
+      bool ok = true;
+      for (int k = 0; k < 6 && ok; ++k) {
+        double d = Lc[7 * k];
+        for (int m = 0; m < k; ++m) d -= Lc[6 * k + m] * Lc[6 * k + m];
+        if (!(d > 0.0) || !isfinite(d)) {
+          ok = false;
+          break;
+        }
+        const double lk = sqrt(d), il = 1.0 / lk;
+        Lc[7 * k] = lk;
+        for (int i = k + 1; i < 6; ++i) {
+          double v = Lc[6 * i + k];
+          for (int m = 0; m < k; ++m) v -= Lc[6 * i + m] * Lc[6 * k + m];
+          Lc[6 * i + k] = v * il;
+        }
+      }
+      if (!ok) {
+        sFail = 1;
+        continue;
+      }
+      double* yc = W.y + 6 * c;
+      for (int k = 0; k < 6; ++k) {
+        double v = yc[k];
+        for (int m = 0; m < k; ++m) v -= Lc[6 * k + m] * yc[m];
+        yc[k] = v / Lc[7 * k];
+      }
+    }
+    __syncthreads();
+    if (sFail) break;
+    // panels: L_rc = A_rc L_cc^-T, one row per thread
+    const int nrow = (b1 - b0) * 6;
+    for (int t = tid; t < nrow; t += kPgoStepThreads) {
+      const int b = b0 + t / 6, a = t % 6;
+      const int col = G.blk_row[b];
+      if (G.blk_ptr[col] == b) continue;   // diagonal block
+      double* row = W.L + 36 * (long long)b + 6 * a;
+      // the block's column: the last column whose first block is <= b
+      int c = c0, hi = c1 - 1;
+      while (c < hi) {
+        const int mid = (c + hi + 1) >> 1;
+        if (G.blk_ptr[mid] <= b) c = mid; else hi = mid - 1;
+      }
+      const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
+      for (int m = 0; m < 6; ++m) {
+        double v = row[m];
+        for (int n = 0; n < m; ++n) v -= row[n] * Lc[6 * m + n];
+        row[m] = v / Lc[7 * m];
+      }
+    }
+    __syncthreads();
+  }
+  const bool fail = sFail != 0;
+  if (fail) {
+    for (int k = tid; k < 12 * G.n_poses; k += kPgoStepThreads) W.cand[k] = A.poses[k];
+    if (tid == 0) {
+      ist[1] = 0;
+      ist[3] += 1;
+    }
+    return;
+  }
+  // back substitution L^T x = y, top level first
+  for (int l = G.n_levels - 1; l >= 0; --l) {
+    const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+    for (int t = tid; t < (c1 - c0) * 6; t += kPgoStepThreads) {
+      const int c = c0 + t / 6, a = t % 6;
+      double v = W.y[6 * c + a];
+      for (int b = G.blk_ptr[c] + 1; b < G.blk_ptr[c + 1]; ++b) {
+        const double* Lb = W.L + 36 * (long long)b;
+        const double* xr = W.x + 6 * G.blk_row[b];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v -= Lb[6 * m + a] * xr[m];
+      }
+      W.x[6 * c + a] = v;
+    }
+    __syncthreads();
+    for (int c = c0 + tid; c < c1; c += kPgoStepThreads) {
+      const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
+      double* xc = W.x + 6 * c;
+      for (int k = 5; k >= 0; --k) {
+        double v = xc[k];
+        for (int m = k + 1; m < 6; ++m) v -= Lc[6 * m + k] * xc[m];
+        xc[k] = v / Lc[7 * k];
+      }
+    }
+    __syncthreads();
+  }
+  // candidate poses: Exp(d) T for the free ones
+  for (int i = tid; i < G.n_poses; i += kPgoStepThreads) {
+    const int c = G.col_of_pose[i];
+    const double* T = A.poses + 12 * (long long)i;
+    double* out = W.cand + 12 * (long long)i;
+    if (c < 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) out[k] = T[k];
+    } else {
+      double Dx[12];
+      exp_se3(W.x + 6 * c, Dx);
+      tcompose(Dx, T, out);
+    }
+  }
+  if (tid == 0) ist[1] = 1;
+}
+
+hipError_t run_pgo(const PgoArgs& A) {
+  hipStream_t s = (hipStream_t)A.stream;
+  const int eb = (A.G.n_edges + kPgoEdgeThreads - 1) / kPgoEdgeThreads;
+  const int n_it = A.settings.max_iters;
+  if (eb > 0) hipLaunchKernelGGL(k_pgo_edges, dim3(eb), dim3(kPgoEdgeThreads), 0, s, A, 1);
+  hipLaunchKernelGGL(k_pgo_step, dim3(1), dim3(kPgoStepThreads), 0, s, A, 0, -1, n_it > 0 ? 1 : 0);
+  for (int it = 0; it < n_it; ++it) {
+    if (eb > 0) hipLaunchKernelGGL(k_pgo_edges, dim3(eb), dim3(kPgoEdgeThreads), 0, s, A, 0);
+    hipLaunchKernelGGL(k_pgo_step, dim3(1), dim3(kPgoStepThreads), 0, s, A, 1, it, it + 1 < n_it ? 1 : 0);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ba

@@ -1,0 +1,78 @@
+// Pose-graph optimisation (paper Sec. 2.3, Eq. 15): host plan of the sparse
+// block Cholesky and the interface to the kernels (pgo.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+
+namespace ba {
+
+// Host plan of one pose graph over its free poses.  Columns of the block
+// factor L are numbered in elimination order, grouped by level of the
+// elimination tree (every column after its children); a column's blocks are
+// its diagonal block followed by its off-diagonal blocks in increasing row.
+struct PgoPlan {
+  int n_poses = 0, n_edges = 0, n_free = 0, n_levels = 0;
+  std::vector<int32_t> col_of_pose;   // n_poses: column of a free pose, -1 when fixed
+  std::vector<int32_t> pose_of_col;   // n_free
+  std::vector<int32_t> lev_ptr;       // n_levels + 1: columns of each level
+  std::vector<int32_t> blk_ptr;       // n_free + 1: blocks of each column
+  std::vector<int32_t> blk_row;       // n_blocks: row (column index) of each block
+  std::vector<int32_t> upd_ptr;       // n_blocks + 1: updates L_rk L_ck^T into block (r, c)
+  std::vector<int32_t> upd_a, upd_b;  //   block ids of L_rk and L_ck
+  std::vector<int32_t> fwd_ptr;       // n_free + 1: forward updates y_c -= L_ck y_k
+  std::vector<int32_t> fwd_blk, fwd_col;
+  std::vector<int32_t> asm_ptr;       // n_blocks + 1: edge terms gathered into each block
+  std::vector<int32_t> asm_edge;      //   edge * 2 + (1 when subtracted)
+  std::vector<int32_t> rhs_ptr;       // n_free + 1: edge terms gathered into each RHS
+  std::vector<int32_t> rhs_edge;      //   edge * 2 + (1 when subtracted)
+  std::vector<int32_t> edge_i, edge_j;
+  int n_blocks() const { return (int)blk_row.size(); }
+};
+
+// Builds the plan; returns an error message (empty on success).
+std::string build_pgo_plan(int32_t n_poses, int32_t n_edges, const int32_t* edge_i,
+                           const int32_t* edge_j, const uint8_t* pose_fixed, PgoPlan& P);
+
+// Device copy of the plan's tables.
+struct PgoDev {
+  int n_poses, n_edges, n_free, n_levels, n_blocks;
+  const int32_t *col_of_pose, *pose_of_col, *lev_ptr, *blk_ptr, *blk_row;
+  const int32_t *upd_ptr, *upd_a, *upd_b, *fwd_ptr, *fwd_blk, *fwd_col;
+  const int32_t *asm_ptr, *asm_edge, *rhs_ptr, *rhs_edge, *edge_i, *edge_j;
+};
+
+// Workspace carved by the solve (FP64 unless noted).
+struct PgoWork {
+  double* edge[2];    // n_edges * 28: w B^T B (21, upper), w B^T r (6), w |r|^2
+  double* cand;       // n_poses * 12 candidate poses
+  double* L;          // n_blocks * 36 factor blocks (row-major)
+  double* y;          // n_free * 6 right-hand side / forward solution
+  double* x;          // n_free * 6 step
+  double* state;      // 8: F, lambda, F0, ...
+  int32_t* istate;    // 8: current edge buffer, candidate valid, accepted, chol failures
+};
+
+size_t pgo_workspace_bytes(const PgoPlan& P);
+PgoWork pgo_carve(const PgoPlan& P, void* ws);
+
+struct PgoArgs {
+  PgoDev G;
+  PgoWork W;
+  double* poses;          // n_poses * 12 world-from-base, in/out
+  const double* deltas;   // n_edges * 12
+  const double* edge_w;   // n_edges or NULL
+  ba_report* report;      // 1 or NULL
+  ba_iter_trace* traces;  // max_iters or NULL
+  DevSettings settings;
+  void* stream;
+};
+
+hipError_t run_pgo(const PgoArgs& A);
+
+}  // namespace ba
