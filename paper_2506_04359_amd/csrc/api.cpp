@@ -643,7 +643,9 @@ ba_status ba_graph_create(int32_t n_poses, int32_t n_edges, const int32_t* edge_
                o_up = blob.add(P.upd_ptr), o_ua = blob.add(P.upd_a), o_ub = blob.add(P.upd_b),
                o_fp = blob.add(P.fwd_ptr), o_fb = blob.add(P.fwd_blk), o_fc = blob.add(P.fwd_col),
                o_ap = blob.add(P.asm_ptr), o_ae = blob.add(P.asm_edge), o_rp = blob.add(P.rhs_ptr),
-               o_re = blob.add(P.rhs_edge), o_ei = blob.add(P.edge_i), o_ej = blob.add(P.edge_j);
+               o_re = blob.add(P.rhs_edge), o_ei = blob.add(P.edge_i), o_ej = blob.add(P.edge_j),
+               o_bc = blob.add(P.blk_col), o_cp = blob.add(P.chunk_ptr), o_cb = blob.add(P.chunk_blk),
+               o_fcp = blob.add(P.fchunk_ptr), o_fcc = blob.add(P.fchunk_col);
   hipError_t e = hipGetDevice(&g->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   e = hipMalloc(&g->mem, blob.size);
@@ -681,6 +683,14 @@ ba_status ba_graph_create(int32_t n_poses, int32_t n_edges, const int32_t* edge_
   D.rhs_edge = at(o_re);
   D.edge_i = at(o_ei);
   D.edge_j = at(o_ej);
+  D.blk_col = at(o_bc);
+  D.chunk_ptr = at(o_cp);
+  D.chunk_blk = at(o_cb);
+  D.fchunk_ptr = at(o_fcp);
+  D.fchunk_col = at(o_fcc);
+  D.n_chunks = (int)P.chunk_blk.size();
+  D.n_fchunks = (int)P.fchunk_col.size();
+  D.n_wide = P.n_wide;
   *out = g.release();
   return BA_OK;
 }
@@ -739,6 +749,7 @@ ba_status ba_pgo_solve(ba_graph g, const ba_settings* s, double* poses, const do
   A.traces = traces;
   A.settings = dev_settings(s);
   A.stream = stream;
+  A.wide_tasks = g->plan.wide_tasks.data();
   e = run_pgo(A);
   if (e != hipSuccess) return hip_fail(e, "pose-graph launch");
   return BA_OK;

@@ -1,20 +1,22 @@
 // gfx950 pose-graph optimisation (paper Sec. 2.3, Eq. 15): LM over the
 // world-from-base poses T_i minimising 1/2 sum_e w_e |Log(D_ij^-1 T_i^-1 T_j)|^2.
 //
-// Per LM attempt two launches:
+// Per LM attempt five launches:
 //   k_pgo_edges  one thread per edge at the candidate poses: r = Log(E),
 //                E = D^-1 T_i^-1 T_j, B = J_l(r)^-1 Ad(D^-1 T_i^-1) (so dr/dxi_j
 //                = B, dr/dxi_i = -B for the left perturbation), and w B^T B,
 //                w B^T r, w |r|^2 into an edge buffer (two buffers: the current
 //                linearisation and the candidate's)
-//   k_pgo_step   one 1024-thread workgroup: the candidate's cost (fixed-order
-//                sum), accept iff it strictly drops, lambda; then the damped
-//                normal equations gathered from the current edge buffer into
-//                the blocks of the factor, the sparse block Cholesky level by
-//                level of the elimination tree (left-looking: each column
-//                gathers its updates, factors its diagonal block, solves its
-//                panel; forward substitution rides along), back substitution
-//                level by level, and the next candidate Exp(d_i) T_i.
+//   k_pgo_decide     one workgroup: the candidate's cost (fixed-order sum),
+//                    accept iff it strictly drops, lambda, trace
+//   k_pgo_assemble   the damped normal equations gathered from the current
+//                    edge buffer into the factor's blocks, -g into y
+//   k_pgo_factor     one 1024-thread workgroup: the sparse block Cholesky
+//                    level by level of the elimination tree (left-looking:
+//                    each column gathers its updates, factors its diagonal
+//                    block in registers, solves its panel; the forward
+//                    substitution rides along), then back substitution
+//   k_pgo_candidate  the next candidate Exp(d_i) T_i
 // Every sum has a fixed order and nothing uses atomics.
 #include <hip/hip_runtime.h>
 
@@ -228,33 +230,28 @@ __device__ __forceinline__ int up6(int a, int b) {
   return 6 * lo - lo * (lo - 1) / 2 + hi - lo;
 }
 
-__global__ __launch_bounds__(kPgoStepThreads) void k_pgo_step(PgoArgs A, int mode, int it, int prepare) {
+// Decision on the candidate just evaluated (mode 1), or the start (mode 0):
+// the cost summed in a fixed order, accept iff it strictly drops, lambda,
+// trace, the accepted poses, and the report after the last attempt.
+__global__ __launch_bounds__(kPgoStepThreads) void k_pgo_decide(PgoArgs A, int mode, int it, int last) {
   __shared__ double sRed[kPgoStepThreads];
-  __shared__ int sFail;
   const int tid = threadIdx.x;
   const PgoDev& G = A.G;
   const PgoWork& W = A.W;
   const DevSettings S = A.settings;
   double* st = W.state;      // 0 F, 1 lambda, 2 F0
   int32_t* ist = W.istate;   // 0 current buffer, 1 candidate valid, 2 accepted, 3 chol failures
-  const double kNaN = __builtin_nan("");
-
-  // cost of the buffer just evaluated, summed in a fixed order
   const int cur0 = mode == 0 ? 0 : ist[0];
   const int ev = mode == 0 ? 0 : 1 - cur0;
-  {
-    double s = 0.0;
-    for (int e = tid; e < G.n_edges; e += kPgoStepThreads) s += W.edge[ev][28 * (long long)e + 27];
-    sRed[tid] = s;
+  double s = 0.0;
+  for (int e = tid; e < G.n_edges; e += kPgoStepThreads) s += W.edge[ev][28 * (long long)e + 27];
+  sRed[tid] = s;
+  __syncthreads();
+  for (int h = kPgoStepThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) sRed[tid] += sRed[tid + h];
     __syncthreads();
-    for (int h = kPgoStepThreads / 2; h > 0; h >>= 1) {
-      if (tid < h) sRed[tid] += sRed[tid + h];
-      __syncthreads();
-    }
   }
   const double Fe = 0.5 * sRed[0];
-  __syncthreads();
-  int cur = cur0;
   double F, lam;
   if (mode == 0) {
     F = Fe;
@@ -276,216 +273,358 @@ __global__ __launch_bounds__(kPgoStepThreads) void k_pgo_step(PgoArgs A, int mod
       ba_iter_trace tr;
       tr.cost = F;
       tr.lambda = lam;
-      tr.cand_cost = valid ? Fe : kNaN;
+      tr.cand_cost = valid ? Fe : __builtin_nan("");
       tr.status = valid ? 0 : 1;
       tr.accepted = accept ? 1 : 0;
       A.traces[it] = tr;
     }
     if (accept) {
       for (int k = tid; k < 12 * G.n_poses; k += kPgoStepThreads) A.poses[k] = W.cand[k];
-      cur = 1 - cur0;
       F = Fe;
     }
     lam = accept ? fmax(lam / S.lambda_down, S.lambda_min) : fmin(lam * S.lambda_up, S.lambda_max);
     if (tid == 0) {
       st[0] = F;
       st[1] = lam;
-      ist[0] = cur;
-      if (accept) ist[2] += 1;
+      if (accept) {
+        ist[0] = 1 - cur0;
+        ist[2] += 1;
+      }
     }
   }
-  if (!prepare) {
-    if (tid == 0 && A.report) {
-      ba_report r;
-      r.initial_cost = st[2];
-      r.final_cost = F;
-      r.final_lambda = lam;
-      r.iters = S.max_iters;
-      r.accepted = ist[2];
-      r.chol_failures = ist[3];
-      r.depth_rejects = 0;
-      r.status = isfinite(st[2]) ? 0 : 1;
-      r.reserved = 0;
-      *A.report = r;
-    }
-    return;
+  if (last && tid == 0 && A.report) {
+    ba_report r;
+    r.initial_cost = mode == 0 ? F : st[2];
+    r.final_cost = F;
+    r.final_lambda = lam;
+    r.iters = S.max_iters;
+    r.accepted = mode == 0 ? 0 : ist[2];
+    r.chol_failures = mode == 0 ? 0 : ist[3];
+    r.depth_rejects = 0;
+    r.status = isfinite(r.initial_cost) ? 0 : 1;
+    r.reserved = 0;
+    *A.report = r;
   }
-  if (tid == 0) sFail = 0;
+}
 
-  // damped normal equations gathered into the factor's blocks, -g into y
-  const double* EB = W.edge[cur];
-  const int nb = G.n_blocks;
-  for (int t = tid; t < nb * 36; t += kPgoStepThreads) {
-    const int b = t / 36, e = t % 36, a = e / 6, c = e % 6;
-    const int ui = up6(a, c);
-    double v = 0.0;
+// The damped normal equations gathered from the current edge buffer into the
+// factor's blocks (one thread per block row), and -g into y.
+__global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_assemble(PgoArgs A) {
+  const PgoDev& G = A.G;
+  const PgoWork& W = A.W;
+  const int t = blockIdx.x * kPgoEdgeThreads + threadIdx.x;
+  const double* EB = W.edge[W.istate[0]];
+  if (t == 0) W.istate[4] = 0;   // pivot failure flag of the factorisation that follows
+  const int nb6 = G.n_blocks * 6;
+  if (t < nb6) {
+    const int b = t / 6, a = t % 6;
+    double v[6] = {0, 0, 0, 0, 0, 0};
     for (int q = G.asm_ptr[b]; q < G.asm_ptr[b + 1]; ++q) {
       const int ce = G.asm_edge[q];
-      const double x = EB[28 * (long long)(ce >> 1) + ui];
-      v += (ce & 1) ? -x : x;
+      const double* x = EB + 28 * (long long)(ce >> 1);
+      const double sg = (ce & 1) ? -1.0 : 1.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] += sg * x[up6(a, c)];
     }
-    // a diagonal block is the first of its column
-    const int col = G.blk_row[b];
-    if (a == c && G.blk_ptr[col] == b) v += lam * fmax(v, 1e-9);
-    W.L[36 * (long long)b + e] = v;
-  }
-  for (int t = tid; t < G.n_free * 6; t += kPgoStepThreads) {
-    const int c = t / 6, a = t % 6;
-    double v = 0.0;
+    if (G.blk_ptr[G.blk_row[b]] == b) {   // diagonal block: damping
+      const double lam = W.state[1];
+      v[a] += lam * fmax(v[a], 1e-9);
+    }
+    double* out = W.L + 36 * (long long)b + 6 * a;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[c] = v[c];
+  } else if (t < nb6 + G.n_free) {
+    const int c = t - nb6;
+    double v[6] = {0, 0, 0, 0, 0, 0};
     for (int q = G.rhs_ptr[c]; q < G.rhs_ptr[c + 1]; ++q) {
       const int ce = G.rhs_edge[q];
-      const double x = EB[28 * (long long)(ce >> 1) + 21 + a];
-      v += (ce & 1) ? -x : x;
+      const double* x = EB + 28 * (long long)(ce >> 1) + 21;
+      const double sg = (ce & 1) ? -1.0 : 1.0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v[a] += sg * x[a];
     }
-    W.y[t] = v;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) W.y[6 * c + a] = v[a];
   }
-  __syncthreads();
+}
 
-  // factor and forward substitution, level by level
-  for (int l = 0; l < G.n_levels; ++l) {
-    const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-    const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
-    // gather the updates of the level's blocks and right-hand sides
-    const int nbt = (b1 - b0) * 36;
-    for (int t = tid; t < nbt + (c1 - c0) * 6; t += kPgoStepThreads) {
-      if (t < nbt) {
-        const int b = b0 + t / 36, e = t % 36, a = e / 6, c = e % 6;
-        double v = W.L[36 * (long long)b + e];
-        for (int u = G.upd_ptr[b]; u < G.upd_ptr[b + 1]; ++u) {
-          const double* La = W.L + 36 * (long long)G.upd_a[u] + 6 * a;
-          const double* Lb = W.L + 36 * (long long)G.upd_b[u] + 6 * c;
+// Sparse block Cholesky by levels of the elimination tree.  Per level:
+// (1) every chunk of at most kPgoChunk updates L_rk L_ck^T of a block (and of
+// forward updates L_ck y_k of a right-hand side) is summed by its own thread
+// into a partial; (2) each column subtracts its partials from its diagonal
+// block and right-hand side in chunk order, factors the block in registers
+// and finishes its forward step; (3) each off-diagonal block row subtracts its
+// partials and solves against the factored diagonal block.  Wide levels run
+// each phase as a launch over the whole GPU; the narrow ones run in one
+// workgroup with barriers between the phases.  A failed pivot sets
+// istate[4].  Back substitution from the top level down: each off-diagonal
+// block forms L_rc^T x_r, then each column sums them in order and solves.
+__device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+  const int q0 = G.chunk_ptr[b0], q1 = G.chunk_ptr[b1];
+  const int f0 = G.fchunk_ptr[c0], f1 = G.fchunk_ptr[c1];
+  double* fpart = W.part + 36 * (long long)G.n_chunks;
+  const int nq = (q1 - q0) * 36;
+  for (int t = t0; t < nq + (f1 - f0) * 6; t += stride) {
+    if (t < nq) {
+      const int q = q0 + t / 36, e = t % 36, a = e / 6, c = e % 6;
+      const int b = G.chunk_blk[q];
+      const int u0 = G.upd_ptr[b] + kPgoChunk * (q - G.chunk_ptr[b]);
+      const int u1 = min(u0 + kPgoChunk, G.upd_ptr[b + 1]);
+      int ia[kPgoChunk], ib[kPgoChunk];
 #pragma unroll
-          for (int m = 0; m < 6; ++m) v -= La[m] * Lb[m];
-        }
-        W.L[36 * (long long)b + e] = v;
-      } else {
-        const int q = t - nbt, c = c0 + q / 6, a = q % 6;
-        double v = W.y[6 * c + a];
-        for (int f = G.fwd_ptr[c]; f < G.fwd_ptr[c + 1]; ++f) {
-          const double* Lf = W.L + 36 * (long long)G.fwd_blk[f] + 6 * a;
-          const double* yk = W.y + 6 * G.fwd_col[f];
+      for (int k = 0; k < kPgoChunk; ++k) {
+        const int u = u0 + k < u1 ? u0 + k : u0;
+        ia[k] = G.upd_a[u];
+        ib[k] = G.upd_b[u];
+      }
+      double acc = 0.0;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) v -= Lf[m] * yk[m];
-        }
-        W.y[6 * c + a] = v;
+      for (int k = 0; k < kPgoChunk; ++k) {
+        const double* La = W.L + 36 * (long long)ia[k] + 6 * a;
+        const double* Lb = W.L + 36 * (long long)ib[k] + 6 * c;
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) s += La[m] * Lb[m];
+        acc += (u0 + k < u1) ? s : 0.0;
+      }
+      W.part[36 * (long long)q + e] = acc;
+    } else {
+      const int fq = f0 + (t - nq) / 6, a = (t - nq) % 6;
+      const int c = G.fchunk_col[fq];
+      const int g0 = G.fwd_ptr[c] + kPgoChunk * (fq - G.fchunk_ptr[c]);
+      const int g1 = min(g0 + kPgoChunk, G.fwd_ptr[c + 1]);
+      int ib[kPgoChunk], ik[kPgoChunk];
+#pragma unroll
+      for (int k = 0; k < kPgoChunk; ++k) {
+        const int f = g0 + k < g1 ? g0 + k : g0;
+        ib[k] = G.fwd_blk[f];
+        ik[k] = G.fwd_col[f];
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kPgoChunk; ++k) {
+        const double* Lf = W.L + 36 * (long long)ib[k] + 6 * a;
+        const double* yk = W.y + 6 * ik[k];
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) s += Lf[m] * yk[m];
+        acc += (g0 + k < g1) ? s : 0.0;
+      }
+      fpart[6 * (long long)fq + a] = acc;
+    }
+  }
+}
+
+__device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+  const double* fpart = W.part + 36 * (long long)G.n_chunks;
+  for (int c = c0 + t0; c < c1; c += stride) {
+    const int bd = G.blk_ptr[c];
+    double* Lc = W.L + 36 * (long long)bd;
+    double m[36], yc[6];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) m[k] = Lc[k];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) yc[a] = W.y[6 * c + a];
+    for (int q = G.chunk_ptr[bd]; q < G.chunk_ptr[bd + 1]; ++q)
+#pragma unroll
+      for (int k = 0; k < 36; ++k) m[k] -= W.part[36 * (long long)q + k];
+    for (int q = G.fchunk_ptr[c]; q < G.fchunk_ptr[c + 1]; ++q)
+#pragma unroll
+      for (int a = 0; a < 6; ++a) yc[a] -= fpart[6 * (long long)q + a];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double d = m[7 * k];
+#pragma unroll
+      for (int q = 0; q < k; ++q) d -= m[6 * k + q] * m[6 * k + q];
+      ok = ok && d > 0.0 && isfinite(d);
+      const double lk = sqrt(fmax(d, 1e-300)), il = 1.0 / lk;
+      m[7 * k] = lk;
+#pragma unroll
+      for (int i = k + 1; i < 6; ++i) {
+        double v = m[6 * i + k];
+#pragma unroll
+        for (int q = 0; q < k; ++q) v -= m[6 * i + q] * m[6 * k + q];
+        m[6 * i + k] = v * il;
       }
     }
+    if (!ok) {
+      W.istate[4] = 1;
+      continue;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double v = yc[k];
+#pragma unroll
+      for (int q = 0; q < k; ++q) v -= m[6 * k + q] * yc[q];
+      yc[k] = v / m[7 * k];
+    }
+#pragma unroll
+    for (int k = 0; k < 36; ++k) Lc[k] = m[k];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) W.y[6 * c + a] = yc[a];
+  }
+}
+
+__device__ __forceinline__ void pgo_phase3(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+  for (int t = t0; t < (b1 - b0) * 6; t += stride) {
+    const int b = b0 + t / 6, a = t % 6;
+    const int c = G.blk_col[b];
+    if (G.blk_ptr[c] == b) continue;   // diagonal block
+    const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
+    double* row = W.L + 36 * (long long)b + 6 * a;
+    double m[36], x[6];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) m[k] = Lc[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = row[k];
+    for (int q = G.chunk_ptr[b]; q < G.chunk_ptr[b + 1]; ++q)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) x[k] -= W.part[36 * (long long)q + 6 * a + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double v = x[k];
+#pragma unroll
+      for (int q = 0; q < k; ++q) v -= x[q] * m[6 * k + q];
+      x[k] = v / m[7 * k];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) row[k] = x[k];
+  }
+}
+
+// One phase of one wide level over the whole grid.
+__global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_wide(PgoArgs A, int l, int phase) {
+  const int t0 = blockIdx.x * kPgoEdgeThreads + threadIdx.x, stride = gridDim.x * kPgoEdgeThreads;
+  if (phase == 1)
+    pgo_phase1(A.G, A.W, l, t0, stride);
+  else if (phase == 2)
+    pgo_phase2(A.G, A.W, l, t0, stride);
+  else
+    pgo_phase3(A.G, A.W, l, t0, stride);
+}
+
+// Levels [l0, n_levels) in one workgroup, then the back substitution.
+__global__ __launch_bounds__(kPgoStepThreads) void k_pgo_factor(PgoArgs A, int l0) {
+  const int tid = threadIdx.x;
+  const PgoDev& G = A.G;
+  const PgoWork& W = A.W;
+  for (int l = l0; l < G.n_levels; ++l) {
+    if (W.istate[4]) break;
+    pgo_phase1(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
-    // diagonal blocks (lower Cholesky in place) and the forward step
-    for (int c = c0 + tid; c < c1; c += kPgoStepThreads) {
-      double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
-      bool ok = true;
-      for (int k = 0; k < 6 && ok; ++k) {
-        double d = Lc[7 * k];
-        for (int m = 0; m < k; ++m) d -= Lc[6 * k + m] * Lc[6 * k + m];
-        if (!(d > 0.0) || !isfinite(d)) {
-          ok = false;
-          break;
-        }
-        const double lk = sqrt(d), il = 1.0 / lk;
-        Lc[7 * k] = lk;
-        for (int i = k + 1; i < 6; ++i) {
-          double v = Lc[6 * i + k];
-          for (int m = 0; m < k; ++m) v -= Lc[6 * i + m] * Lc[6 * k + m];
-          Lc[6 * i + k] = v * il;
-        }
-      }
-      if (!ok) {
-        sFail = 1;
-        continue;
-      }
-      double* yc = W.y + 6 * c;
-      for (int k = 0; k < 6; ++k) {
-        double v = yc[k];
-        for (int m = 0; m < k; ++m) v -= Lc[6 * k + m] * yc[m];
-        yc[k] = v / Lc[7 * k];
-      }
-    }
+    pgo_phase2(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
-    if (sFail) break;
-    // panels: L_rc = A_rc L_cc^-T, one row per thread
-    const int nrow = (b1 - b0) * 6;
-    for (int t = tid; t < nrow; t += kPgoStepThreads) {
-      const int b = b0 + t / 6, a = t % 6;
-      const int col = G.blk_row[b];
-      if (G.blk_ptr[col] == b) continue;   // diagonal block
-      double* row = W.L + 36 * (long long)b + 6 * a;
-      // the block's column: the last column whose first block is <= b
-      int c = c0, hi = c1 - 1;
-      while (c < hi) {
-        const int mid = (c + hi + 1) >> 1;
-        if (G.blk_ptr[mid] <= b) c = mid; else hi = mid - 1;
-      }
-      const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
-      for (int m = 0; m < 6; ++m) {
-        double v = row[m];
-        for (int n = 0; n < m; ++n) v -= row[n] * Lc[6 * m + n];
-        row[m] = v / Lc[7 * m];
-      }
-    }
+    if (W.istate[4]) break;
+    pgo_phase3(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
   }
-  const bool fail = sFail != 0;
-  if (fail) {
-    for (int k = tid; k < 12 * G.n_poses; k += kPgoStepThreads) W.cand[k] = A.poses[k];
+  if (W.istate[4]) {
     if (tid == 0) {
-      ist[1] = 0;
-      ist[3] += 1;
+      W.istate[1] = 0;
+      W.istate[3] += 1;
     }
     return;
   }
-  // back substitution L^T x = y, top level first
   for (int l = G.n_levels - 1; l >= 0; --l) {
     const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-    for (int t = tid; t < (c1 - c0) * 6; t += kPgoStepThreads) {
-      const int c = c0 + t / 6, a = t % 6;
-      double v = W.y[6 * c + a];
-      for (int b = G.blk_ptr[c] + 1; b < G.blk_ptr[c + 1]; ++b) {
-        const double* Lb = W.L + 36 * (long long)b;
-        const double* xr = W.x + 6 * G.blk_row[b];
+    const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+    for (int b = b0 + tid; b < b1; b += kPgoStepThreads) {
+      const int c = G.blk_col[b];
+      if (G.blk_ptr[c] == b) continue;
+      const double* Lb = W.L + 36 * (long long)b;
+      const double* xr = W.x + 6 * G.blk_row[b];
+      double lb[36], xv[6];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) v -= Lb[6 * m + a] * xr[m];
+      for (int k = 0; k < 36; ++k) lb[k] = Lb[k];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) xv[m] = xr[m];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v += lb[6 * m + a] * xv[m];
+        W.bpart[6 * (long long)b + a] = v;
       }
-      W.x[6 * c + a] = v;
     }
     __syncthreads();
     for (int c = c0 + tid; c < c1; c += kPgoStepThreads) {
+      double v[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v[a] = W.y[6 * c + a];
+      for (int b = G.blk_ptr[c] + 1; b < G.blk_ptr[c + 1]; ++b)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) v[a] -= W.bpart[6 * (long long)b + a];
       const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
-      double* xc = W.x + 6 * c;
+      double m[36];
+#pragma unroll
+      for (int k = 0; k < 36; ++k) m[k] = Lc[k];
+#pragma unroll
       for (int k = 5; k >= 0; --k) {
-        double v = xc[k];
-        for (int m = k + 1; m < 6; ++m) v -= Lc[6 * m + k] * xc[m];
-        xc[k] = v / Lc[7 * k];
+        double s = v[k];
+#pragma unroll
+        for (int q = k + 1; q < 6; ++q) s -= m[6 * q + k] * v[q];
+        v[k] = s / m[7 * k];
       }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) W.x[6 * c + a] = v[a];
     }
     __syncthreads();
   }
-  // candidate poses: Exp(d) T for the free ones
-  for (int i = tid; i < G.n_poses; i += kPgoStepThreads) {
-    const int c = G.col_of_pose[i];
-    const double* T = A.poses + 12 * (long long)i;
-    double* out = W.cand + 12 * (long long)i;
-    if (c < 0) {
+  if (tid == 0) W.istate[1] = 1;
+}
+
+// Candidate poses Exp(d_i) T_i for the free poses (the others copied); a
+// failed factorisation leaves the current poses.
+__global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_candidate(PgoArgs A) {
+  const int i = blockIdx.x * kPgoEdgeThreads + threadIdx.x;
+  if (i >= A.G.n_poses) return;
+  const int c = A.G.col_of_pose[i];
+  const double* T = A.poses + 12 * (long long)i;
+  double* out = A.W.cand + 12 * (long long)i;
+  if (c < 0 || A.W.istate[1] == 0) {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) out[k] = T[k];
-    } else {
-      double Dx[12];
-      exp_se3(W.x + 6 * c, Dx);
-      tcompose(Dx, T, out);
-    }
+    for (int k = 0; k < 12; ++k) out[k] = T[k];
+  } else {
+    double Dx[12];
+    exp_se3(A.W.x + 6 * c, Dx);
+    tcompose(Dx, T, out);
   }
-  if (tid == 0) ist[1] = 1;
 }
 
 hipError_t run_pgo(const PgoArgs& A) {
   hipStream_t s = (hipStream_t)A.stream;
   const int eb = (A.G.n_edges + kPgoEdgeThreads - 1) / kPgoEdgeThreads;
+  const int ab = (A.G.n_blocks * 6 + A.G.n_free + kPgoEdgeThreads - 1) / kPgoEdgeThreads;
+  const int pb = (A.G.n_poses + kPgoEdgeThreads - 1) / kPgoEdgeThreads;
   const int n_it = A.settings.max_iters;
+  auto prepare = [&]() {
+    // the assembly also clears the pivot-failure flag, so it runs even when
+    // there is nothing to gather
+    hipLaunchKernelGGL(k_pgo_assemble, dim3(ab > 0 ? ab : 1), dim3(kPgoEdgeThreads), 0, s, A);
+    for (int l = 0; l < A.G.n_wide; ++l) {
+      const int* w = A.wide_tasks + 3 * l;
+      for (int ph = 1; ph <= 3; ++ph) {
+        const int blocks = (w[ph - 1] + kPgoEdgeThreads - 1) / kPgoEdgeThreads;
+        if (blocks > 0)
+          hipLaunchKernelGGL(k_pgo_wide, dim3(blocks), dim3(kPgoEdgeThreads), 0, s, A, l, ph);
+      }
+    }
+    hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(kPgoStepThreads), 0, s, A, A.G.n_wide);
+    hipLaunchKernelGGL(k_pgo_candidate, dim3(pb), dim3(kPgoEdgeThreads), 0, s, A);
+  };
   if (eb > 0) hipLaunchKernelGGL(k_pgo_edges, dim3(eb), dim3(kPgoEdgeThreads), 0, s, A, 1);
-  hipLaunchKernelGGL(k_pgo_step, dim3(1), dim3(kPgoStepThreads), 0, s, A, 0, -1, n_it > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_pgo_decide, dim3(1), dim3(kPgoStepThreads), 0, s, A, 0, -1, n_it == 0 ? 1 : 0);
+  if (n_it > 0) prepare();
   for (int it = 0; it < n_it; ++it) {
     if (eb > 0) hipLaunchKernelGGL(k_pgo_edges, dim3(eb), dim3(kPgoEdgeThreads), 0, s, A, 0);
-    hipLaunchKernelGGL(k_pgo_step, dim3(1), dim3(kPgoStepThreads), 0, s, A, 1, it, it + 1 < n_it ? 1 : 0);
+    hipLaunchKernelGGL(k_pgo_decide, dim3(1), dim3(kPgoStepThreads), 0, s, A, 1, it, it + 1 == n_it ? 1 : 0);
+    if (it + 1 < n_it) prepare();
   }
   return hipGetLastError();
 }

@@ -32,8 +32,20 @@ struct PgoPlan {
   std::vector<int32_t> rhs_ptr;       // n_free + 1: edge terms gathered into each RHS
   std::vector<int32_t> rhs_edge;      //   edge * 2 + (1 when subtracted)
   std::vector<int32_t> edge_i, edge_j;
+  // the update and forward lists cut into chunks of kPgoChunk entries, each
+  // summed by its own thread: chunks of block b are [chunk_ptr[b],
+  // chunk_ptr[b+1]), chunk_blk the block of a chunk; the same for the forward
+  // lists of the columns
+  std::vector<int32_t> blk_col;       // n_blocks: column of each block
+  // the first n_wide levels run each phase over the whole GPU; wide_tasks
+  // holds their task counts (phase 1, 2, 3) per level
+  int n_wide = 0;
+  std::vector<int32_t> wide_tasks;
+  std::vector<int32_t> chunk_ptr, chunk_blk, fchunk_ptr, fchunk_col;
   int n_blocks() const { return (int)blk_row.size(); }
 };
+
+constexpr int kPgoChunk = 4;
 
 // Builds the plan; returns an error message (empty on success).
 std::string build_pgo_plan(int32_t n_poses, int32_t n_edges, const int32_t* edge_i,
@@ -45,6 +57,9 @@ struct PgoDev {
   const int32_t *col_of_pose, *pose_of_col, *lev_ptr, *blk_ptr, *blk_row;
   const int32_t *upd_ptr, *upd_a, *upd_b, *fwd_ptr, *fwd_blk, *fwd_col;
   const int32_t *asm_ptr, *asm_edge, *rhs_ptr, *rhs_edge, *edge_i, *edge_j;
+  const int32_t *blk_col, *chunk_ptr, *chunk_blk, *fchunk_ptr, *fchunk_col;
+  int n_chunks, n_fchunks;
+  int n_wide;
 };
 
 // Workspace carved by the solve (FP64 unless noted).
@@ -54,8 +69,10 @@ struct PgoWork {
   double* L;          // n_blocks * 36 factor blocks (row-major)
   double* y;          // n_free * 6 right-hand side / forward solution
   double* x;          // n_free * 6 step
+  double* part;       // n_chunks * 36 + n_fchunks * 6 partial sums of the update chunks
+  double* bpart;      // n_blocks * 6 back-substitution terms L_rc^T x_r
   double* state;      // 8: F, lambda, F0, ...
-  int32_t* istate;    // 8: current edge buffer, candidate valid, accepted, chol failures
+  int32_t* istate;    // 8: current edge buffer, candidate valid, accepted, chol failures, pivot failed
 };
 
 size_t pgo_workspace_bytes(const PgoPlan& P);
@@ -71,6 +88,7 @@ struct PgoArgs {
   ba_iter_trace* traces;  // max_iters or NULL
   DevSettings settings;
   void* stream;
+  const int* wide_tasks;  // HOST, 3 * G.n_wide launch sizes
 };
 
 hipError_t run_pgo(const PgoArgs& A);

@@ -275,13 +275,42 @@ std::string build_pgo_plan(int32_t n_poses, int32_t n_edges, const int32_t* edge
   P.rhs_ptr.assign(nf + 1, 0);
   for (int c = 0; c < nf; ++c) P.rhs_ptr[c + 1] = P.rhs_ptr[c] + (int)rh[c].size();
   for (int c = 0; c < nf; ++c) P.rhs_edge.insert(P.rhs_edge.end(), rh[c].begin(), rh[c].end());
+  P.blk_col.resize(nb);
+  for (int c = 0; c < nf; ++c)
+    for (int b = P.blk_ptr[c]; b < P.blk_ptr[c + 1]; ++b) P.blk_col[b] = c;
+  P.chunk_ptr.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    const int n = P.upd_ptr[b + 1] - P.upd_ptr[b];
+    P.chunk_ptr[b + 1] = P.chunk_ptr[b] + (n + kPgoChunk - 1) / kPgoChunk;
+    for (int q = P.chunk_ptr[b]; q < P.chunk_ptr[b + 1]; ++q) P.chunk_blk.push_back(b);
+  }
+  P.fchunk_ptr.assign(nf + 1, 0);
+  for (int c = 0; c < nf; ++c) {
+    const int n = P.fwd_ptr[c + 1] - P.fwd_ptr[c];
+    P.fchunk_ptr[c + 1] = P.fchunk_ptr[c] + (n + kPgoChunk - 1) / kPgoChunk;
+    for (int q = P.fchunk_ptr[c]; q < P.fchunk_ptr[c + 1]; ++q) P.fchunk_col.push_back(c);
+  }
+  // leading levels whose update phase has at least 4096 tasks run as
+  // launches over the whole GPU
+  for (int l = 0; l < P.n_levels; ++l) {
+    const int c0 = P.lev_ptr[l], c1 = P.lev_ptr[l + 1];
+    const int b0 = P.blk_ptr[c0], b1 = P.blk_ptr[c1];
+    const int t1 = (P.chunk_ptr[b1] - P.chunk_ptr[b0]) * 36 + (P.fchunk_ptr[c1] - P.fchunk_ptr[c0]) * 6;
+    if (t1 < 4096 && l > 0) break;
+    P.wide_tasks.push_back(t1);
+    P.wide_tasks.push_back(c1 - c0);
+    P.wide_tasks.push_back((b1 - b0) * 6);
+    P.n_wide = l + 1;
+  }
   return "";
 }
 
 size_t pgo_workspace_bytes(const PgoPlan& P) {
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   return 2 * up((size_t)P.n_edges * 28 * 8) + up((size_t)P.n_poses * 12 * 8) +
-         up((size_t)P.n_blocks() * 36 * 8) + 2 * up((size_t)P.n_free * 6 * 8) + up(8 * 8) + up(8 * 4);
+         up((size_t)P.n_blocks() * 36 * 8) + 2 * up((size_t)P.n_free * 6 * 8) +
+         up(((size_t)P.chunk_blk.size() * 36 + P.fchunk_col.size() * 6) * 8) +
+         up((size_t)P.n_blocks() * 6 * 8) + up(8 * 8) + up(8 * 4);
 }
 
 PgoWork pgo_carve(const PgoPlan& P, void* ws) {
@@ -300,6 +329,10 @@ PgoWork pgo_carve(const PgoPlan& P, void* ws) {
   p += up((size_t)P.n_free * 6 * 8);
   W.x = (double*)p;
   p += up((size_t)P.n_free * 6 * 8);
+  W.part = (double*)p;
+  p += up(((size_t)P.chunk_blk.size() * 36 + P.fchunk_col.size() * 6) * 8);
+  W.bpart = (double*)p;
+  p += up((size_t)P.n_blocks() * 6 * 8);
   W.state = (double*)p;
   p += up(8 * 8);
   W.istate = (int32_t*)p;
