@@ -53,6 +53,10 @@ PNP_FLOPS_PER_OBS_PASS = 209
 # t_cw (18), normalised pixel (4), ray direction and centre (33), normalisation
 # (9), d.c (5), M and b (30)
 TRI_FLOPS_PER_OBS_PASS = 143
+# pose-graph edge: D^-1 T_i^-1 T_j (120), Log (60), J^-1 (60), the series of Q
+# (about 8 terms of 3 3x3 products, 1300), M, N (240), B^T B (21 x 12), B^T r
+# (72), |r|^2 (12)
+PGO_FLOPS_PER_EDGE = 2100
 TRI_FLOPS_PER_OBS_START = 144
 N_WINDOWS = 256
 ITERS = 15
@@ -439,12 +443,26 @@ def main():
         ms_g = sum(a.elapsed_time(b) for a, b in evs) / args.steps
         rep_g = ba.parse_reports(rg)[0]
         info = graph.info()
+        plan = ba.Graph(pg.n_poses, pg.edge_i, pg.edge_j, pg.pose_fixed, host_only=True).plan()
+        n_upd = int(plan["upd_ptr"][-1])
+        n_offd = info["n_blocks"] - info["n_free"]
+        # per attempt: the edges at the candidate, the factorisation (updates
+        # 432, diagonal blocks 182, panel rows 6 x 36), forward and back
+        # substitution (72 per block each)
+        flops_att = (pg.n_edges * PGO_FLOPS_PER_EDGE + n_upd * 432 + info["n_free"] * 182
+                     + n_offd * 6 * 36 + info["n_blocks"] * 144)
+        flops_g = flops_att * pg.max_iters
         out["pgo"] = {"workload": "pgo-helix-3x500", "poses": pg.n_poses, "edges": pg.n_edges,
                       "free_poses": info["n_free"], "factor_blocks": info["n_blocks"],
                       "tree_levels": info["n_levels"], "lm_attempts": pg.max_iters, "ms_per_solve": ms_g,
                       "lm_iters_per_s": pg.max_iters / (ms_g / 1e3),
                       "edges_per_s": pg.n_edges * (1 + pg.max_iters) / (ms_g / 1e3),
-                      "initial_cost": float(rep_g["initial_cost"]), "final_cost": float(rep_g["final_cost"])}
+                      "initial_cost": float(rep_g["initial_cost"]), "final_cost": float(rep_g["final_cost"]),
+                      "roofline": {"bound": "alu", "achieved": flops_g / (ms_g * 1e-3) / 1e12,
+                                   "peak": PEAK_VALU_FP64, "unit": "TFLOP/s",
+                                   "frac": flops_g / (ms_g * 1e-3) / 1e12 / PEAK_VALU_FP64, "traffic": None,
+                                   "kernel": "k_pgo_* (one solve)", "flops_per_launch": flops_g,
+                                   "avg_launch_ms": ms_g}}
         log(f"pgo: {ms_g:.3f} ms per solve ({pg.n_poses} poses, {pg.n_edges} edges, "
             f"{info['n_levels']} levels)")
         del graph
