@@ -47,17 +47,14 @@ PEAK_VALU_FP64 = 78.6        # MI355X FP64 vector peak (also the FP32 rate witho
 # residual (9), s (3), w rho and the cost sum (2), the rows of A R_c (20),
 # w rho' (1), the two cross products (18), w J rows (12), U (21 x 4), g (6 x 4)
 PNP_FLOPS_PER_OBS_PASS = 209
-# triangulation, per observation: a pass x_b (18), x_c (18), projection and
-# residual (9), s (3), w rho and the sum (2), rows of A R_c (20), J rows A R_c R_i
-# (30), w rho' (1), w J (6), V (6 x 4), g (3 x 4); the ray start once: R_cw (45),
-# t_cw (18), normalised pixel (4), ray direction and centre (33), normalisation
-# (9), d.c (5), M and b (30)
-TRI_FLOPS_PER_OBS_PASS = 143
-# pose-graph edge: D^-1 T_i^-1 T_j (120), Log (60), J^-1 (60), the series of Q
-# (about 8 terms of 3 3x3 products, 1300), M, N (240), B^T B (21 x 12), B^T r
-# (72), |r|^2 (12)
-PGO_FLOPS_PER_EDGE = 2100
-TRI_FLOPS_PER_OBS_START = 144
+# triangulation, per observation with the world-to-camera transforms of a
+# workgroup's poses composed in LDS (every workgroup of the benchmark batch): a
+# pass x_c (18), projection and residual (9), s (3), w rho and the sum (2), the
+# rows of A R_cw, the Jacobian (20), w rho' (1), w J (6), V (6 x 4), g (3 x 4);
+# the ray start once: normalised pixel (4), ray direction and centre (33),
+# normalisation (9), d.c (5), M and b (30)
+TRI_FLOPS_PER_OBS_PASS = 95
+TRI_FLOPS_PER_OBS_START = 81
 N_WINDOWS = 256
 ITERS = 15
 

@@ -5,7 +5,10 @@
 //
 // One lane per landmark (a workgroup's landmarks ordered by observation count
 // across its lanes); the landmark's observations are a contiguous range.  When
-// the poses a workgroup reads span at most 128 indices they are copied to LDS.
+// the poses a workgroup reads span a range that, times the camera count, is at
+// most 128, the world-to-camera transforms T_cb T_bw_i of that range are
+// composed once into LDS, so each observation needs one transform and the
+// Jacobian is A R_cw directly.
 //   start     the weighted least-squares intersection of the viewing rays,
 //             (sum w (I - d d^T)) p0 = sum w (I - d d^T) c, by a 3x3 FP64
 //             Cholesky; fewer than two views or a pivot <= 1e-10 trace marks
@@ -30,7 +33,7 @@
 namespace ba {
 
 constexpr int kTriThreads = 256;
-constexpr int kTriPoseCache = 128;   // poses a workgroup keeps in LDS
+constexpr int kTriPoseCache = 128;   // (pose, camera) transforms a workgroup keeps in LDS
 
 // Cholesky solve of a 3x3 SPD system stored as (00, 01, 02, 11, 12, 22):
 // x = A^-1 b.  False on a pivot <= floor or a non-finite one.
@@ -61,9 +64,12 @@ __device__ int kTriCamZero = 0;
 __device__ double kTriWeightOne = 1.0;
 
 // Ray start and LM refinement of landmark j (observations [o0, o1), indices
-// already checked).  Pose i is read at P + 12 (i - pbase): the workgroup's
-// LDS copy or the caller's array.
-template <typename Real>
+// already checked).  COMPOSED: P holds, per (pose i, camera c) at
+// 16 ((i - pbase) n_cams + c), the camera record with the world-to-camera
+// transform T_cb T_bw_i in place of T_cb (so the point goes to the camera in
+// one transform and A R_cw is the Jacobian); otherwise P holds the poses
+// (at 12 (i - pbase)) and the cameras come from sCam.
+template <typename Real, bool COMPOSED>
 __device__ __forceinline__ void tri_landmark(const TriArgs& A, int j, long long o0, long long o1,
                                              const double* sCam, const double* P, int pbase) {
   const DevSettings S = A.settings;
@@ -114,15 +120,24 @@ __device__ __forceinline__ void tri_landmark(const TriArgs& A, int j, long long 
     Ob cur = load(o0);
     for (long long o = o0; o < o1; ++o) {
       const Ob nxt = load(o + 1 < o1 ? o + 1 : o);
-      const double* T = P + 12 * (cur.i - pbase);
-      const double* C = sCam + 16 * cur.c;
       double Rcw[9], tcw[3];
+      const double* C;
+      if constexpr (COMPOSED) {
+        C = P + 16 * ((cur.i - pbase) * A.n_cams + cur.c);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
+        for (int k = 0; k < 9; ++k) Rcw[k] = C[4 + k];
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
-          Rcw[3 * a + b] = C[4 + 3 * a] * T[b] + C[5 + 3 * a] * T[4 + b] + C[6 + 3 * a] * T[8 + b];
-        tcw[a] = C[4 + 3 * a] * T[3] + C[5 + 3 * a] * T[7] + C[6 + 3 * a] * T[11] + C[13 + a];
+        for (int a = 0; a < 3; ++a) tcw[a] = C[13 + a];
+      } else {
+        const double* T = P + 12 * (cur.i - pbase);
+        C = sCam + 16 * cur.c;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            Rcw[3 * a + b] = C[4 + 3 * a] * T[b] + C[5 + 3 * a] * T[4 + b] + C[6 + 3 * a] * T[8 + b];
+          tcw[a] = C[4 + 3 * a] * T[3] + C[5 + 3 * a] * T[7] + C[6 + 3 * a] * T[11] + C[13 + a];
+        }
       }
       const double v[3] = {(cur.u - C[2]) / C[0], (cur.v - C[3]) / C[1], 1.0};
       double d[3], ctr[3];
@@ -163,21 +178,34 @@ __device__ __forceinline__ void tri_landmark(const TriArgs& A, int j, long long 
     Ob cur = load(o0);
     for (long long o = o0; o < o1; ++o) {
       const Ob nxt = load(o + 1 < o1 ? o + 1 : o);
-      const double* T = P + 12 * (cur.i - pbase);
-      const double* C = sCam + 16 * cur.c;
-      double xb[3];
+      Real J0[3], J1[3];
+      Lin<Real> L;
+      if constexpr (COMPOSED) {
+        // the record's transform takes the world point to the camera: the
+        // rows of A R_cw are the Jacobian
+        const double* C = P + 16 * ((cur.i - pbase) * A.n_cams + cur.c);
+        L = linearise<Real>(q, C, cur.u - C[2], cur.v - C[3], cur.w, S.huber_delta);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) xb[a] = T[4 * a] * q[0] + T[4 * a + 1] * q[1] + T[4 * a + 2] * q[2] + T[4 * a + 3];
-      const Lin<Real> L = linearise<Real>(xb, C, cur.u - C[2], cur.v - C[3], cur.w, S.huber_delta);
+        for (int b = 0; b < 3; ++b) {
+          J0[b] = L.a0[b];
+          J1[b] = L.a1[b];
+        }
+      } else {
+        const double* T = P + 12 * (cur.i - pbase);
+        const double* C = sCam + 16 * cur.c;
+        double xb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xb[a] = T[4 * a] * q[0] + T[4 * a + 1] * q[1] + T[4 * a + 2] * q[2] + T[4 * a + 3];
+        L = linearise<Real>(xb, C, cur.u - C[2], cur.v - C[3], cur.w, S.huber_delta);
+        // J rows = (rows of A R_c) R_i
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          J0[b] = L.a0[0] * (Real)T[b] + L.a0[1] * (Real)T[4 + b] + L.a0[2] * (Real)T[8 + b];
+          J1[b] = L.a1[0] * (Real)T[b] + L.a1[1] * (Real)T[4 + b] + L.a1[2] * (Real)T[8 + b];
+        }
+      }
       nbad += (L.Z > S.min_depth) ? 0 : 1;
       F += L.rho_w;
-      // J rows = (rows of A R_c) R_i
-      Real J0[3], J1[3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        J0[b] = L.a0[0] * (Real)T[b] + L.a0[1] * (Real)T[4 + b] + L.a0[2] * (Real)T[8 + b];
-        J1[b] = L.a1[0] * (Real)T[b] + L.a1[1] * (Real)T[4 + b] + L.a1[2] * (Real)T[8 + b];
-      }
       const Real w1 = (Real)(L.wo * L.d1);
       int e = 0;
 #pragma unroll
@@ -265,7 +293,7 @@ __device__ __forceinline__ void tri_landmark(const TriArgs& A, int j, long long 
 template <typename Real>
 __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
   __shared__ double sCam[kMaxCams * 16];
-  __shared__ double sPose[kTriPoseCache * 12];
+  __shared__ double sComp[kTriPoseCache * 16];
   __shared__ int sCount[kTriThreads];
   __shared__ int sOrder[kTriThreads];
   __shared__ int sRange[2][kTriThreads / 64];
@@ -325,11 +353,28 @@ __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
     pmin = sRange[0][w] < pmin ? sRange[0][w] : pmin;
     pmax = sRange[1][w] > pmax ? sRange[1][w] : pmax;
   }
-  // every index was checked against n_poses, so [pmin, pmax] is in range
-  const bool cached = pmax >= pmin && pmax - pmin < kTriPoseCache;
+  // every index was checked against n_poses, so [pmin, pmax] is in range;
+  // compose T_cb T_bw_i for every (pose, camera) the range holds
+  const bool cached = pmax >= pmin && (long long)(pmax - pmin + 1) * A.n_cams <= kTriPoseCache;
   if (cached) {
-    const int n = 12 * (pmax - pmin + 1);
-    for (int k = threadIdx.x; k < n; k += blockDim.x) sPose[k] = A.poses[12 * (long long)pmin + k];
+    const int n = (pmax - pmin + 1) * A.n_cams;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      const int i = pmin + r / A.n_cams, c = r % A.n_cams;
+      const double* T = A.poses + 12 * (long long)i;
+      const double* C = sCam + 16 * c;
+      double* out = sComp + 16 * r;
+      out[0] = C[0];
+      out[1] = C[1];
+      out[2] = C[2];
+      out[3] = C[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          out[4 + 3 * a + b] = C[4 + 3 * a] * T[b] + C[5 + 3 * a] * T[4 + b] + C[6 + 3 * a] * T[8 + b];
+        out[13 + a] = C[4 + 3 * a] * T[3] + C[5 + 3 * a] * T[7] + C[6 + 3 * a] * T[11] + C[13 + a];
+      }
+    }
   }
   __syncthreads();
   if (j >= A.n_points) return;
@@ -354,9 +399,9 @@ __global__ __launch_bounds__(kTriThreads) void k_tri(TriArgs A) {
     return;
   }
   if (cached)
-    tri_landmark<Real>(A, j, o0, o1, sCam, sPose, pmin);
+    tri_landmark<Real, true>(A, j, o0, o1, sCam, sComp, pmin);
   else
-    tri_landmark<Real>(A, j, o0, o1, sCam, A.poses, 0);
+    tri_landmark<Real, false>(A, j, o0, o1, sCam, A.poses, 0);
 }
 
 template <typename Real>
