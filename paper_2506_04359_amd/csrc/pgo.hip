@@ -417,6 +417,7 @@ __device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, in
   }
 }
 
+template <bool SUM>
 __device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
   const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
   const double* fpart = W.part + 36 * (long long)G.n_chunks;
@@ -428,12 +429,14 @@ __device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, in
     for (int k = 0; k < 36; ++k) m[k] = Lc[k];
 #pragma unroll
     for (int a = 0; a < 6; ++a) yc[a] = W.y[6 * c + a];
-    for (int q = G.chunk_ptr[bd]; q < G.chunk_ptr[bd + 1]; ++q)
+    if constexpr (SUM) {
+      for (int q = G.chunk_ptr[bd]; q < G.chunk_ptr[bd + 1]; ++q)
 #pragma unroll
-      for (int k = 0; k < 36; ++k) m[k] -= W.part[36 * (long long)q + k];
-    for (int q = G.fchunk_ptr[c]; q < G.fchunk_ptr[c + 1]; ++q)
+        for (int k = 0; k < 36; ++k) m[k] -= W.part[36 * (long long)q + k];
+      for (int q = G.fchunk_ptr[c]; q < G.fchunk_ptr[c + 1]; ++q)
 #pragma unroll
-      for (int a = 0; a < 6; ++a) yc[a] -= fpart[6 * (long long)q + a];
+        for (int a = 0; a < 6; ++a) yc[a] -= fpart[6 * (long long)q + a];
+    }
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -469,6 +472,7 @@ __device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, in
   }
 }
 
+template <bool SUM>
 __device__ __forceinline__ void pgo_phase3(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
   const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
   const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
@@ -483,9 +487,10 @@ __device__ __forceinline__ void pgo_phase3(const PgoDev& G, const PgoWork& W, in
     for (int k = 0; k < 36; ++k) m[k] = Lc[k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = row[k];
-    for (int q = G.chunk_ptr[b]; q < G.chunk_ptr[b + 1]; ++q)
+    if constexpr (SUM)
+      for (int q = G.chunk_ptr[b]; q < G.chunk_ptr[b + 1]; ++q)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) x[k] -= W.part[36 * (long long)q + 6 * a + k];
+        for (int k = 0; k < 6; ++k) x[k] -= W.part[36 * (long long)q + 6 * a + k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       double v = x[k];
@@ -498,15 +503,42 @@ __device__ __forceinline__ void pgo_phase3(const PgoDev& G, const PgoWork& W, in
   }
 }
 
+// The level's partials subtracted from its blocks and right-hand sides, one
+// entry per thread, in chunk order (the narrow levels' variant of the sums
+// that phases 2 and 3 otherwise do per column / row).
+__device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+  const double* fpart = W.part + 36 * (long long)G.n_chunks;
+  const int nb = (b1 - b0) * 36;
+  for (int t = t0; t < nb + (c1 - c0) * 6; t += stride) {
+    if (t < nb) {
+      const int b = b0 + t / 36, e = t % 36;
+      const int q0 = G.chunk_ptr[b], q1 = G.chunk_ptr[b + 1];
+      if (q0 == q1) continue;
+      double v = W.L[36 * (long long)b + e];
+      for (int q = q0; q < q1; ++q) v -= W.part[36 * (long long)q + e];
+      W.L[36 * (long long)b + e] = v;
+    } else {
+      const int c = c0 + (t - nb) / 6, a = (t - nb) % 6;
+      const int q0 = G.fchunk_ptr[c], q1 = G.fchunk_ptr[c + 1];
+      if (q0 == q1) continue;
+      double v = W.y[6 * c + a];
+      for (int q = q0; q < q1; ++q) v -= fpart[6 * (long long)q + a];
+      W.y[6 * c + a] = v;
+    }
+  }
+}
+
 // One phase of one wide level over the whole grid.
 __global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_wide(PgoArgs A, int l, int phase) {
   const int t0 = blockIdx.x * kPgoEdgeThreads + threadIdx.x, stride = gridDim.x * kPgoEdgeThreads;
   if (phase == 1)
     pgo_phase1(A.G, A.W, l, t0, stride);
   else if (phase == 2)
-    pgo_phase2(A.G, A.W, l, t0, stride);
+    pgo_phase2<true>(A.G, A.W, l, t0, stride);
   else
-    pgo_phase3(A.G, A.W, l, t0, stride);
+    pgo_phase3<true>(A.G, A.W, l, t0, stride);
 }
 
 // Levels [l0, n_levels) in one workgroup, then the back substitution.
@@ -518,10 +550,12 @@ __global__ __launch_bounds__(kPgoStepThreads) void k_pgo_factor(PgoArgs A, int l
     if (W.istate[4]) break;
     pgo_phase1(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
-    pgo_phase2(G, W, l, tid, kPgoStepThreads);
+    pgo_phase1b(G, W, l, tid, kPgoStepThreads);
+    __syncthreads();
+    pgo_phase2<false>(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
     if (W.istate[4]) break;
-    pgo_phase3(G, W, l, tid, kPgoStepThreads);
+    pgo_phase3<false>(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
   }
   if (W.istate[4]) {
