@@ -491,11 +491,12 @@ __device__ __forceinline__ void pose_sums_add(Real* sS, Real* sB, Real* sD, int 
   }
 }
 
-// Stored row stride of a pair's Z_bar (6 rows of 3): padded to 4 in FP32 so a
-// row is one 16-byte LDS read; unpadded in FP64, where LDS is the constraint.
+// Stored row stride of a pair's Z_bar (6 rows of 3), unpadded: the Schur units
+// are bound by LDS bandwidth, and a padded row (4 floats) carries a quarter of
+// dead bytes; the 18-word pair stride also spreads pairs over more banks.
 template <typename Real>
 struct ZRow {
-  static constexpr int R = sizeof(Real) == 4 ? 4 : 3;
+  static constexpr int R = 3;
   static constexpr int S = 6 * R;
 };
 
