@@ -445,11 +445,11 @@ __device__ __forceinline__ void run_sums(Real* v, int key) {
   run_step<Real, N, 0x143, 0xc>(v, key);   // row_bcast:31 into rows 2 and 3
 }
 
-// Rows of one target block per Schur work unit in pass A (1, 2, 3 or 6): three
-// rows read 9 Z rows per product for 54 FMAs and keep enough units per tile to
-// balance the threads.
+// Rows of one target block per Schur work unit in pass A (1, 2, 3 or 6): two
+// rows read 8 Z rows per product for 36 FMAs and keep enough units per tile to
+// balance the threads (measured faster than three or six rows per unit).
 #ifndef BA_ROWS_PER_UNIT
-#define BA_ROWS_PER_UNIT 3
+#define BA_ROWS_PER_UNIT 2
 #endif
 constexpr int kRowsPerUnit = BA_ROWS_PER_UNIT;
 static_assert(6 % kRowsPerUnit == 0, "rows per unit must divide 6");
