@@ -55,6 +55,10 @@ PNP_FLOPS_PER_OBS_PASS = 209
 # normalisation (9), d.c (5), M and b (30)
 TRI_FLOPS_PER_OBS_PASS = 95
 TRI_FLOPS_PER_OBS_START = 81
+# pose-graph edge: D^-1 T_i^-1 T_j (120), Log (60), J^-1 (60), the series of Q
+# (about 8 terms of 3 3x3 products, 1300), M, N (240), B^T B (21 x 12), B^T r
+# (72), |r|^2 (12)
+PGO_FLOPS_PER_EDGE = 2100
 N_WINDOWS = 256
 ITERS = 15
 
