@@ -351,12 +351,11 @@ __global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_assemble(PgoArgs A) {
 // Sparse block Cholesky by levels of the elimination tree.  Per level:
 // (1) every chunk of at most kPgoChunk updates L_rk L_ck^T of a block (and of
 // forward updates L_ck y_k of a right-hand side) is summed by its own thread
-// into a partial; (2) each column subtracts its partials from its diagonal
-// block and right-hand side in chunk order, factors the block in registers
-// and finishes its forward step; (3) each off-diagonal block row subtracts its
-// partials and solves against the factored diagonal block.  Wide levels run
-// each phase as a launch over the whole GPU; the narrow ones run in one
-// workgroup with barriers between the phases.  A failed pivot sets
+// into a partial; (2) one wave per column subtracts its partials in chunk
+// order, factors the diagonal block in registers, finishes the forward step
+// and solves the column's panel rows.  Wide levels run each of the two phases
+// as a launch over the whole GPU; the narrow ones run in one workgroup, where
+// the partials are first subtracted entry-parallel.  A failed pivot sets
 // istate[4].  Back substitution from the top level down: each off-diagonal
 // block forms L_rc^T x_r, then each column sums them in order and solves.
 __device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
@@ -417,11 +416,42 @@ __device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, in
   }
 }
 
+// The level's partials subtracted from its blocks and right-hand sides, one
+// entry per thread, in chunk order (the narrow levels' variant of the sums
+// that phases 2 and 3 otherwise do per column / row).
+__device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+  const double* fpart = W.part + 36 * (long long)G.n_chunks;
+  const int nb = (b1 - b0) * 36;
+  for (int t = t0; t < nb + (c1 - c0) * 6; t += stride) {
+    if (t < nb) {
+      const int b = b0 + t / 36, e = t % 36;
+      const int q0 = G.chunk_ptr[b], q1 = G.chunk_ptr[b + 1];
+      if (q0 == q1) continue;
+      double v = W.L[36 * (long long)b + e];
+      for (int q = q0; q < q1; ++q) v -= W.part[36 * (long long)q + e];
+      W.L[36 * (long long)b + e] = v;
+    } else {
+      const int c = c0 + (t - nb) / 6, a = (t - nb) % 6;
+      const int q0 = G.fchunk_ptr[c], q1 = G.fchunk_ptr[c + 1];
+      if (q0 == q1) continue;
+      double v = W.y[6 * c + a];
+      for (int q = q0; q < q1; ++q) v -= fpart[6 * (long long)q + a];
+      W.y[6 * c + a] = v;
+    }
+  }
+}
+
+// Phases 2 and 3 of a level with one wave per column: every lane factors the
+// column's diagonal block in registers (the same arithmetic in each lane) and
+// finishes the forward step, then the lanes solve the column's panel rows.
+// With SUM the chunk partials are subtracted here (the wide levels).
 template <bool SUM>
-__device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+__device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, int l, int w0, int nw, int lane) {
   const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
   const double* fpart = W.part + 36 * (long long)G.n_chunks;
-  for (int c = c0 + t0; c < c1; c += stride) {
+  for (int c = c0 + w0; c < c1; c += nw) {
     const int bd = G.blk_ptr[c];
     double* Lc = W.L + 36 * (long long)bd;
     double m[36], yc[6];
@@ -455,7 +485,7 @@ __device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, in
       }
     }
     if (!ok) {
-      W.istate[4] = 1;
+      if (lane == 0) W.istate[4] = 1;
       continue;
     }
 #pragma unroll
@@ -465,67 +495,33 @@ __device__ __forceinline__ void pgo_phase2(const PgoDev& G, const PgoWork& W, in
       for (int q = 0; q < k; ++q) v -= m[6 * k + q] * yc[q];
       yc[k] = v / m[7 * k];
     }
+    // panel rows (every lane has read the diagonal block above)
+    const int nrow = (G.blk_ptr[c + 1] - bd - 1) * 6;
+    for (int t = lane; t < nrow; t += 64) {
+      const int b = bd + 1 + t / 6, a = t % 6;
+      double* row = W.L + 36 * (long long)b + 6 * a;
+      double x[6];
 #pragma unroll
-    for (int k = 0; k < 36; ++k) Lc[k] = m[k];
+      for (int k = 0; k < 6; ++k) x[k] = row[k];
+      if constexpr (SUM)
+        for (int q = G.chunk_ptr[b]; q < G.chunk_ptr[b + 1]; ++q)
 #pragma unroll
-    for (int a = 0; a < 6; ++a) W.y[6 * c + a] = yc[a];
-  }
-}
-
-template <bool SUM>
-__device__ __forceinline__ void pgo_phase3(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
-  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
-  for (int t = t0; t < (b1 - b0) * 6; t += stride) {
-    const int b = b0 + t / 6, a = t % 6;
-    const int c = G.blk_col[b];
-    if (G.blk_ptr[c] == b) continue;   // diagonal block
-    const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
-    double* row = W.L + 36 * (long long)b + 6 * a;
-    double m[36], x[6];
+          for (int k = 0; k < 6; ++k) x[k] -= W.part[36 * (long long)q + 6 * a + k];
 #pragma unroll
-    for (int k = 0; k < 36; ++k) m[k] = Lc[k];
+      for (int k = 0; k < 6; ++k) {
+        double v = x[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) x[k] = row[k];
-    if constexpr (SUM)
-      for (int q = G.chunk_ptr[b]; q < G.chunk_ptr[b + 1]; ++q)
+        for (int q = 0; q < k; ++q) v -= x[q] * m[6 * k + q];
+        x[k] = v / m[7 * k];
+      }
 #pragma unroll
-        for (int k = 0; k < 6; ++k) x[k] -= W.part[36 * (long long)q + 6 * a + k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      double v = x[k];
-#pragma unroll
-      for (int q = 0; q < k; ++q) v -= x[q] * m[6 * k + q];
-      x[k] = v / m[7 * k];
+      for (int k = 0; k < 6; ++k) row[k] = x[k];
     }
+    if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) row[k] = x[k];
-  }
-}
-
-// The level's partials subtracted from its blocks and right-hand sides, one
-// entry per thread, in chunk order (the narrow levels' variant of the sums
-// that phases 2 and 3 otherwise do per column / row).
-__device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
-  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
-  const double* fpart = W.part + 36 * (long long)G.n_chunks;
-  const int nb = (b1 - b0) * 36;
-  for (int t = t0; t < nb + (c1 - c0) * 6; t += stride) {
-    if (t < nb) {
-      const int b = b0 + t / 36, e = t % 36;
-      const int q0 = G.chunk_ptr[b], q1 = G.chunk_ptr[b + 1];
-      if (q0 == q1) continue;
-      double v = W.L[36 * (long long)b + e];
-      for (int q = q0; q < q1; ++q) v -= W.part[36 * (long long)q + e];
-      W.L[36 * (long long)b + e] = v;
-    } else {
-      const int c = c0 + (t - nb) / 6, a = (t - nb) % 6;
-      const int q0 = G.fchunk_ptr[c], q1 = G.fchunk_ptr[c + 1];
-      if (q0 == q1) continue;
-      double v = W.y[6 * c + a];
-      for (int q = q0; q < q1; ++q) v -= fpart[6 * (long long)q + a];
-      W.y[6 * c + a] = v;
+      for (int k = 0; k < 36; ++k) Lc[k] = m[k];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) W.y[6 * c + a] = yc[a];
     }
   }
 }
@@ -535,10 +531,8 @@ __global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_wide(PgoArgs A, int l, 
   const int t0 = blockIdx.x * kPgoEdgeThreads + threadIdx.x, stride = gridDim.x * kPgoEdgeThreads;
   if (phase == 1)
     pgo_phase1(A.G, A.W, l, t0, stride);
-  else if (phase == 2)
-    pgo_phase2<true>(A.G, A.W, l, t0, stride);
   else
-    pgo_phase3<true>(A.G, A.W, l, t0, stride);
+    pgo_phase23<true>(A.G, A.W, l, t0 >> 6, stride >> 6, threadIdx.x & 63);
 }
 
 // Levels [l0, n_levels) in one workgroup, then the back substitution.
@@ -552,10 +546,7 @@ __global__ __launch_bounds__(kPgoStepThreads) void k_pgo_factor(PgoArgs A, int l
     __syncthreads();
     pgo_phase1b(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
-    pgo_phase2<false>(G, W, l, tid, kPgoStepThreads);
-    __syncthreads();
-    if (W.istate[4]) break;
-    pgo_phase3<false>(G, W, l, tid, kPgoStepThreads);
+    pgo_phase23<false>(G, W, l, tid >> 6, kPgoStepThreads / 64, tid & 63);
     __syncthreads();
   }
   if (W.istate[4]) {
@@ -643,11 +634,10 @@ hipError_t run_pgo(const PgoArgs& A) {
     hipLaunchKernelGGL(k_pgo_assemble, dim3(ab > 0 ? ab : 1), dim3(kPgoEdgeThreads), 0, s, A);
     for (int l = 0; l < A.G.n_wide; ++l) {
       const int* w = A.wide_tasks + 3 * l;
-      for (int ph = 1; ph <= 3; ++ph) {
-        const int blocks = (w[ph - 1] + kPgoEdgeThreads - 1) / kPgoEdgeThreads;
-        if (blocks > 0)
-          hipLaunchKernelGGL(k_pgo_wide, dim3(blocks), dim3(kPgoEdgeThreads), 0, s, A, l, ph);
-      }
+      const int b1 = (w[0] + kPgoEdgeThreads - 1) / kPgoEdgeThreads;          // update tasks
+      const int b2 = (64 * w[1] + kPgoEdgeThreads - 1) / kPgoEdgeThreads;     // one wave per column
+      if (b1 > 0) hipLaunchKernelGGL(k_pgo_wide, dim3(b1), dim3(kPgoEdgeThreads), 0, s, A, l, 1);
+      if (b2 > 0) hipLaunchKernelGGL(k_pgo_wide, dim3(b2), dim3(kPgoEdgeThreads), 0, s, A, l, 2);
     }
     hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(kPgoStepThreads), 0, s, A, A.G.n_wide);
     hipLaunchKernelGGL(k_pgo_candidate, dim3(pb), dim3(kPgoEdgeThreads), 0, s, A);

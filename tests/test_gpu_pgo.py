@@ -81,6 +81,23 @@ def test_weights_and_several_fixed_poses():
     _check(d, s, _gpu(d, s, edge_w=w, fixed=fixed), edge_w=w, fixed=fixed)
 
 
+def test_reversed_and_repeated_edges():
+    """Edges stored j -> i (with the inverse delta) and an edge given twice."""
+    import paper_2506_04359_amd as ba
+    d = bagen.make_pose_graph(laps=2, per_lap=20, seed=16)
+    ei, ej, D = d.edge_i.copy(), d.edge_j.copy(), d.deltas.copy()
+    for e in range(0, d.n_edges, 3):
+        ei[e], ej[e] = d.edge_j[e], d.edge_i[e]
+        D[e] = pgo.inverse(d.deltas[e])
+    ei = np.concatenate([ei, ei[5:6]])
+    ej = np.concatenate([ej, ej[5:6]])
+    D = np.concatenate([D, D[5:6]])
+    r = bagen.PoseGraphData(poses_gt=d.poses_gt, poses_init=d.poses_init, edge_i=ei, edge_j=ej, deltas=D,
+                            edge_w=np.ones(ei.shape[0]), pose_fixed=d.pose_fixed, loop=np.zeros(ei.shape[0], bool))
+    s = ba.Settings(max_iters=8, precision=ba.BA_FP64)
+    _check(r, s, _gpu(r, s))
+
+
 def test_degenerate_graphs():
     """Negative weights (every factorisation fails: poses kept), every pose
     fixed, and a graph without edges."""
@@ -108,3 +125,40 @@ def test_benchmark_graph():
     assert g["info"]["n_levels"] <= 64
     ref = _check(d, s, g, backend="sparse")
     assert ref.final_cost < 0.2 * ref.initial_cost
+
+
+def test_graph_replays_equal_the_eager_solve():
+    """ba_pgo_solve captured in a HIP graph: every replay (with eager work and a
+    synchronisation between replays) gives the eager solve's poses and report
+    bit for bit."""
+    import torch
+    import paper_2506_04359_amd as ba
+    dev = torch.device("cuda:0")
+    d = bagen.make_pose_graph(laps=2, per_lap=60, seed=17)
+    g = ba.Graph(d.n_poses, d.edge_i, d.edge_j, d.pose_fixed)
+    s = ba.Settings(max_iters=6, precision=ba.BA_FP64)
+    P0 = torch.tensor(d.poses_init.reshape(-1, 12), dtype=torch.float64, device=dev)
+    P = P0.clone()
+    D = torch.tensor(d.deltas.reshape(-1, 12), dtype=torch.float64, device=dev)
+    raw = torch.empty(g.workspace_size() + 256, dtype=torch.uint8, device=dev)
+    off = (-raw.data_ptr()) % 256
+    ws = raw[off:off + g.workspace_size()]
+    rep = torch.zeros(48, dtype=torch.uint8, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ba.pgo_solve(g, s, P, D, ws, report=rep)
+    torch.cuda.synchronize()
+    eager_P, eager_rep = P.clone(), rep.clone()
+    graph = torch.cuda.CUDAGraph()
+    P.copy_(P0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=side):
+        ba.pgo_solve(g, s, P, D, ws, report=rep)
+    for _ in range(3):
+        P.copy_(P0)
+        rep.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(P, eager_P) and torch.equal(rep, eager_rep)
