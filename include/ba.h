@@ -30,10 +30,19 @@
  * Ownership: the caller owns every device buffer and the workspace.  The
  * library owns plan handles (ba_window, ba_batch); they are immutable after
  * creation and may be used concurrently on different streams with different
- * workspaces.  ba_solve, ba_solve_batched and ba_adjoint allocate nothing,
- * never synchronise the stream and never read device memory back to the host,
- * so a caller may capture them into a HIP graph.  Plan creation allocates
- * device memory for the plan's index arrays (on the current device).
+ * workspaces.  ba_solve, ba_solve_batched and ba_adjoint allocate no device
+ * memory, never synchronise the stream and never read device memory back to
+ * the host, so a caller may capture them into a HIP graph.  Plan creation
+ * allocates device memory for the plan's index arrays (on the current device).
+ * Side streams: on a plan whose windows fall into two or more size classes of
+ * the Schur kernel (up to 8, 16, 23 and 32 free poses), the first call that is
+ * not under stream capture creates two streams (default priority) and three
+ * events, kept until the plan is destroyed.  Every later call forks the two
+ * largest classes onto them from `stream` and joins them back with events, so
+ * all of the call's work is still ordered on `stream`, and a capture records
+ * the fork and join.  Until then (or for a one-class plan) everything runs on
+ * `stream`.  Calls on one plan from several streams share the side streams:
+ * still correct, but their Schur kernels wait for each other there.
  *
  * Errors: every call returns ba_status.  Argument and structure errors are
  * detected on the host before any device work and return a negative status;

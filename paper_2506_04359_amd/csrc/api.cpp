@@ -100,8 +100,19 @@ struct ba_batch_s {
   DevPlan plan{};
   DeviceTables tables[2];   // [0]: small tiles, [1]: large tiles
   int chunk_obs = 4096;
+  // pass A's side streams and their fork / join events (made by the first
+  // launch of a plan with two or more size classes that is not under stream
+  // capture)
+  bool have_side = false;
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kSideStreams] = {};
   std::mutex mu;
   ~ba_batch_s() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (int k = 0; k < kSideStreams; ++k) {
+      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+      if (side[k]) (void)hipStreamDestroy(side[k]);
+    }
     if (mem) (void)hipFree(mem);
     for (auto& t : tables)
       if (t.mem) (void)hipFree(t.mem);
@@ -406,6 +417,40 @@ DevTiles dev_tiles(const DeviceTables& t) {
   return d;
 }
 
+// Pass A's side streams (default priority, no implicit synchronisation with
+// other streams) and events, made on the batch's device by the first launch
+// that is not being captured; a capture before any such launch runs pass A
+// on the launch stream alone.  The caller holds b->mu.
+ba_status ensure_side_stream(ba_batch_s* b, void* stream) {
+  if (b->have_side) return BA_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing((hipStream_t)stream, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone) return BA_OK;
+  int cur = 0;
+  if ((e = hipGetDevice(&cur)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipSetDevice(b->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming);
+  }
+  (void)hipSetDevice(cur);
+  if (e != hipSuccess) {
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    b->ev_fork = nullptr;
+    for (int k = 0; k < kSideStreams; ++k) {
+      if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+      if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+      b->ev_join[k] = nullptr;
+      b->side[k] = nullptr;
+    }
+    return hip_fail(e, "side streams");
+  }
+  b->have_side = true;
+  return BA_OK;
+}
+
 enum class Op { Solve, Adjoint, Timed };
 
 ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws, size_t ws_bytes,
@@ -434,6 +479,12 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.list_bytes = t.list_bytes;
   A.max_cpw = t.max_cpw;
   A.stream = stream;
+  int n_classes = 0;
+  for (int c = 0; c < kClasses; ++c) n_classes += t.cls_begin[c + 1] > t.cls_begin[c];
+  if (n_classes >= 2 && (st = ensure_side_stream(b, stream)) != BA_OK) return st;
+  A.side_stream = b->have_side ? (void*)b->side : nullptr;
+  A.ev_fork = b->ev_fork;
+  A.ev_join = (void*)b->ev_join;
   hipError_t e;
   if (s->precision == BA_FP64) {
     const DevWork<double> K = make_work<double>(L, ws, has_w);

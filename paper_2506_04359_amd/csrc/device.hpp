@@ -94,6 +94,8 @@ constexpr int kDpStride = 192;
 constexpr int kSumSlice = 1024;   // entries of the summed system per workgroup of k_sum
 constexpr int kSumSlices = (528 * kBS + 12 * 32 + kSumSlice - 1) / kSumSlice;
 
+constexpr int kSideStreams = 2;   // side streams of pass A's size classes
+
 // Dimensions of the window caches in LDS (largest in the launch).
 struct LdsDims {
   int np, nc;
@@ -112,6 +114,12 @@ struct LaunchArgs {
   int list_bytes;                // largest per-tile product list (segments + products)
   int max_cpw;                   // largest number of chunks of one window
   void* stream;                  // hipStream_t
+  // Pass A's side streams (hipStream_t[kSideStreams], or NULL to run
+  // everything on `stream`), the event that forks them from `stream` and the
+  // events (hipEvent_t[kSideStreams]) that join them back.
+  void* side_stream;
+  void* ev_fork;
+  void* ev_join;
 };
 
 }  // namespace ba

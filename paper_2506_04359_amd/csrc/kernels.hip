@@ -1596,16 +1596,64 @@ hipError_t set_attrs() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-// Pass A once per size class, each with the LDS its largest window needs.
+// Pass A over the size classes, each launch with the LDS its largest window
+// needs.  With side streams, the largest class and the next one each run on a
+// side stream, concurrently with the rest on the launch stream: the classes
+// share the CUs, so one class's long workgroups fill the others' launch tails,
+// and workgroups of a small class fit beside one of the largest class in the
+// LDS of a CU (measured on the 256-window batch: +21 % LM attempts per second
+// over the four launches in sequence; merging classes of equal occupancy into
+// one launch gained 6 %).
+struct PassAGroup {
+  int begin, n;
+  size_t lds;
+  int stream;   // 0: the launch stream, k > 0: side stream k - 1
+};
+
 template <typename Real, int TP, bool ADJ>
-void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
+int pass_a_groups(const LaunchArgs& A, PassAGroup* g) {
+  int ng = 0;
   for (int c = 0; c < kClasses; ++c) {
     const int n = A.cls_begin[c + 1] - A.cls_begin[c];
     if (n <= 0) continue;
     const size_t lds = pass_a_lds<Real, TP>(A.dims.np, A.dims.nc, A.cls_nf[c], A.list_bytes, ADJ);
-    hipLaunchKernelGGL((k_pass_a<Real, TP, ADJ>), dim3(n), dim3(TP), lds, (hipStream_t)A.stream,
-                       A.plan, A.tiles, K, A.user, A.settings, it, A.cls_begin[c], A.dims);
+    g[ng++] = PassAGroup{A.cls_begin[c], n, lds, 0};
   }
+  if (A.side_stream && ng >= 2) {
+    g[ng - 1].stream = 1;
+    if (ng >= 3) g[ng - 2].stream = 2;
+  }
+  return ng;
+}
+
+template <typename Real, int TP, bool ADJ>
+void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
+  static_assert(kSideStreams >= 2, "pass A uses two side streams");
+  PassAGroup g[kClasses];
+  const int ng = pass_a_groups<Real, TP, ADJ>(A, g);
+  const hipStream_t main = (hipStream_t)A.stream;
+  const hipStream_t* side = (const hipStream_t*)A.side_stream;
+  const hipEvent_t* join = (const hipEvent_t*)A.ev_join;
+  bool used[kSideStreams + 1] = {};
+  for (int k = 0; k < ng; ++k) used[g[k].stream] = true;
+  bool fork = false;
+  for (int s = 1; s <= kSideStreams; ++s) fork = fork || used[s];
+  if (fork) (void)hipEventRecord((hipEvent_t)A.ev_fork, main);
+  for (int s = 1; s <= kSideStreams; ++s)
+    if (used[s]) (void)hipStreamWaitEvent(side[s - 1], (hipEvent_t)A.ev_fork, 0);
+  for (int k = ng - 1; k >= 0; --k)   // side launches first
+    if (g[k].stream)
+      hipLaunchKernelGGL((k_pass_a<Real, TP, ADJ>), dim3(g[k].n), dim3(TP), g[k].lds, side[g[k].stream - 1], A.plan,
+                         A.tiles, K, A.user, A.settings, it, g[k].begin, A.dims);
+  for (int k = 0; k < ng; ++k)
+    if (!g[k].stream)
+      hipLaunchKernelGGL((k_pass_a<Real, TP, ADJ>), dim3(g[k].n), dim3(TP), g[k].lds, main, A.plan, A.tiles, K,
+                         A.user, A.settings, it, g[k].begin, A.dims);
+  for (int s = 1; s <= kSideStreams; ++s)
+    if (used[s]) {
+      (void)hipEventRecord(join[s - 1], side[s - 1]);
+      (void)hipStreamWaitEvent(main, join[s - 1], 0);
+    }
 }
 
 template <typename Real, int TP>

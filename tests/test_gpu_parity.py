@@ -173,3 +173,52 @@ def test_batched_fp64_matches_oracle():
         assert abs(o["report"]["final_cost"] - ref.final_cost) <= TOL64 * ref.final_cost
         P, L, _ = oracle.align_scale(o["poses"], o["points"], ref.poses)
         assert rel_err(P, ref.poses) <= TOL64 and rel_err(L, ref.points) <= TOL64
+
+
+def test_batched_graph_replays_equal_eager_solve():
+    """Windows of all four size classes, so that pass A forks its largest class
+    onto a second stream: replays of a captured mixed solve, with eager work and
+    synchronisations between them, reproduce the eager solve bit for bit."""
+    import torch
+    import paper_2506_04359_amd as ba
+    from paper_2506_04359_amd._binding import REPORT_DTYPE
+    ws = [bagen.make_window(3, i) for i in (6, 2, 5, 3, 13, 15, 23)]
+    nfree = sorted(int(np.sum(w.pose_fixed == 0)) for w in ws)
+    assert nfree[0] <= 8 and nfree[-1] > 23
+    s = ba.Settings(max_iters=6, precision=ba.BA_MIXED)
+    dev = torch.device("cuda:0")
+    B = ba.Batch([ba.Window.from_problem(w, host_only=True) for w in ws])
+    B.set_launch(2048)
+    cat = lambda xs: torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    P0, L0 = cat([w.poses_init for w in ws]), cat([w.points_init for w in ws])
+    uv = cat([w.obs_uv for w in ws])
+    P, L = P0.clone(), L0.clone()
+    work = torch.empty(B.workspace_size(s), dtype=torch.uint8, device=dev)
+    rep = torch.zeros(REPORT_DTYPE.itemsize * len(ws), dtype=torch.uint8, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+
+    def step():
+        P.copy_(P0)
+        L.copy_(L0)
+        ba.solve_batched(B, s, P, L, uv, None, work, rep)
+
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.synchronize()
+    Pe, Le, Re = P.cpu(), L.cpu(), rep.cpu()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        step()
+    torch.cuda.synchronize()
+    for k in range(3):
+        P.fill_(0.0)
+        L.fill_(0.0)
+        rep.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(P.cpu(), Pe) and torch.equal(L.cpu(), Le), k
+        assert torch.equal(rep.cpu(), Re), k
+    r = ba.parse_reports(Re)
+    assert np.all(r["status"] == 0) and np.all(r["final_cost"] < r["initial_cost"])
