@@ -37,12 +37,13 @@
  * Side streams: on a plan whose windows fall into two or more size classes of
  * the Schur kernel (up to 8, 16, 23 and 32 free poses), the first call that is
  * not under stream capture creates two streams (default priority) and three
- * events, kept until the plan is destroyed.  Every later call forks the two
- * largest classes onto them from `stream` and joins them back with events, so
- * all of the call's work is still ordered on `stream`, and a capture records
- * the fork and join.  Until then (or for a one-class plan) everything runs on
+ * events, kept until the plan is destroyed.  Every later call forks the work
+ * of the two largest classes onto them from `stream` (a solve: their whole LM
+ * loop; the adjoint: their Schur kernel) and joins it back with events, so all
+ * of the call's work is still ordered on `stream`, and a capture records the
+ * fork and join.  Until then (or for a one-class plan) everything runs on
  * `stream`.  Calls on one plan from several streams share the side streams:
- * still correct, but their Schur kernels wait for each other there.
+ * still correct, but their forked work waits for each other there.
  *
  * Errors: every call returns ba_status.  Argument and structure errors are
  * detected on the host before any device work and return a negative status;

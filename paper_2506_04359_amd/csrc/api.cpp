@@ -81,7 +81,10 @@ struct DeviceTables {
   int32_t* pair_rec = nullptr;
   int32_t* tile_rec = nullptr;
   uint32_t* lists = nullptr;
+  int32_t* win_order = nullptr;
   int cls_begin[kClasses + 1] = {0, 0, 0, 0, 0};
+  int cls_win_begin[kClasses + 1] = {0, 0, 0, 0, 0};
+  int cls_win_nf[kClasses] = {0, 0, 0, 0};
   int cls_nf[kClasses] = {0, 0, 0, 0};
   int list_bytes = 0;   // largest per-tile segment + product list
   int max_cpw = 0;      // largest chunk count of one window
@@ -168,6 +171,7 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   const size_t o_ct = blob.add(t.chunk_tile_begin);
   const size_t o_cp = blob.add(t.chunk_part_off);
   const size_t o_co = blob.add(t.chunk_order);
+  const size_t o_wo = blob.add(t.win_order);
   const size_t o_pr = blob.add(t.pair_rec);
   const size_t o_tr = blob.add(t.tile_rec);
   const size_t o_ls = blob.add(t.lists);
@@ -195,6 +199,7 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   D.chunk_tile_begin = (int32_t*)((char*)mem + o_ct);
   D.chunk_part_off = (int64_t*)((char*)mem + o_cp);
   D.chunk_order = (int32_t*)((char*)mem + o_co);
+  D.win_order = (int32_t*)((char*)mem + o_wo);
   D.pair_rec = (int32_t*)((char*)mem + o_pr);
   D.tile_rec = (int32_t*)((char*)mem + o_tr);
   D.lists = (uint32_t*)((char*)mem + o_ls);
@@ -203,6 +208,8 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   for (size_t i = 0; i + 1 < t.win_chunk_begin.size(); ++i)
     D.max_cpw = std::max(D.max_cpw, t.win_chunk_begin[i + 1] - t.win_chunk_begin[i]);
   for (int c = 0; c <= kClasses; ++c) D.cls_begin[c] = t.class_begin[c];
+  for (int c = 0; c <= kClasses; ++c) D.cls_win_begin[c] = t.class_win_begin[c];
+  for (int c = 0; c < kClasses; ++c) D.cls_win_nf[c] = t.class_win_nf[c];
   for (int c = 0; c < kClasses; ++c) D.cls_nf[c] = t.class_nf[c];
   return BA_OK;
 }
@@ -410,6 +417,7 @@ DevTiles dev_tiles(const DeviceTables& t) {
   d.chunk_tile_begin = t.chunk_tile_begin;
   d.chunk_part_off = t.chunk_part_off;
   d.chunk_order = t.chunk_order;
+  d.win_order = t.win_order;
   d.pair_rec = t.pair_rec;
   d.tile_rec = t.tile_rec;
   d.lists = t.lists;
@@ -473,6 +481,8 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.settings = dev_settings(s);
   A.max_nf = b->max_nf;
   for (int c = 0; c <= kClasses; ++c) A.cls_begin[c] = t.cls_begin[c];
+  for (int c = 0; c <= kClasses; ++c) A.cls_win_begin[c] = t.cls_win_begin[c];
+  for (int c = 0; c < kClasses; ++c) A.cls_win_nf[c] = t.cls_win_nf[c];
   for (int c = 0; c < kClasses; ++c) A.cls_nf[c] = t.cls_nf[c];
   A.dims.np = b->max_np;
   A.dims.nc = b->max_nc;

@@ -43,6 +43,7 @@ struct DevPlan {
 
 struct DevTiles {
   const int32_t* chunk_order;     // chunks grouped by size class
+  const int32_t* win_order;       // windows grouped by size class
   const int32_t* pair_rec;        // 4 per pair position (thread order of its tile)
   const int32_t* tile_rec;        // 8 per tile
   const uint32_t* lists;          // per tile: segment words then products
@@ -94,7 +95,7 @@ constexpr int kDpStride = 192;
 constexpr int kSumSlice = 1024;   // entries of the summed system per workgroup of k_sum
 constexpr int kSumSlices = (528 * kBS + 12 * 32 + kSumSlice - 1) / kSumSlice;
 
-constexpr int kSideStreams = 2;   // side streams of pass A's size classes
+constexpr int kSideStreams = 2;   // side streams of the size classes
 
 // Dimensions of the window caches in LDS (largest in the launch).
 struct LdsDims {
@@ -109,6 +110,8 @@ struct LaunchArgs {
   DevSettings settings;
   int max_nf;
   int cls_begin[kClasses + 1];   // chunk_order ranges of the size classes
+  int cls_win_begin[kClasses + 1];   // win_order ranges of the size classes
+  int cls_win_nf[kClasses];      // largest free-pose count of each class's windows
   int cls_nf[kClasses];          // largest free-pose count of each class
   LdsDims dims;                  // largest pose / camera count of the batch
   int list_bytes;                // largest per-tile product list (segments + products)

@@ -307,6 +307,19 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
     }
   }
   t.class_begin[kClasses] = (int32_t)t.chunk_order.size();
+  // the windows of each class, in window order (every chunk of a window is in
+  // its window's class)
+  t.win_order.clear();
+  for (int c = 0; c < kClasses; ++c) {
+    t.class_win_begin[c] = (int32_t)t.win_order.size();
+    t.class_win_nf[c] = 0;
+    for (int32_t i = 0; i < (int32_t)wins.size(); ++i)
+      if (size_class(wins[i]->n_free) == c) {
+        t.win_order.push_back(i);
+        t.class_win_nf[c] = std::max(t.class_win_nf[c], wins[i]->n_free);
+      }
+  }
+  t.class_win_begin[kClasses] = (int32_t)t.win_order.size();
 }
 
 }  // namespace ba

@@ -79,6 +79,9 @@ struct LaunchTables {
   std::vector<int64_t> chunk_part_off;   // n_chunks, element offset of its S partial
   std::vector<int32_t> chunk_order;      // n_chunks, grouped by size class
   int32_t class_begin[kClasses + 1] = {0, 0, 0, 0, 0};
+  std::vector<int32_t> win_order;        // n_windows, grouped by size class
+  int32_t class_win_begin[kClasses + 1] = {0, 0, 0, 0, 0};
+  int32_t class_win_nf[kClasses] = {0, 0, 0, 0};   // largest n_free of the class's windows
   int32_t class_nf[kClasses] = {0, 0, 0, 0};   // largest n_free in each class
   int64_t part_elems = 0;                // total partial elements
   // Per tile, the order in which its pairs are handled: free pairs sorted by
