@@ -114,3 +114,45 @@ def test_autograd_function_matches_direct_adjoint():
     ruv, rw = oracle.adjoint_dense(Pn, Ln, prob, 1.0, gx)
     assert np.abs(uv.grad.cpu().numpy() - ruv).max() <= 1e-8 * np.abs(ruv).max()
     assert np.abs(ow.grad.cpu().numpy() - rw).max() <= 1e-8 * np.abs(rw).max()
+
+
+def test_fp64_batched_adjoint_of_four_classes_matches_single_windows():
+    """A batch whose windows fall into all four size classes (pass A forks the
+    two largest classes onto side streams): every window's adjoint equals the
+    single-window call's, and the single-window calls follow the dense oracle."""
+    import torch
+    import paper_2506_04359_amd as ba
+    ws = [bagen.tiny_window(seed=80 + k, n_kf=n, n_lm=25, noise=0.6, fixed=(0, 1))
+          for k, n in enumerate((6, 15, 22, 28))]
+    assert [int((w.pose_fixed == 0).sum()) for w in ws] == [4, 13, 20, 26]
+    dev = torch.device("cuda:0")
+    s = ba.Settings(max_iters=1, precision=ba.BA_FP64)
+    single = []
+    for k, w in enumerate(ws):
+        P0, L0 = np.ascontiguousarray(w.poses_gt), np.ascontiguousarray(w.points_gt)
+        guv, gw, rep, G = _gpu_adjoint(w, s, P0, L0)
+        assert rep["chol_failures"] == 0
+        if k == 0:
+            ruv, rw = _oracle_adjoint(w, P0, L0, G)
+            assert np.abs(guv - ruv).max() <= 1e-9 * np.abs(ruv).max()
+            assert np.abs(gw - rw).max() <= 1e-9 * np.abs(rw).max()
+        single.append((guv, gw, G))
+    B = ba.Batch([ba.Window.from_problem(w, host_only=True) for w in ws])
+    cat = lambda xs: torch.tensor(np.ascontiguousarray(np.concatenate(xs)), dtype=torch.float64, device=dev)
+    P, L = cat([w.poses_gt for w in ws]), cat([w.points_gt for w in ws])
+    uv = cat([w.obs_uv for w in ws])
+    gP = cat([g[2] for g in single])
+    guv = torch.zeros_like(uv)
+    gw = torch.zeros(uv.shape[0], dtype=torch.float64, device=dev)
+    for _ in range(2):   # the first call makes the side streams, the second forks onto them
+        guv.zero_()
+        gw.zero_()
+        rep, _ = ba.adjoint(B, s, P, L, uv, None, gP, None, guv, gw)
+        torch.cuda.synchronize()
+        assert np.all(ba.parse_reports(rep)[: len(ws)]["chol_failures"] == 0)
+        o = 0
+        for w, (suv, sw, _) in zip(ws, single):
+            buv, bw = guv[o:o + w.n_obs].cpu().numpy(), gw[o:o + w.n_obs].cpu().numpy()
+            assert np.abs(buv - suv).max() <= 1e-9 * np.abs(suv).max()
+            assert np.abs(bw - sw).max() <= 1e-9 * np.abs(sw).max()
+            o += w.n_obs

@@ -166,3 +166,23 @@ def test_batch_with_an_empty_window():
     assert r["initial_cost"] == 0.0 and r["final_cost"] == 0.0 and r["accepted"] == 0
     assert r["iters"] == 6
     assert np.array_equal(out[1]["poses"], e.poses_init)
+
+
+def test_four_class_batch_with_an_empty_largest_class():
+    """Windows of four size classes, so that each class runs its LM loop as its
+    own chain: the largest class holds only a window without landmarks (its
+    chain has no pass-A or pass-B work), the others follow the oracle."""
+    import paper_2506_04359_amd as ba
+    a = bagen.tiny_window(seed=74, n_kf=4, n_lm=15)
+    b = bagen.tiny_window(seed=75, n_kf=12, n_lm=30)
+    c = bagen.tiny_window(seed=76, n_kf=20, n_lm=40)
+    e = _empty_like(bagen.tiny_window(seed=77, n_kf=27, n_lm=4), n_poses=27)
+    assert [int((w.pose_fixed == 0).sum()) for w in (a, b, c, e)] == [3, 11, 19, 26]
+    s = ba.Settings(max_iters=6, precision=ba.BA_FP64)
+    out = gpu_solve_batched([c, e, a, b], s)
+    for w, o in ((c, out[0]), (a, out[2]), (b, out[3])):
+        _fp64_replay_parity(w, s, o)
+    r = out[1]["report"]
+    assert r["initial_cost"] == 0.0 and r["final_cost"] == 0.0 and r["accepted"] == 0
+    assert r["iters"] == 6
+    assert np.array_equal(out[1]["poses"], e.poses_init)

@@ -189,7 +189,7 @@ def test_batched_graph_replays_equal_eager_solve():
     dev = torch.device("cuda:0")
     B = ba.Batch([ba.Window.from_problem(w, host_only=True) for w in ws])
     B.set_launch(2048)
-    cat = lambda xs: torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    cat = lambda xs: torch.tensor(np.ascontiguousarray(np.concatenate(xs)), dtype=torch.float64, device=dev)
     P0, L0 = cat([w.poses_init for w in ws]), cat([w.points_init for w in ws])
     uv = cat([w.obs_uv for w in ws])
     P, L = P0.clone(), L0.clone()
@@ -222,3 +222,12 @@ def test_batched_graph_replays_equal_eager_solve():
         assert torch.equal(rep.cpu(), Re), k
     r = ba.parse_reports(Re)
     assert np.all(r["status"] == 0) and np.all(r["final_cost"] < r["initial_cost"])
+    # the per-stage timing solve (every attempt's stages over all windows, the
+    # size classes joined per attempt) computes the same solve
+    P.copy_(P0)
+    L.copy_(L0)
+    stages = B.profile_stages(s, P, L, uv, None, work, rep)
+    torch.cuda.synchronize()
+    assert all(v > 0.0 for v in stages.values()), stages
+    assert torch.equal(P.cpu(), Pe) and torch.equal(L.cpu(), Le)
+    assert torch.equal(rep.cpu(), Re)
