@@ -39,7 +39,7 @@
  * not under stream capture creates two streams (default priority) and three
  * events, kept until the plan is destroyed.  Every later call forks the work
  * of the two largest classes onto them from `stream` (a solve: their whole LM
- * loop; the adjoint: their Schur kernel) and joins it back with events, so all
+ * loop; the adjoint: its one pass) and joins it back with events, so all
  * of the call's work is still ordered on `stream`, and a capture records the
  * fork and join.  Until then (or for a one-class plan) everything runs on
  * `stream`.  Calls on one plan from several streams share the side streams:

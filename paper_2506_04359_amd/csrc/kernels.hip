@@ -1701,7 +1701,56 @@ void launch_pass_a_class(const LaunchArgs& A, const DevWork<Real>& K, int it, in
 // launch stream (as pass A's split in launch_pass_a).  The small grids of the
 // reduce and pass B then overlap with other classes' pass A instead of every
 // class waiting for the slowest one in each attempt (256-window batch: 271 k
-// -> 285 k LM attempts/s; four chains on four streams: 279 k).
+// -> 285 k LM attempts/s; four chains on four streams: 279 k; the smallest
+// class on a side stream with a larger one: 242-273 k).
+struct ClassChains {
+  int n = 0, nside = 0;
+  int cls[kClasses];            // the classes that hold windows, ascending
+  hipStream_t st[kClasses];     // the stream of each
+};
+
+// The chains of a launch, or n = 0 when everything runs on the launch stream
+// (no side streams, or fewer than two classes).
+inline ClassChains class_chains(const LaunchArgs& A) {
+  ClassChains C;
+  int ncls = 0;
+  for (int c = 0; c < kClasses; ++c)
+    if (A.cls_win_begin[c + 1] > A.cls_win_begin[c]) C.cls[ncls++] = c;
+  if (!A.side_stream || ncls < 2) return C;
+  const hipStream_t* side = (const hipStream_t*)A.side_stream;
+  C.n = ncls;
+  C.nside = ncls >= 3 ? 2 : 1;   // classes on side streams: the largest nside
+  for (int k = 0; k < ncls; ++k) {
+    const int r = ncls - 1 - k;  // rank from the largest class
+    C.st[k] = r < C.nside ? side[r] : (hipStream_t)A.stream;
+  }
+  return C;
+}
+
+inline void fork_chains(const LaunchArgs& A, const ClassChains& C) {
+  const hipStream_t* side = (const hipStream_t*)A.side_stream;
+  (void)hipEventRecord((hipEvent_t)A.ev_fork, (hipStream_t)A.stream);
+  for (int r = 0; r < C.nside; ++r) (void)hipStreamWaitEvent(side[r], (hipEvent_t)A.ev_fork, 0);
+}
+
+inline void join_chains(const LaunchArgs& A, const ClassChains& C) {
+  const hipStream_t* side = (const hipStream_t*)A.side_stream;
+  const hipEvent_t* join = (const hipEvent_t*)A.ev_join;
+  for (int r = 0; r < C.nside; ++r) {
+    (void)hipEventRecord(join[r], side[r]);
+    (void)hipStreamWaitEvent((hipStream_t)A.stream, join[r], 0);
+  }
+}
+
+// One attempt of class C.cls[k] on its chain's stream.
+template <typename Real, int TP, bool ADJ>
+void launch_class_attempt(const LaunchArgs& A, const DevWork<Real>& K, int it, const ClassChains& C, int k) {
+  const int c = C.cls[k];
+  launch_pass_a_class<Real, TP, ADJ>(A, K, it, c, C.st[k]);
+  launch_stages<Real, TP, ADJ>(A, K, it, A.cls_win_begin[c], A.cls_win_begin[c + 1] - A.cls_win_begin[c],
+                               A.cls_begin[c], A.cls_begin[c + 1] - A.cls_begin[c], A.cls_win_nf[c], C.st[k]);
+}
+
 template <typename Real, int TP>
 hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
@@ -1709,31 +1758,12 @@ hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, main, A.plan, K, A.settings);
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, main, A.plan, A.tiles, K, A.user);
   const int iters = A.settings.max_iters;
-  int cls[kClasses], ncls = 0;
-  for (int c = 0; c < kClasses; ++c)
-    if (A.cls_win_begin[c + 1] > A.cls_win_begin[c]) cls[ncls++] = c;
-  if (A.side_stream && ncls >= 2 && iters > 0) {
-    const hipStream_t* side = (const hipStream_t*)A.side_stream;
-    const hipEvent_t* join = (const hipEvent_t*)A.ev_join;
-    const int nside = ncls >= 3 ? 2 : 1;   // classes on side streams: the largest nside
-    hipStream_t st[kClasses];
-    for (int k = 0; k < ncls; ++k) {
-      const int r = ncls - 1 - k;   // rank from the largest class
-      st[k] = r < nside ? side[r] : main;
-    }
-    (void)hipEventRecord((hipEvent_t)A.ev_fork, main);
-    for (int r = 0; r < nside; ++r) (void)hipStreamWaitEvent(side[r], (hipEvent_t)A.ev_fork, 0);
+  const ClassChains C = class_chains(A);
+  if (C.n > 0 && iters > 0) {
+    fork_chains(A, C);
     for (int it = 0; it < iters; ++it)
-      for (int k = ncls - 1; k >= 0; --k) {
-        const int c = cls[k];
-        launch_pass_a_class<Real, TP, false>(A, K, it, c, st[k]);
-        launch_stages<Real, TP, false>(A, K, it, A.cls_win_begin[c], A.cls_win_begin[c + 1] - A.cls_win_begin[c],
-                                       A.cls_begin[c], A.cls_begin[c + 1] - A.cls_begin[c], A.cls_win_nf[c], st[k]);
-      }
-    for (int r = 0; r < nside; ++r) {
-      (void)hipEventRecord(join[r], side[r]);
-      (void)hipStreamWaitEvent(main, join[r], 0);
-    }
+      for (int k = C.n - 1; k >= 0; --k) launch_class_attempt<Real, TP, false>(A, K, it, C, k);
+    join_chains(A, C);
   } else {
     for (int it = 0; it < iters; ++it) {
       launch_pass_a<Real, TP, false>(A, K, it);
@@ -1746,14 +1776,22 @@ hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   return hipGetLastError();
 }
 
+// The adjoint's single pass, in the same class chains as a solve.
 template <typename Real, int TP>
 hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
   const int nw = A.plan.n_windows, nc = A.tiles.n_chunks;
   const hipStream_t main = (hipStream_t)A.stream;
   hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, main, A.plan, K, A.settings);
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, main, A.plan, A.tiles, K, A.user);
-  launch_pass_a<Real, TP, true>(A, K, 0);
-  launch_stages<Real, TP, true>(A, K, 0, 0, nw, 0, nc, A.max_nf, main);
+  const ClassChains C = class_chains(A);
+  if (C.n > 0) {
+    fork_chains(A, C);
+    for (int k = C.n - 1; k >= 0; --k) launch_class_attempt<Real, TP, true>(A, K, 0, C, k);
+    join_chains(A, C);
+  } else {
+    launch_pass_a<Real, TP, true>(A, K, 0);
+    launch_stages<Real, TP, true>(A, K, 0, 0, nw, 0, nc, A.max_nf, main);
+  }
   return hipGetLastError();
 }
 
