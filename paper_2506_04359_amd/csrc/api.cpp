@@ -103,9 +103,9 @@ struct ba_batch_s {
   DevPlan plan{};
   DeviceTables tables[2];   // [0]: small tiles, [1]: large tiles
   int chunk_obs = 4096;
-  // pass A's side streams and their fork / join events (made by the first
-  // launch of a plan with two or more size classes that is not under stream
-  // capture)
+  // the side streams of the size classes and their fork / join events (made
+  // by the first launch of a plan with two or more size classes that is not
+  // under stream capture)
   bool have_side = false;
   hipStream_t side[kSideStreams] = {};
   hipEvent_t ev_fork = nullptr, ev_join[kSideStreams] = {};
@@ -425,10 +425,10 @@ DevTiles dev_tiles(const DeviceTables& t) {
   return d;
 }
 
-// Pass A's side streams (default priority, no implicit synchronisation with
-// other streams) and events, made on the batch's device by the first launch
-// that is not being captured; a capture before any such launch runs pass A
-// on the launch stream alone.  The caller holds b->mu.
+// The side streams of the size classes (default priority, no implicit
+// synchronisation with other streams) and their events, made on the batch's
+// device by the first launch that is not being captured; a capture before any
+// such launch runs everything on the launch stream.  The caller holds b->mu.
 ba_status ensure_side_stream(ba_batch_s* b, void* stream) {
   if (b->have_side) return BA_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -490,7 +490,7 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.max_cpw = t.max_cpw;
   A.stream = stream;
   int n_classes = 0;
-  for (int c = 0; c < kClasses; ++c) n_classes += t.cls_begin[c + 1] > t.cls_begin[c];
+  for (int c = 0; c < kClasses; ++c) n_classes += t.cls_win_begin[c + 1] > t.cls_win_begin[c];
   if (n_classes >= 2 && (st = ensure_side_stream(b, stream)) != BA_OK) return st;
   A.side_stream = b->have_side ? (void*)b->side : nullptr;
   A.ev_fork = b->ev_fork;

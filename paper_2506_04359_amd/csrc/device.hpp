@@ -117,9 +117,9 @@ struct LaunchArgs {
   int list_bytes;                // largest per-tile product list (segments + products)
   int max_cpw;                   // largest number of chunks of one window
   void* stream;                  // hipStream_t
-  // Pass A's side streams (hipStream_t[kSideStreams], or NULL to run
-  // everything on `stream`), the event that forks them from `stream` and the
-  // events (hipEvent_t[kSideStreams]) that join them back.
+  // The side streams of the size classes (hipStream_t[kSideStreams], or NULL
+  // to run everything on `stream`), the event that forks them from `stream`
+  // and the events (hipEvent_t[kSideStreams]) that join them back.
   void* side_stream;
   void* ev_fork;
   void* ev_join;
