@@ -184,7 +184,9 @@ ba_status ba_solve(ba_window w, const ba_settings* s, double* poses, double* poi
                    size_t ws_bytes, ba_report* report, ba_iter_trace* trace, void* stream);
 
 /* Solve every window of a batch in one launch sequence (one kernel per stage
- * covering all windows).  Arrays are packed window-major (see ba_batch_create);
+ * and size class covering that class's windows; the classes run as concurrent
+ * chains, see "Side streams" above).  Arrays are packed window-major (see
+ * ba_batch_create);
  * reports: DEVICE, n_windows; traces: DEVICE, n_windows x max_iters or NULL.
  * Every window runs the same number of attempts. */
 ba_status ba_solve_batched(ba_batch b, const ba_settings* s, double* poses, double* points,
