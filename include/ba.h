@@ -28,12 +28,19 @@
  *                       rejected attempt.  Exactly max_iters attempts run.
  *
  * Ownership: the caller owns every device buffer and the workspace.  The
- * library owns plan handles (ba_window, ba_batch); they are immutable after
- * creation and may be used concurrently on different streams with different
- * workspaces.  ba_solve, ba_solve_batched and ba_adjoint allocate no device
- * memory, never synchronise the stream and never read device memory back to
- * the host, so a caller may capture them into a HIP graph.  Plan creation
- * allocates device memory for the plan's index arrays (on the current device).
+ * library owns plan handles (ba_window, ba_batch).  A plan's structure is
+ * immutable after creation; its one mutable part is the launch shape, which
+ * ba_set_launch and ba_autotune replace (with new launch tables, and possibly
+ * a new workspace size: query ba_workspace_size again).  Once any call on a
+ * plan has been captured into a HIP graph, the tables they replace are kept
+ * until the plan is destroyed, so a graph captured earlier still replays the
+ * shape it was captured with (with the workspace it was captured with).  A
+ * plan may be used concurrently on different streams with different
+ * workspaces; re-tuning it concurrently with a solve is not allowed.
+ * ba_solve, ba_solve_batched and ba_adjoint allocate no device memory, never
+ * synchronise the stream and never read device memory back to the host, so a
+ * caller may capture them into a HIP graph.  Plan creation allocates device
+ * memory for the plan's index arrays (on the current device).
  * Side streams: on a plan whose windows fall into two or more size classes of
  * the Schur kernel (up to 8, 16, 23 and 32 free poses), the first call that is
  * not under stream capture creates two streams (default priority) and three
@@ -43,7 +50,10 @@
  * of the call's work is still ordered on `stream`, and a capture records the
  * fork and join.  Until then (or for a one-class plan) everything runs on
  * `stream`.  Calls on one plan from several streams share the side streams:
- * still correct, but their forked work waits for each other there.
+ * still correct, but their forked work waits for each other there.  While a
+ * capture on one stream holds the side streams (from its fork until the
+ * capture ends), a call of the same plan on another stream runs all of its
+ * work on its own stream instead.
  *
  * Errors: every call returns ba_status.  Argument and structure errors are
  * detected on the host before any device work and return a negative status;

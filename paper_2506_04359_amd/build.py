@@ -41,11 +41,11 @@ def build(verbose: bool = False) -> str:
                                                           "-o", os.path.join(obj, "tri.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "pgo.hip"),
                                                           "-o", os.path.join(obj, "pgo.o")],
-        [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "pgo_plan.cpp"),
-                                                          "-o", os.path.join(obj, "pgo_plan.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "api.cpp"),
                                                           "-o", os.path.join(obj, "api.o")],
+        # the host plans are plain C++ (also built with the sanitizers by the tests)
         ["g++"] + COMMON + ["-c", os.path.join(CSRC, "plan.cpp"), "-o", os.path.join(obj, "plan.o")],
+        ["g++"] + COMMON + ["-c", os.path.join(CSRC, "pgo_plan.cpp"), "-o", os.path.join(obj, "pgo_plan.o")],
     ]
     for cmd in steps:
         out = _run(cmd)

@@ -103,6 +103,12 @@ struct ba_batch_s {
   DevPlan plan{};
   DeviceTables tables[2];   // [0]: small tiles, [1]: large tiles
   int chunk_obs = 4096;
+  // Set by the first launch made under stream capture: a graph may then hold
+  // the launch tables' device pointers in its kernel arguments, so tables
+  // replaced by ba_set_launch / ba_autotune are kept (in `retired`) until the
+  // batch is destroyed instead of being freed.
+  bool captured = false;
+  std::vector<void*> retired;
   // the side streams of the size classes and their fork / join events (made
   // by the first launch of a plan with two or more size classes that is not
   // under stream capture)
@@ -119,6 +125,7 @@ struct ba_batch_s {
     if (mem) (void)hipFree(mem);
     for (auto& t : tables)
       if (t.mem) (void)hipFree(t.mem);
+    for (void* m : retired) (void)hipFree(m);
   }
 };
 
@@ -187,7 +194,12 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
       }
     }
   DeviceTables& D = b->tables[which];
-  if (D.mem) (void)hipFree(D.mem);
+  if (D.mem) {
+    // hipFree waits for the device, so eager launches are done with the old
+    // tables; a captured graph may still use them at any later replay
+    if (b->captured) b->retired.push_back(D.mem);
+    else (void)hipFree(D.mem);
+  }
   D.mem = mem;
   D.tp = tp;
   D.chunk_obs = chunk_obs;
@@ -491,11 +503,28 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.stream = stream;
   int n_classes = 0;
   for (int c = 0; c < kClasses; ++c) n_classes += t.cls_win_begin[c + 1] > t.cls_win_begin[c];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long cap_id = 0;
+  hipError_t e = hipStreamGetCaptureInfo((hipStream_t)stream, &cs, &cap_id);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamGetCaptureInfo");
+  if (cs != hipStreamCaptureStatusNone) b->captured = true;
   if (n_classes >= 2 && (st = ensure_side_stream(b, stream)) != BA_OK) return st;
-  A.side_stream = b->have_side ? (void*)b->side : nullptr;
+  // The side streams join a capture of `stream` through the fork event and
+  // stay in it until that capture ends.  While they belong to another capture
+  // (a call on another stream of this plan is being captured) the call runs
+  // every class on `stream`, so that nothing is recorded into a foreign graph.
+  bool use_side = b->have_side;
+  for (int k = 0; k < kSideStreams && use_side; ++k) {
+    hipStreamCaptureStatus ss = hipStreamCaptureStatusNone;
+    unsigned long long sid = 0;
+    if ((e = hipStreamGetCaptureInfo(b->side[k], &ss, &sid)) != hipSuccess)
+      return hip_fail(e, "hipStreamGetCaptureInfo");
+    if (ss != hipStreamCaptureStatusNone && !(cs == hipStreamCaptureStatusActive && sid == cap_id))
+      use_side = false;
+  }
+  A.side_stream = use_side ? (void*)b->side : nullptr;
   A.ev_fork = b->ev_fork;
   A.ev_join = (void*)b->ev_join;
-  hipError_t e;
   if (s->precision == BA_FP64) {
     const DevWork<double> K = make_work<double>(L, ws, has_w);
     if (op == Op::Solve)

@@ -1629,7 +1629,7 @@ int pass_a_groups(const LaunchArgs& A, PassAGroup* g) {
 }
 
 template <typename Real, int TP, bool ADJ>
-void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
+hipError_t launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
   static_assert(kSideStreams >= 2, "pass A uses two side streams");
   PassAGroup g[kClasses];
   const int ng = pass_a_groups<Real, TP, ADJ>(A, g);
@@ -1640,9 +1640,10 @@ void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
   for (int k = 0; k < ng; ++k) used[g[k].stream] = true;
   bool fork = false;
   for (int s = 1; s <= kSideStreams; ++s) fork = fork || used[s];
-  if (fork) (void)hipEventRecord((hipEvent_t)A.ev_fork, main);
+  hipError_t e = hipSuccess;
+  if (fork && (e = hipEventRecord((hipEvent_t)A.ev_fork, main)) != hipSuccess) return e;
   for (int s = 1; s <= kSideStreams; ++s)
-    if (used[s]) (void)hipStreamWaitEvent(side[s - 1], (hipEvent_t)A.ev_fork, 0);
+    if (used[s] && (e = hipStreamWaitEvent(side[s - 1], (hipEvent_t)A.ev_fork, 0)) != hipSuccess) return e;
   for (int k = ng - 1; k >= 0; --k)   // side launches first
     if (g[k].stream)
       hipLaunchKernelGGL((k_pass_a<Real, TP, ADJ>), dim3(g[k].n), dim3(TP), g[k].lds, side[g[k].stream - 1], A.plan,
@@ -1653,9 +1654,10 @@ void launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
                          A.user, A.settings, it, g[k].begin, A.dims);
   for (int s = 1; s <= kSideStreams; ++s)
     if (used[s]) {
-      (void)hipEventRecord(join[s - 1], side[s - 1]);
-      (void)hipStreamWaitEvent(main, join[s - 1], 0);
+      if ((e = hipEventRecord(join[s - 1], side[s - 1])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(main, join[s - 1], 0)) != hipSuccess) return e;
     }
+  return hipGetLastError();
 }
 
 // Workgroups along y of k_sum for windows of at most nf free poses.
@@ -1727,19 +1729,22 @@ inline ClassChains class_chains(const LaunchArgs& A) {
   return C;
 }
 
-inline void fork_chains(const LaunchArgs& A, const ClassChains& C) {
+inline hipError_t fork_chains(const LaunchArgs& A, const ClassChains& C) {
   const hipStream_t* side = (const hipStream_t*)A.side_stream;
-  (void)hipEventRecord((hipEvent_t)A.ev_fork, (hipStream_t)A.stream);
-  for (int r = 0; r < C.nside; ++r) (void)hipStreamWaitEvent(side[r], (hipEvent_t)A.ev_fork, 0);
+  hipError_t e = hipEventRecord((hipEvent_t)A.ev_fork, (hipStream_t)A.stream);
+  for (int r = 0; r < C.nside && e == hipSuccess; ++r) e = hipStreamWaitEvent(side[r], (hipEvent_t)A.ev_fork, 0);
+  return e;
 }
 
-inline void join_chains(const LaunchArgs& A, const ClassChains& C) {
+inline hipError_t join_chains(const LaunchArgs& A, const ClassChains& C) {
   const hipStream_t* side = (const hipStream_t*)A.side_stream;
   const hipEvent_t* join = (const hipEvent_t*)A.ev_join;
-  for (int r = 0; r < C.nside; ++r) {
-    (void)hipEventRecord(join[r], side[r]);
-    (void)hipStreamWaitEvent((hipStream_t)A.stream, join[r], 0);
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < C.nside && e == hipSuccess; ++r) {
+    e = hipEventRecord(join[r], side[r]);
+    if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)A.stream, join[r], 0);
   }
+  return e;
 }
 
 // One attempt of class C.cls[k] on its chain's stream.
@@ -1759,19 +1764,20 @@ hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, main, A.plan, A.tiles, K, A.user);
   const int iters = A.settings.max_iters;
   const ClassChains C = class_chains(A);
+  hipError_t e = hipSuccess;
   if (C.n > 0 && iters > 0) {
-    fork_chains(A, C);
+    if ((e = fork_chains(A, C)) != hipSuccess) return e;
     for (int it = 0; it < iters; ++it)
       for (int k = C.n - 1; k >= 0; --k) launch_class_attempt<Real, TP, false>(A, K, it, C, k);
-    join_chains(A, C);
+    if ((e = join_chains(A, C)) != hipSuccess) return e;
   } else {
     for (int it = 0; it < iters; ++it) {
-      launch_pass_a<Real, TP, false>(A, K, it);
+      if ((e = launch_pass_a<Real, TP, false>(A, K, it)) != hipSuccess) return e;
       launch_stages<Real, TP, false>(A, K, it, 0, nw, 0, nc, A.max_nf, main);
     }
   }
-  if (iters == 0)   // the report still needs the input cost
-    launch_pass_a<Real, TP, false>(A, K, 0);
+  if (iters == 0 && (e = launch_pass_a<Real, TP, false>(A, K, 0)) != hipSuccess)   // the report still needs the input cost
+    return e;
   hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, main, A.plan, K, A.user, iters == 0 ? 1 : 0);
   return hipGetLastError();
 }
@@ -1784,12 +1790,13 @@ hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
   hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, main, A.plan, K, A.settings);
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, main, A.plan, A.tiles, K, A.user);
   const ClassChains C = class_chains(A);
+  hipError_t e = hipSuccess;
   if (C.n > 0) {
-    fork_chains(A, C);
+    if ((e = fork_chains(A, C)) != hipSuccess) return e;
     for (int k = C.n - 1; k >= 0; --k) launch_class_attempt<Real, TP, true>(A, K, 0, C, k);
-    join_chains(A, C);
+    if ((e = join_chains(A, C)) != hipSuccess) return e;
   } else {
-    launch_pass_a<Real, TP, true>(A, K, 0);
+    if ((e = launch_pass_a<Real, TP, true>(A, K, 0)) != hipSuccess) return e;
     launch_stages<Real, TP, true>(A, K, 0, 0, nw, 0, nc, A.max_nf, main);
   }
   return hipGetLastError();
@@ -1812,8 +1819,9 @@ hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* 
   hipLaunchKernelGGL(k_init<Real>, dim3((nw + 63) / 64), dim3(64), 0, main, A.plan, K, A.settings);
   hipLaunchKernelGGL(k_pack<Real>, dim3(nc), dim3(256), 0, main, A.plan, A.tiles, K, A.user);
   (void)hipEventRecord(ev[0], main);
-  for (int it = 0; it < iters; ++it) {
-    launch_pass_a<Real, TP, false>(A, K, it);
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < iters && e == hipSuccess; ++it) {
+    e = launch_pass_a<Real, TP, false>(A, K, it);
     (void)hipEventRecord(ev[4 * it + 1], main);
     hipLaunchKernelGGL(k_sum<Real>, dim3(nw, sum_slices(A.max_nf)), dim3(256), 0, main, A.plan, A.tiles, K, 0);
     hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr, main, A.plan,
@@ -1827,7 +1835,7 @@ hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* 
     (void)hipEventRecord(ev[4 * it + 4], main);
   }
   hipLaunchKernelGGL(k_finalize<Real>, dim3(nw), dim3(256), 0, main, A.plan, K, A.user, 0);
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipGetLastError();
   if (e == hipSuccess) e = hipEventSynchronize(ev[nev - 1]);
   for (int k = 0; k < 4; ++k) stage_ms[k] = 0.0;
   for (int it = 0; it < iters && e == hipSuccess; ++it)

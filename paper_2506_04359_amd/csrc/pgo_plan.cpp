@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "pgo.hpp"
+#include "pgo_plan.hpp"
 
 namespace ba {
 

@@ -122,9 +122,27 @@ inline int size_class(int n_free) {
 void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_obs,
                  LaunchTables& out);
 
+// Packed fields of the plan tables and the limits that keep them in range.
+//   segment word : blk (10 bits) | first product (13 bits) | count (9 bits)
+//   product      : qa (8 bits) | qc (8 bits), tile-local pair indices
+//   pair record  : pose (8 bits) | q (8 bits) | observations of the pair (15 bits)
+constexpr int kSegBlkBits = 10, kSegStartBits = 13, kSegLenBits = 9;
+static_assert(kSegBlkBits + kSegStartBits + kSegLenBits == 32, "segment word is 32 bits");
+// target blocks of S: nf (nf + 1) / 2 upper blocks
+static_assert(kMaxFree * (kMaxFree + 1) / 2 <= (1 << kSegBlkBits), "block index field too narrow");
+// products of one tile: sum over its landmarks of P (P - 1) / 2 with sum P <= TP
+// and P <= kMaxFree, at most TP (kMaxFree - 1) / 2
+static_assert(kTileLarge * (kMaxFree - 1) / 2 < (1 << kSegStartBits), "product index field too narrow");
+// products of one target block in one tile: one per landmark, at most TP / 2
+static_assert(kTileLarge / 2 < (1 << kSegLenBits), "product count field too narrow");
+static_assert(kTileSmall <= kTileLarge && kTileLarge <= 256, "tile-local pair index is 8 bits");
+static_assert(kMaxPoses <= 256, "pose index of a pair record is 8 bits");
+static_assert(kMaxObsPerLandmark < (1 << 15), "observations of a pair record are 15 bits");
+
 // Segment word of the product lists.
 inline uint32_t seg_word(int blk, int start, int len) {
-  return (uint32_t)blk | ((uint32_t)start << 10) | ((uint32_t)len << 23);
+  return (uint32_t)blk | ((uint32_t)start << kSegBlkBits) |
+         ((uint32_t)len << (kSegBlkBits + kSegStartBits));
 }
 
 }  // namespace ba

@@ -111,9 +111,17 @@ def mixed_check(w, g, backend="schur", align=False, dec_replay=True, s=None):
     rms_g = oracle.rms(g["poses"], g["points"], prob)
     rms_o = oracle.rms(ref.poses, ref.points, prob)
     assert abs(rms_g - rms_o) <= 1e-3, (rms_g, rms_o)
-    P = g["poses"]
+    P, L = g["poses"], g["points"]
     if align:
-        P, _, _ = oracle.align_scale(g["poses"], g["points"], ref.poses)
+        P, L, _ = oracle.align_scale(g["poses"], g["points"], ref.poses)
     ang, dt = pose_errors(P, ref.poses)
     assert ang <= 1e-4 and dt <= 1e-4, (ang, dt)
+    dp = point_errors(L, ref.points)
+    assert dp <= 1e-4, dp
     return ref
+
+
+def point_errors(La, Lb):
+    """Largest |p_a - p_b| / max(|p_b|, 1 m) over the landmarks."""
+    d = np.linalg.norm(La - Lb, axis=1)
+    return float((d / np.maximum(np.linalg.norm(Lb, axis=1), 1.0)).max()) if len(d) else 0.0

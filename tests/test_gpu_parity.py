@@ -110,11 +110,10 @@ def test_fp64_zero_iterations_reports_input_cost():
 
 
 def test_fp64_observation_order_does_not_matter():
-    # The plan sorts the observations, so a permuted input gives the same device
-    # order.  The LDS accumulation of S uses atomics whose order varies from run
-    # to run, so results agree to rounding (amplified along the mono scale
-    # gauge), not bit for bit: states are compared after scale alignment at the
-    # FP64 parity bar and the cost traces at 1e-12.
+    # The plan sorts the observations by (landmark, pose, camera, user index),
+    # and nothing on the device depends on the user order (no atomics; every
+    # sum runs in a fixed order), so a permuted input gives the same solve bit
+    # for bit.
     import paper_2506_04359_amd as ba
     w = bagen.make_window(1)
     s = ba.Settings(max_iters=10, precision=ba.BA_FP64)
@@ -124,11 +123,23 @@ def test_fp64_observation_order_does_not_matter():
     for f in ("obs_pose", "obs_point", "obs_cam", "obs_uv", "obs_w", "outlier"):
         setattr(w2, f, getattr(w, f)[perm])
     b = gpu_solve(w2, s)
-    assert np.array_equal(a["trace"]["accepted"], b["trace"]["accepted"])
-    assert rel_err(b["trace"]["cost"], a["trace"]["cost"]) <= 1e-12
-    Pb, Lb, _ = oracle.align_scale(b["poses"], b["points"], a["poses"])
-    assert rel_err(Pb, a["poses"]) <= TOL64
-    assert rel_err(Lb, a["points"]) <= TOL64
+    assert a["trace"].tobytes() == b["trace"].tobytes()
+    assert np.array_equal(a["poses"], b["poses"]) and np.array_equal(a["points"], b["points"])
+    assert a["report"].tobytes() == b["report"].tobytes()
+
+
+def test_mixed_observation_order_does_not_matter():
+    # the same in mixed precision, on a stereo window with outliers
+    w = bagen.make_window(2)
+    s = settings_for(w, max_iters=4)
+    a = gpu_solve(w, s)
+    perm = np.random.default_rng(2).permutation(w.n_obs)
+    w2 = w.copy()
+    for f in ("obs_pose", "obs_point", "obs_cam", "obs_uv", "obs_w", "outlier"):
+        setattr(w2, f, getattr(w, f)[perm])
+    b = gpu_solve(w2, s)
+    assert a["trace"].tobytes() == b["trace"].tobytes()
+    assert np.array_equal(a["poses"], b["poses"]) and np.array_equal(a["points"], b["points"])
 
 
 def test_mixed_stereo_window():
@@ -138,8 +149,13 @@ def test_mixed_stereo_window():
     ref = mixed_check(w, g)
     assert g["report"]["final_cost"] < 0.5 * g["report"]["initial_cost"]
     prob = oracle.Problem.from_window(w)
+    # the RMS over the inliers alone (the generator's outlier flags) meets the same bar
+    inl = ~np.asarray(w.outlier, bool)
+    rg = oracle.rms(g["poses"], g["points"], prob, mask=inl)
+    ro = oracle.rms(ref.poses, ref.points, prob, mask=inl)
+    assert abs(rg - ro) <= 1e-3, (rg, ro)
     print("stereo mixed: rms", oracle.rms(g["poses"], g["points"], prob), "oracle",
-          oracle.rms(ref.poses, ref.points, prob))
+          oracle.rms(ref.poses, ref.points, prob), "inliers", rg, ro)
 
 
 def test_mixed_rig_window():
@@ -150,15 +166,17 @@ def test_mixed_rig_window():
 
 
 def test_batched_equals_single_and_oracle():
-    import paper_2506_04359_amd as ba
+    # Each window's batched result equals its solve as a batch of its own with
+    # the same launch shape, bit for bit (chunks are cut per window, and every
+    # reduction runs in a fixed order), and meets the mixed bar against the oracle.
     ws = [bagen.make_window(3, i) for i in range(6)]
     s = settings_for(ws[0])
     out = gpu_solve_batched(ws, s, chunk_obs=2048)
     for w, o in zip(ws, out):
-        single = gpu_solve(w, s)
-        # same kernels, same precision; only the chunking differs (so the FP32
-        # partials of S are grouped differently before the FP64 sum)
-        assert abs(o["report"]["final_cost"] - single["report"]["final_cost"]) <= 1e-5 * single["report"]["final_cost"]
+        single = gpu_solve_batched([w], s, chunk_obs=2048)[0]
+        assert np.array_equal(o["poses"], single["poses"]) and np.array_equal(o["points"], single["points"])
+        assert o["trace"].tobytes() == single["trace"].tobytes()
+        assert o["report"].tobytes() == single["report"].tobytes()
         mixed_check(w, o, align=True)
 
 
@@ -231,3 +249,62 @@ def test_batched_graph_replays_equal_eager_solve():
     assert all(v > 0.0 for v in stages.values()), stages
     assert torch.equal(P.cpu(), Pe) and torch.equal(L.cpu(), Le)
     assert torch.equal(rep.cpu(), Re)
+
+
+def test_graph_replay_after_retune_uses_the_captured_shape():
+    """A graph captured before ba_set_launch replaces the launch tables still
+    replays its own shape (the replaced tables stay alive once the plan has
+    been captured), and the plan solves with the new shape afterwards."""
+    import torch
+    import paper_2506_04359_amd as ba
+    from paper_2506_04359_amd._binding import REPORT_DTYPE
+    ws = [bagen.make_window(3, i) for i in (6, 2, 13, 23)]
+    s = ba.Settings(max_iters=5, precision=ba.BA_MIXED)
+    dev = torch.device("cuda:0")
+    B = ba.Batch([ba.Window.from_problem(w, host_only=True) for w in ws])
+    B.set_launch(2048)
+    cat = lambda xs: torch.tensor(np.ascontiguousarray(np.concatenate(xs)), dtype=torch.float64, device=dev)
+    P0, L0 = cat([w.poses_init for w in ws]), cat([w.points_init for w in ws])
+    uv = cat([w.obs_uv for w in ws])
+    P, L = P0.clone(), L0.clone()
+    work = torch.empty(B.workspace_size(s), dtype=torch.uint8, device=dev)
+    rep = torch.zeros(REPORT_DTYPE.itemsize * len(ws), dtype=torch.uint8, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+
+    def step(wk):
+        P.copy_(P0)
+        L.copy_(L0)
+        ba.solve_batched(B, s, P, L, uv, None, wk, rep)
+
+    with torch.cuda.stream(side):
+        step(work)
+    torch.cuda.synchronize()
+    Pe, Le, Re = P.cpu(), L.cpu(), rep.cpu()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        step(work)
+    torch.cuda.synchronize()
+    B.set_launch(8192)       # replaces the tables the graph was captured with
+    work2 = torch.empty(B.workspace_size(s), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    for k in range(2):
+        P.fill_(0.0)
+        L.fill_(0.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(P.cpu(), Pe) and torch.equal(L.cpu(), Le), k
+        assert torch.equal(rep.cpu(), Re), k
+    # eager solve with the new shape: a different grouping of the FP32
+    # partials, the same solve to the mixed bar
+    with torch.cuda.stream(side):
+        step(work2)
+    torch.cuda.synchronize()
+    Pn, Ln = P.cpu().numpy(), L.cpu().numpy()
+    po = lo = 0
+    for w in ws:
+        g_ = dict(poses=Pn[po:po + w.n_poses], points=Ln[lo:lo + w.n_points], trace=None)
+        mixed_check(w, g_, align=True, dec_replay=False, s=s)
+        po += w.n_poses
+        lo += w.n_points
