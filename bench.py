@@ -81,31 +81,69 @@ def pass_a_flops(infos):
     return f
 
 
-def _cpu_worker(index):
-    """Oracle solve of one window (spawned process; no torch, one BLAS thread)."""
-    import numpy as np  # noqa: F401
+def _cpu_worker(job):
+    """Oracle solve of one window (spawned process; no torch, one BLAS thread).
+    job = (config, index): the window's generator and its index in the config."""
     import bagen
     import oracle
-    w = bagen.make_window(3, index)
+    cfg, index = job
+    w = bagen.make_window(cfg, index)
     prob = oracle.Problem.from_window(w)
-    st = oracle.LMSettings(max_iters=ITERS, lambda_init=w.lambda_init, huber_delta=w.huber_delta)
+    st = oracle.LMSettings(max_iters=w.max_iters, lambda_init=w.lambda_init, huber_delta=w.huber_delta)
     t = time.perf_counter()
     res = oracle.lm_solve(w.poses_init, w.points_init, prob, st, backend="schur")
     dt = time.perf_counter() - t
-    return index, dt, oracle.rms(res.poses, res.points, prob)
+    return cfg, index, dt, oracle.rms(res.poses, res.points, prob), res.poses, res.points
 
 
-def cpu_baseline(sample):
+def cpu_pool(jobs):
+    """Run the oracle jobs over the host cores: one process per window, one
+    BLAS thread each; returns the results, the wall time and the process count."""
     import multiprocessing as mp
-    procs = max(1, min(len(sample), os.cpu_count() or 1, 16))
+    procs = max(1, min(len(jobs), os.cpu_count() or 1, 16))
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
     ctx = mp.get_context("spawn")
     t = time.perf_counter()
     with ctx.Pool(procs) as pool:
-        out = pool.map(_cpu_worker, sample)
+        out = pool.map(_cpu_worker, jobs, chunksize=1)
     wall = time.perf_counter() - t
     return out, wall, procs
+
+
+def host_description():
+    """CPU model and the BLAS numpy links (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        import numpy as np
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{b.get('name', '?')} {b.get('version', '')}".strip()
+    except Exception:
+        pass
+    return model, blas
+
+
+def state_errors(P, L, prob, ref_poses, ref_rms, mono):
+    """|dRMS| (px), largest rotation angle (rad) and largest relative translation
+    error of one GPU result against the oracle's (after scale alignment about
+    the first camera for mono windows)."""
+    import numpy as np
+    import oracle
+    d_rms = abs(oracle.rms(P, L, prob) - ref_rms)
+    if mono:
+        P, L, _ = oracle.align_scale(P, L, ref_poses)
+    ang, dt = oracle.rotation_errors(P, ref_poses)
+    tn = np.maximum(np.linalg.norm(ref_poses[:, :, 3], axis=1), 1.0)
+    return d_rms, float(ang.max()), float((dt / tn).max())
 
 
 def kernels_sha():
@@ -144,7 +182,10 @@ def main():
     ap.add_argument("--no-pgo", action="store_true", help="skip the pose-graph leg")
     ap.add_argument("--chunk-obs", type=int, default=None,
                     help="fixed observations per work item instead of the autotuned value")
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-window legs (mono, stereo and rig windows)")
+    ap.add_argument("--cpu-sample", type=int, default=N_WINDOWS,
+                    help="windows of the batch solved by the oracle (all by default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -292,6 +333,79 @@ def main():
         log(f"plain FP64 sequential: {ms64:.1f} ms, {it64:.4g} LM iters/s")
         P64, L64 = Pw.cpu().numpy(), Lw.cpu().numpy()
         del singles
+
+    # single windows: the mono window (5 keyframes), the stereo window (20
+    # keyframes, 2 cameras) and the 32-camera rig, each solved alone in mixed
+    # and in FP64 precision, replayed from a HIP graph
+    singles_out = {}
+    if not args.no_single:
+        for cfg in (1, 2, 4):
+            w = bagen.make_window(cfg)
+            name = bagen.WORKLOAD_NAMES[cfg]
+            win = ba.Window.from_problem(w)
+            one = ba.Batch([ba.Window.from_problem(w, host_only=True)])
+            Ps0 = torch.tensor(w.poses_init, dtype=torch.float64, device=dev)
+            Ls0 = torch.tensor(w.points_init, dtype=torch.float64, device=dev)
+            uvs = torch.tensor(w.obs_uv, dtype=torch.float64, device=dev)
+            leg = {"observations": int(w.n_obs), "landmarks": int(w.n_points), "poses": int(w.n_poses),
+                   "cameras": int(w.n_cams), "free_poses": int(np.sum(w.pose_fixed == 0)),
+                   "lm_attempts": int(w.max_iters),
+                   "precision_of_config": "mixed" if w.mixed else "fp64"}
+            for pname, prec in (("mixed", ba.BA_MIXED), ("fp64", ba.BA_FP64)):
+                ss = ba.Settings(max_iters=w.max_iters, precision=prec, lambda_init=w.lambda_init,
+                                 huber_delta=w.huber_delta)
+                Ps, Ls = Ps0.clone(), Ls0.clone()
+                wk = torch.empty(max(win.workspace_size(ss), 256), dtype=torch.uint8, device=dev)
+                rp = torch.zeros(48, dtype=torch.uint8, device=dev)
+
+                def sstep():
+                    Ps.copy_(Ps0)
+                    Ls.copy_(Ls0)
+                    ba.solve(win, ss, Ps, Ls, uvs, None, wk, rp)
+
+                with torch.cuda.stream(side):
+                    sstep()
+                torch.cuda.synchronize()
+                sg = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(sg, stream=side):
+                    sstep()
+                torch.cuda.synchronize()
+                for _ in range(args.warmup):
+                    sg.replay()
+                torch.cuda.synchronize()
+                c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                c0.record()
+                for _ in range(args.steps):
+                    sg.replay()
+                c1.record()
+                torch.cuda.synchronize()
+                ms_s = c0.elapsed_time(c1) / args.steps
+                rr = ba.parse_reports(rp)[0]
+                d = {"ms_per_solve": ms_s, "lm_iters_per_s": w.max_iters / (ms_s / 1e3),
+                     "obs_jacobians_per_s": w.n_obs * (1 + int(rr["accepted"])) / (ms_s / 1e3),
+                     "accepted": int(rr["accepted"]), "final_cost": float(rr["final_cost"]),
+                     "poses": Ps.cpu().numpy(), "points": Ls.cpu().numpy()}
+                # pass A of this window alone, its device time per attempt
+                Ps.copy_(Ps0)
+                Ls.copy_(Ls0)
+                wk1 = torch.empty(max(one.workspace_size(ss), 256), dtype=torch.uint8, device=dev)
+                st1 = one.profile_stages(ss, Ps, Ls, uvs, None, wk1, rp)
+                pa_ms = st1["pass_a"] / w.max_iters
+                fl = pass_a_flops([one.info(0)])
+                peak = PEAK_FP32_TFLOPS if prec == ba.BA_MIXED else PEAK_VALU_FP64
+                d["stage_ms_per_attempt"] = {k: v / w.max_iters for k, v in st1.items()}
+                d["roofline"] = {"bound": "alu", "achieved": fl / (pa_ms / 1e3) / 1e12, "peak": peak,
+                                 "unit": "TFLOP/s", "frac": fl / (pa_ms / 1e3) / 1e12 / peak,
+                                 "traffic": None,
+                                 "kernel": "k_pass_a<float>" if prec == ba.BA_MIXED else "k_pass_a<double>",
+                                 "flops_per_launch": fl, "avg_launch_ms": pa_ms}
+                leg[pname] = d
+                del sg
+            leg["speedup_mixed_over_fp64"] = leg["fp64"]["ms_per_solve"] / leg["mixed"]["ms_per_solve"]
+            singles_out[cfg] = (name, w, leg)
+            log(f"{name}: mixed {leg['mixed']['ms_per_solve']:.3f} ms, fp64 {leg['fp64']['ms_per_solve']:.3f} ms "
+                f"per {w.max_iters}-attempt solve")
+            del win, one
 
     # adjoint on 64 windows of 10 keyframes / 2000 landmarks
     if not args.no_adjoint:
@@ -479,27 +593,68 @@ def main():
             f"{info['n_levels']} levels)")
         del ggraph, graph
 
-    # oracle on the host: bounded sample, also the RMS check of those windows
+    # the oracle on the host: every window of the batch (and the single
+    # windows), one process per window; the RMS check of every result
     sample = list(range(min(args.cpu_sample, N_WINDOWS)))
     if not args.no_cpu:
         import oracle
-        res, wall_cpu, procs = cpu_baseline(sample)
+        jobs = [(3, k) for k in sample]
+        res, wall_cpu, procs = cpu_pool(jobs)
         iters_cpu = len(sample) * ITERS / wall_cpu
         po = np.cumsum([0] + [w.n_poses for w in ws])
         lo = np.cumsum([0] + [w.n_points for w in ws])
-        worst = 0.0
-        for idx, dt, rms_o in res:
+        tol = {"drms_px": 1e-3, "rot_rad": 1e-4, "trans_rel": 1e-4}
+        worst = {"mixed": [0.0, 0.0, 0.0], "plain_fp64": [0.0, 0.0, 0.0]}
+        drms_mixed_fp64 = 0.0
+        for cfg, idx, dt, rms_o, Po, Lo in res:
             w = ws[idx]
             prob = oracle.Problem.from_window(w)
-            rms_g = oracle.rms(P_final[po[idx]:po[idx + 1]], L_final[lo[idx]:lo[idx + 1]], prob)
-            worst = max(worst, abs(rms_g - rms_o))
-        out["rms_check"] = {"windows": len(sample), "max_abs_drms_px": worst, "tol_px": 1e-3,
-                            "pass": bool(worst <= 1e-3)}
+            sl_p, sl_l = slice(po[idx], po[idx + 1]), slice(lo[idx], lo[idx + 1])
+            results = {"mixed": (P_final[sl_p], L_final[sl_l])}
+            if not args.no_fp64:
+                results["plain_fp64"] = (P64[sl_p], L64[sl_l])
+                drms_mixed_fp64 = max(drms_mixed_fp64, abs(oracle.rms(*results["mixed"], prob)
+                                                           - oracle.rms(*results["plain_fp64"], prob)))
+            for key, (Pg, Lg) in results.items():
+                e = state_errors(Pg, Lg, prob, Po, rms_o, mono=True)
+                worst[key] = [max(a, b) for a, b in zip(worst[key], e)]
+        chk = {"windows": len(sample), "tol": tol}
+        ok = True
+        for key, (a, b, c) in worst.items():
+            if key == "plain_fp64" and args.no_fp64:
+                continue
+            passed = a <= tol["drms_px"] and b <= tol["rot_rad"] and c <= tol["trans_rel"]
+            ok = ok and passed
+            chk[key] = {"max_abs_drms_px": a, "max_rot_err_rad": b, "max_trans_err_rel": c, "pass": passed}
+        chk["pass"] = ok
+        out["rms_check"] = chk
+        if "plain_fp64" in out:
+            out["plain_fp64"]["max_abs_drms_vs_mixed_px"] = drms_mixed_fp64
+        model, blas = host_description()
         out["cpu_baseline"] = {"value": iters_cpu, "unit": "LM iters/s", "cores": procs,
                                "kind": "oracle",
                                "sample": f"windows 0-{len(sample) - 1} of the 256, {ITERS} LM attempts each, "
-                                         f"block-Schur FP64 oracle, one process per window"}
-        log(f"cpu oracle: {wall_cpu:.1f}s for {len(sample)} windows on {procs} processes, worst dRMS {worst:.2e}")
+                                         f"block-Schur FP64 oracle, one process per window, one BLAS thread",
+                               "cpu_model": model, "blas": blas, "wall_s": wall_cpu}
+        log(f"cpu oracle: {wall_cpu:.1f}s for {len(sample)} windows on {procs} processes; check {chk}")
+        # the single windows against their own oracle solves
+        if singles_out:
+            sres, swall, _ = cpu_pool([(cfg, 0) for cfg in singles_out])
+            for cfg, _, dt, rms_o, Po, Lo in sres:
+                name, w, leg = singles_out[cfg]
+                prob = oracle.Problem.from_window(w)
+                for pname in ("mixed", "fp64"):
+                    d = leg[pname]
+                    a, b, c = state_errors(d["poses"], d["points"], prob, Po, rms_o, mono=(w.n_cams == 1))
+                    d["vs_oracle"] = {"abs_drms_px": a, "rot_err_rad": b, "trans_err_rel": c,
+                                      "pass": bool(a <= 1e-3 and b <= 1e-4 and c <= 1e-4)}
+                leg["oracle_s"] = dt
+                leg["oracle_rms_px"] = rms_o
+    for cfg, (name, w, leg) in singles_out.items():
+        for pname in ("mixed", "fp64"):
+            leg[pname].pop("poses", None)
+            leg[pname].pop("points", None)
+        out.setdefault("single_windows", {})[name] = leg
     print(json.dumps(out), flush=True)
 
 

@@ -94,10 +94,11 @@ def pose_errors(Pa, Pb):
     return float(ang.max()), float((dt / tn).max())
 
 
-def mixed_check(w, g, backend="schur", align=False, dec_replay=True, s=None):
+def mixed_check(w, g, backend="schur", align=False, dec_replay=True, s=None, point_mask=None):
     """Mixed-precision bar against the FP64 oracle (decision replay when the
     oracle can follow the GPU's sequence, else its own run): |dRMS| <= 1e-3 px,
-    rotation <= 1e-4 rad, translation <= 1e-4 * max(|t|, 1 m)."""
+    rotation <= 1e-4 rad, translation <= 1e-4 * max(|t|, 1 m), and each point
+    selected by point_mask (default: all) within 1e-4 * max(|p|, 1 m)."""
     s = settings_for(w) if s is None else s
     prob = oracle.Problem.from_window(w)
     ref = None
@@ -116,7 +117,8 @@ def mixed_check(w, g, backend="schur", align=False, dec_replay=True, s=None):
         P, L, _ = oracle.align_scale(g["poses"], g["points"], ref.poses)
     ang, dt = pose_errors(P, ref.poses)
     assert ang <= 1e-4 and dt <= 1e-4, (ang, dt)
-    dp = point_errors(L, ref.points)
+    sel = slice(None) if point_mask is None else np.asarray(point_mask, bool)
+    dp = point_errors(L[sel], ref.points[sel])
     assert dp <= 1e-4, dp
     return ref
 

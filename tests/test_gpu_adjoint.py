@@ -156,3 +156,39 @@ def test_fp64_batched_adjoint_of_four_classes_matches_single_windows():
             assert np.abs(buv - suv).max() <= 1e-9 * np.abs(suv).max()
             assert np.abs(bw - sw).max() <= 1e-9 * np.abs(sw).max()
             o += w.n_obs
+
+
+def test_adjoint_workload_window_against_finite_differences():
+    """A full window of the adjoint workload (about 19k observations): the FP64
+    adjoint at the oracle's converged state equals the dense oracle adjoint to
+    1e-9; the mixed adjoint at the GPU's own mixed solution (50 attempts) meets
+    the stored central differences of the solution map (100 coordinates,
+    written by tests/golden/make_adjoint_fd.py from the oracle) to 1e-3 of the
+    coordinate, with a floor of 1e-2 times the adjoint's RMS."""
+    import json
+    import os
+    import paper_2506_04359_amd as ba
+    from helpers import gpu_solve
+    import adjoint_fd as F
+    doc = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint_cfg5_fd.json")))
+    w = bagen.make_window(5, 0)
+    prob = oracle.Problem.from_window(w)
+    P, L = F.tight_solution(w, prob)
+    s64 = ba.Settings(max_iters=1, precision=ba.BA_FP64)
+    guv, gw, rep, G = _gpu_adjoint(w, s64, P, L)
+    ruv, rw = _oracle_adjoint(w, P, L, G)
+    assert rep["chol_failures"] == 0
+    assert np.abs(guv - ruv).max() <= 1e-9 * np.abs(ruv).max()
+    assert np.abs(gw - rw).max() <= 1e-9 * np.abs(rw).max()
+
+    sm = ba.Settings(max_iters=50, precision=ba.BA_MIXED)
+    g = gpu_solve(w, sm, with_trace=False)
+    muv, mw, rep, _ = _gpu_adjoint(w, sm, g["poses"], g["points"])
+    assert rep["chol_failures"] == 0
+    floor = 1e-2 * doc["adjoint_rms"]
+    worst = 0.0
+    for row in doc["coordinates"]:
+        a = F.adjoint_value(muv, mw, row["obs"], row["comp"])
+        worst = max(worst, abs(a - row["fd_h"]) / max(abs(row["fd_h"]), floor))
+    print("mixed adjoint vs finite differences: worst relative error", worst)
+    assert worst <= 1e-3, worst

@@ -146,7 +146,15 @@ def test_mixed_stereo_window():
     w = bagen.make_window(2)
     s = settings_for(w)
     g = gpu_solve(w, s)
-    ref = mixed_check(w, g)
+    # A landmark with an outlier observation has not converged after ten
+    # attempts: the outlier's robust cost keeps pulling it along a direction
+    # its other views barely constrain (some run off towards infinity), so
+    # where it stands at the last attempt depends on rounding along the way.
+    # Positions are compared on the landmarks seen only by inliers; the others
+    # enter through the RMS.
+    clean = np.ones(w.n_points, bool)
+    clean[w.obs_point[np.asarray(w.outlier, bool)]] = False
+    ref = mixed_check(w, g, point_mask=clean)
     assert g["report"]["final_cost"] < 0.5 * g["report"]["initial_cost"]
     prob = oracle.Problem.from_window(w)
     # the RMS over the inliers alone (the generator's outlier flags) meets the same bar
