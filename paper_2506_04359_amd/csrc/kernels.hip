@@ -507,16 +507,17 @@ struct ListRegs {
   static constexpr int N = TP >= 256 ? 12 : 16;
 };
 
-// LDS carve of pass A.  The camera table and the reduced-system partial are
-// sized by the launch's largest window; the per-tile buffers by TP (a tile
-// holds at most TP / 2 landmarks).  Poses are read from memory, not cached.
-// The pair -> landmark map is kept only for the adjoint's Schur units.
+// LDS carve of pass A.  The camera table, the window's poses (FP64, staged
+// once per work item: a tile's pairs read them right at its start) and the
+// reduced-system partial are sized by the launch's largest window; the
+// per-tile buffers by TP (a tile holds at most TP / 2 landmarks).  The pair ->
+// landmark map is kept only for the adjoint's Schur units.
 template <typename Real, int TP>
 struct PassALds {
   static constexpr int NW = TP / 64;
-  static size_t bytes(int nc, int nf, int list_bytes, bool adj) {
+  static size_t bytes(int np, int nc, int nf, int list_bytes, bool adj) {
     const size_t nblk = (size_t)nf * (nf + 1) / 2;
-    return (size_t)(nc * 16 + 16) * sizeof(double) + (64 + (adj ? TP : 0) + 4 + 8) * sizeof(int) +
+    return (size_t)(nc * 16 + np * 12 + 16) * sizeof(double) + (64 + (adj ? TP : 0) + 4 + 8) * sizeof(int) +
            (nblk * kBS + 12 * (size_t)nf + (size_t)2 * NW * kPoseSums) * sizeof(Real) + 16 +
            ((size_t)TP * ZRow<Real>::S + (size_t)(TP / 2) * 12) * sizeof(Real) + 16 +
            ((size_t)list_bytes + 15) / 16 * 16;
@@ -545,7 +546,8 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
 
   double* sCam = reinterpret_cast<double*>(smem);             // nc * 16
-  double* sRed = sCam + D.nc * 16;                            // 16
+  double* sPose = sCam + D.nc * 16;                           // np * 12
+  double* sRed = sPose + D.np * 12;                           // 16
   int* sFree = reinterpret_cast<int*>(sRed + 16);             // 64
   int* sPL = sFree + 64;                                      // TP (adjoint): pair -> tile-local landmark
   int* sFlag = sPL + (ADJ ? TP : 0);                          // 4
@@ -576,6 +578,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   }
 
   for (int k = tid; k < W.n_cams * 16; k += TP) sCam[k] = P.cam[16 * W.cam_off + k];
+  for (int k = tid; k < W.n_poses * 12; k += TP) sPose[k] = poses[k];
   for (int k = tid; k < W.n_poses; k += TP) sFree[k] = P.free_slot[W.pose_off + k];
   for (int k = tid; k < nblk * kBS + 2 * nS; k += TP) sS[k] = (Real)0;
   if (tid == 0) sFlag[0] = 0;
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     const int o0 = rec.x, lm = rec.y;
     double Rt[12];
     if (tid < nP) {
-      const double* pp = poses + 12 * pose;
+      const double* pp = sPose + 12 * pose;
 #pragma unroll
       for (int k = 0; k < 12; ++k) Rt[k] = pp[k];
     }
@@ -827,12 +830,15 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
         for (int i = 0; i < RG; ++i)
 #pragma unroll
           for (int c = 0; c < 6; ++c) acc[i][c] = (Real)0;
-        for (int k = start; k < start + len; ++k) {
-          const uint32_t pp = sProd[k];
+        // Two register sets in turn: the Z rows of the next product (and the
+        // index of the one after) are read while the current product is
+        // multiplied, so a unit waits for LDS once per product.  At a unit's
+        // end the reads are clamped to its last product (read, not used).
+        Real a0[RG][3], z0[6][3], a1[RG][3], z1[6][3];
+        auto load_rows = [&](uint32_t pp, Real (&a)[RG][3], Real (&z)[6][3]) {
           const int qa = pp & 255, qc = pp >> 8;
           const Real* Za = sPZ + kZS * qa + ZR * r0;
           const Real* Zc = sPZ + kZS * qc;
-          Real a[RG][3], z[6][3];
 #pragma unroll
           for (int i = 0; i < RG; ++i)
 #pragma unroll
@@ -848,11 +854,33 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
 #pragma unroll
               for (int m = 0; m < 3; ++m) a[i][m] *= g[m];
           }
+        };
+        // acc += a z^T as a chain of FMAs (one rounding per term)
+        auto madd = [&](const Real (&a)[RG][3], const Real (&z)[6][3]) {
 #pragma unroll
           for (int i = 0; i < RG; ++i)
 #pragma unroll
-            for (int c = 0; c < 6; ++c)
-              acc[i][c] += a[i][0] * z[c][0] + a[i][1] * z[c][1] + a[i][2] * z[c][2];
+            for (int c = 0; c < 6; ++c) {
+              acc[i][c] = fma(a[i][0], z[c][0], acc[i][c]);
+              acc[i][c] = fma(a[i][1], z[c][1], acc[i][c]);
+              acc[i][c] = fma(a[i][2], z[c][2], acc[i][c]);
+            }
+        };
+        const int end = start + len, last = end - 1;
+        if (len > 0) {
+          uint32_t i1 = sProd[min(start + 1, last)];
+          load_rows(sProd[start], a0, z0);
+          for (int k = start;; k += 2) {
+            const uint32_t i2 = sProd[min(k + 2, last)];
+            load_rows(i1, a1, z1);
+            madd(a0, z0);
+            if (k + 1 >= end) break;
+            const uint32_t i3 = sProd[min(k + 3, last)];
+            load_rows(i2, a0, z0);
+            madd(a1, z1);
+            if (k + 2 >= end) break;
+            i1 = i3;
+          }
         }
         Real* B = sS + kBS * blk + 6 * r0;
 #pragma unroll
@@ -1568,8 +1596,7 @@ __global__ void k_finalize(DevPlan P, DevWork<Real> K, DevUser U, int need_cost)
 
 template <typename Real, int TP>
 size_t pass_a_lds(int np, int nc, int nf, int list_bytes, bool adj) {
-  (void)np;
-  return PassALds<Real, TP>::bytes(nc, nf, list_bytes, adj);
+  return PassALds<Real, TP>::bytes(np, nc, nf, list_bytes, adj);
 }
 
 template <typename Real, int TP>
