@@ -193,6 +193,27 @@ ba_status ba_solve(ba_window w, const ba_settings* s, double* poses, double* poi
                    const double* obs_uv, const double* obs_w, void* workspace,
                    size_t ws_bytes, ba_report* report, ba_iter_trace* trace, void* stream);
 
+/* Largest workspace of ba_solve_noalloc, in bytes, per device (64 MiB). */
+#define BA_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* ba_solve without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture that must not call hipMalloc,
+ * tight serving loops, harnesses that forbid allocation.  The workspace is a
+ * static device array of BA_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends; the call itself allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).  The first
+ * call on a device looks up that device's copy of the array.
+ * Every call on one device shares its array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams, or beside a
+ * replay of a graph that captured this call) race and corrupt each other, so
+ * order them on one stream.  Nothing in the array needs to start at zero (the
+ * solve initialises what it reads).  Arguments, results and errors as
+ * ba_solve; a window whose workspace (ba_workspace_size) exceeds the limit
+ * returns BA_ERR_WORKSPACE_TOO_SMALL before any device work. */
+ba_status ba_solve_noalloc(ba_window w, const ba_settings* s, double* poses, double* points,
+                           const double* obs_uv, const double* obs_w, ba_report* report,
+                           ba_iter_trace* trace, void* stream);
+
 /* Solve every window of a batch in one launch sequence (one kernel per stage
  * and size class covering that class's windows; the classes run as concurrent
  * chains, see "Side streams" above).  Arrays are packed window-major (see

@@ -32,5 +32,6 @@ from ._binding import (  # noqa: F401
     pgo_solve,
     solve,
     solve_batched,
+    solve_noalloc,
 )
 from .autograd import BASolve  # noqa: F401

@@ -22,6 +22,10 @@ BA_ERR_UNSUPPORTED = -5
 BA_ERR_STATE = -6
 
 
+# include/ba.h BA_NOALLOC_SCRATCH_BYTES
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
 class BAError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"ba status {status}: {message}")
@@ -73,6 +77,7 @@ def lib():
         L.ba_batch_info.argtypes = [vp, i32, ctypes.POINTER(_PlanInfo)]
         L.ba_workspace_size.argtypes = [vp, vp, ctypes.POINTER(_Settings), ctypes.POINTER(sz)]
         L.ba_solve.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp, vp, vp]
+        L.ba_solve_noalloc.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, vp, vp]
         L.ba_solve_batched.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
                                        vp, vp]
         L.ba_adjoint.argtypes = [vp, vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, vp, vp,
@@ -100,7 +105,7 @@ def lib():
         L.ba_status_string.restype = ctypes.c_char_p
         L.ba_last_error.restype = ctypes.c_char_p
         for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
-                  "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_batched",
+                  "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_noalloc", "ba_solve_batched",
                   "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
                   "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate", "ba_graph_create", "ba_graph_info",
                   "ba_graph_plan_array", "ba_graph_workspace_size", "ba_pgo_solve"):
@@ -293,6 +298,20 @@ def solve(window: Window, settings: Settings, poses, points, obs_uv, obs_w=None,
                           _ptr(obs_uv), _ptr(obs_w), _ptr(workspace), workspace.numel(),
                           _ptr(report), _ptr(trace), _stream(stream)))
     return report, trace, workspace
+
+
+def solve_noalloc(window: Window, settings: Settings, poses, points, obs_uv, obs_w=None,
+                  report=None, trace=None, stream=None):
+    """ba_solve on the library's per-device scratch (no workspace argument; the
+    call allocates nothing on the device when `report` is given).  Returns
+    (report bytes tensor, trace bytes tensor or None)."""
+    import torch
+    if report is None:
+        report = torch.zeros(REPORT_DTYPE.itemsize, dtype=torch.uint8, device=poses.device)
+    _check(lib().ba_solve_noalloc(window.handle, ctypes.byref(settings.c()), _ptr(poses),
+                                  _ptr(points), _ptr(obs_uv), _ptr(obs_w), _ptr(report),
+                                  _ptr(trace), _stream(stream)))
+    return report, trace
 
 
 def solve_batched(batch: Batch, settings: Settings, poses, points, obs_uv, obs_w=None,

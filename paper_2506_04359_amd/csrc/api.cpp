@@ -22,6 +22,12 @@
 #include "tri.hpp"
 #include "pgo.hpp"
 
+// Device scratch of ba_solve_noalloc: one copy per GPU the library runs on,
+// held until the process ends.  Host code never passes this name to a kernel
+// or a copy (on the host it is only a stand-in for the symbol): it uses the
+// per-device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[BA_NOALLOC_SCRATCH_BYTES];
+
 namespace ba {
 
 // defined in kernels.hip
@@ -554,6 +560,33 @@ ba_batch_s* batch_of(ba_window w, ba_batch b) {
   return nullptr;
 }
 
+// Address of `scratch` on one device, looked up once per device with that
+// device current (each GPU holds its own copy at its own address).
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+ba_status scratch_on(int device, void** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return set_error(BA_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipSetDevice");
+    if (!p) return set_error(BA_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return BA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -965,6 +998,25 @@ ba_status ba_solve(ba_window w, const ba_settings* s, double* poses, double* poi
   if (!w->batch) return set_error(BA_ERR_STATE, "host-only window cannot be solved");
   return ba_solve_batched(w->batch, s, poses, points, obs_uv, obs_w, workspace, ws_bytes, report,
                           trace, stream);
+}
+
+ba_status ba_solve_noalloc(ba_window w, const ba_settings* s, double* poses, double* points,
+                           const double* obs_uv, const double* obs_w, ba_report* report,
+                           ba_iter_trace* trace, void* stream) {
+  if (!w) return set_error(BA_ERR_INVALID_ARG, "window is NULL");
+  if (!w->batch) return set_error(BA_ERR_STATE, "host-only window cannot be solved");
+  size_t need = 0;
+  ba_status st = ba_workspace_size(w, nullptr, s, &need);
+  if (st != BA_OK) return st;
+  if (need > (size_t)BA_NOALLOC_SCRATCH_BYTES)
+    return set_error(BA_ERR_WORKSPACE_TOO_SMALL,
+                     "window needs " + std::to_string(need) + " bytes of workspace; ba_solve_noalloc " +
+                         "holds at most " + std::to_string((size_t)BA_NOALLOC_SCRATCH_BYTES) +
+                         " per device (use ba_solve with a workspace)");
+  void* ptr = nullptr;
+  if ((st = scratch_on(w->batch->device, &ptr)) != BA_OK) return st;
+  return ba_solve_batched(w->batch, s, poses, points, obs_uv, obs_w, ptr,
+                          (size_t)BA_NOALLOC_SCRATCH_BYTES, report, trace, stream);
 }
 
 ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double* poses,
