@@ -33,7 +33,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -766,3 +766,120 @@ PGO_WORKLOADS = {
 
 def make_pgo_workload(name: str, seed: int = 9000) -> PoseGraphData:
     return make_pose_graph(seed=seed, name=name, **PGO_WORKLOADS[name])
+
+
+# ---------------------------------------------------------------------------
+# visual-inertial windows: a mono camera on a base that carries the IMU
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ViWindow:
+    """A mono window plus IMU samples between consecutive keyframes.
+
+    The ground-truth motion is integrated from piecewise-constant body rates and
+    specific forces (one value per sample interval), so the samples are exactly
+    consistent with the discrete motion: R <- R Exp(w dt) (world-from-base),
+    v <- v + (g + R f) dt, p <- p + v dt + (g + R f) dt^2 / 2."""
+    window: Window
+    gravity: np.ndarray         # (3,) world frame, m / s^2 (y down)
+    dt: float                   # IMU sample interval, s
+    gyro: List[np.ndarray]      # per keyframe interval: (n, 3) measured rates
+    accel: List[np.ndarray]     # per keyframe interval: (n, 3) measured specific forces
+    vel_gt: np.ndarray          # (N, 3) world-frame velocity at each keyframe
+    ba_gt: np.ndarray           # (3,) constant accelerometer bias
+    bg_gt: np.ndarray           # (3,) constant gyro bias
+    vel_init: np.ndarray        # (N, 3)
+    ba_init: np.ndarray         # (N, 3)
+    bg_init: np.ndarray         # (N, 3)
+    noise: Tuple[float, float, float, float]   # sigma_g, sigma_a, sigma_bg, sigma_ba (densities)
+
+
+def _exp_so3_gen(phi):
+    th = float(np.linalg.norm(phi))
+    if th < 1e-12:
+        return np.eye(3)
+    return _rot_axis(phi / th, th)
+
+
+def make_vi_window(seed: int = 9000, n_kf: int = 10, n_lm: int = 400, kf_dt: float = 0.25,
+                   rate: float = 200.0, sigma_px: float = 0.5, imu_noise: bool = True,
+                   init_noise: bool = True, max_iters: int = 15) -> ViWindow:
+    """A camera moving forward (+z, about 1 m/s) with smooth rotation and
+    acceleration; keyframes every kf_dt s, IMU at `rate` Hz; landmarks in a box
+    ahead seen in >= min(3, n_kf) keyframes (tracks of up to 6 visible
+    keyframes).  Biases
+    are constant; the state estimates start at zero bias, perturbed velocity,
+    pose and points (pose 0 fixed at its ground truth)."""
+    rng = np.random.default_rng(seed)
+    g = np.array([0.0, 9.81, 0.0])
+    dt = 1.0 / rate
+    n_per = int(round(kf_dt * rate))
+    noise = (1.7e-4, 2.0e-3, 2.0e-5, 3.0e-3)
+    ba = rng.normal(scale=0.05, size=3)
+    bg = rng.normal(scale=0.01, size=3)
+    ph = rng.uniform(0, 2 * math.pi, 6)
+    Rw = _rot_y(rng.uniform(-0.1, 0.1))        # world-from-base at t = 0
+    p = np.zeros(3)
+    v = np.array([0.1, 0.0, 1.0])
+    poses, vels, gyros, accels = [], [], [], []
+    t = 0.0
+    for i in range(n_kf):
+        poses.append(np.concatenate([Rw.T, (-Rw.T @ p)[:, None]], axis=1))
+        vels.append(v.copy())
+        if i == n_kf - 1:
+            break
+        gy, ac = [], []
+        for _ in range(n_per):
+            w = np.array([0.15 * math.sin(0.9 * t + ph[0]), 0.3 * math.sin(0.6 * t + ph[1]),
+                          0.1 * math.sin(1.1 * t + ph[2])])
+            aw = np.array([0.4 * math.sin(0.8 * t + ph[3]), 0.2 * math.sin(0.7 * t + ph[4]),
+                           0.3 * math.sin(0.5 * t + ph[5])])
+            f = Rw.T @ (aw - g)                   # specific force in the base frame
+            acc = g + Rw @ f
+            p = p + v * dt + 0.5 * acc * dt * dt
+            v = v + acc * dt
+            Rw = Rw @ _exp_so3_gen(w * dt)
+            gy.append(w + bg)
+            ac.append(f + ba)
+            t += dt
+        gy, ac = np.asarray(gy), np.asarray(ac)
+        if imu_noise:
+            gy = gy + rng.normal(scale=noise[0] / math.sqrt(dt), size=gy.shape)
+            ac = ac + rng.normal(scale=noise[1] / math.sqrt(dt), size=ac.shape)
+        gyros.append(gy)
+        accels.append(ac)
+    poses = np.stack(poses)
+    ext = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)[None]
+    intr, size = _MONO_K[None], _MONO_SIZE[None]
+    z_end = float(-(poses[-1, :, :3].T @ poses[-1, :, 3])[2])
+    pts, trk_p, trk_j = [], [], []
+    min_vis = min(3, n_kf)
+    for _ in range(1000):
+        if len(pts) >= n_lm:
+            break
+        n_c = 4 * (n_lm - len(pts)) + 64
+        cand = np.stack([rng.uniform(-5.0, 5.0, n_c), rng.uniform(-3.0, 3.0, n_c),
+                         rng.uniform(z_end + 3.0, z_end + 20.0, n_c)], axis=1)
+        vis = np.stack([_visible(intr[0], size[0], _to_cam(poses[i], ext[0], cand)) for i in range(n_kf)], axis=1)
+        for c in np.nonzero(vis.sum(1) >= min_vis)[0]:
+            if len(pts) >= n_lm:
+                break
+            frames = np.nonzero(vis[c])[0]
+            L = int(rng.integers(min_vis, min(6, frames.size) + 1))
+            frames = np.sort(rng.choice(frames, size=L, replace=False))
+            trk_p.append(frames)
+            trk_j.append(np.full(frames.size, len(pts)))
+            pts.append(cand[c])
+    if len(pts) < n_lm:
+        raise ValueError("could not place the landmarks in view")
+    points = np.asarray(pts)
+    op, oj = np.concatenate(trk_p), np.concatenate(trk_j)
+    w = _assemble(rng, intr=intr, ext=ext, size=size, poses=poses, points=points,
+                  tracks=(op, oj, np.zeros_like(op)), sigma=sigma_px, outlier_frac=0.0, fixed=[0],
+                  max_iters=max_iters, mixed=False, name=f"vi-mono-{n_kf}kf-{n_lm}lm",
+                  point_sigma=0.1 if init_noise else 0.0, pose_rot=0.03 if init_noise else 0.0,
+                  pose_trans=0.03 if init_noise else 0.0)
+    vels = np.stack(vels)
+    vel_init = vels + (rng.normal(scale=0.05, size=vels.shape) if init_noise else 0.0)
+    return ViWindow(window=w, gravity=g, dt=dt, gyro=gyros, accel=accels, vel_gt=vels, ba_gt=ba, bg_gt=bg,
+                    vel_init=vel_init, ba_init=np.zeros((n_kf, 3)), bg_init=np.zeros((n_kf, 3)), noise=noise)

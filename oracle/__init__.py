@@ -14,7 +14,9 @@ What it computes (paper: Sec. 2.2, "3D module", Eq. 2 and Eq. 3):
     reference (``backend='dense'``) and as the textbook block-Schur form
     (``backend='schur'``), which must agree.
   * the implicit-function adjoint of the converged solution with respect to the
-    2D keypoints and the observation weights (``adjoint``).
+    2D keypoints and the observation weights (``adjoint``);
+  * visual-inertial bundle adjustment (Eq. 9): IMU preintegration, the IMU
+    factor and a dense LM over poses, velocities, biases and points (``imu``).
 
 The paper leaves the solver's details open; the readings taken here are a Huber
 robust kernel on the pixel residual, Marquardt diagonal damping with x10 / /10,
