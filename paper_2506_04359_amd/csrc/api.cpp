@@ -94,6 +94,8 @@ struct DeviceTables {
   int cls_nf[kClasses] = {0, 0, 0, 0};
   int list_bytes = 0;   // largest per-tile segment + product list
   int max_cpw = 0;      // largest chunk count of one window
+  int cls_sum_slices[kClasses] = {0, 0, 0, 0};   // k_sum workgroups per window, per class
+  int sum_slices = 0;
 };
 
 }  // namespace ba
@@ -170,6 +172,7 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
     d.chunk_begin = t.win_chunk_begin[i];
     d.chunk_end = t.win_chunk_begin[i + 1];
     d.sum_off = so;
+    d.sum_groups = sum_groups(d.chunk_end - d.chunk_begin);
     so += (int32_t)partial_elems(w.n_free);
     po += w.n_poses;
     lo += w.n_points;
@@ -225,6 +228,16 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   D.max_cpw = 0;
   for (size_t i = 0; i + 1 < t.win_chunk_begin.size(); ++i)
     D.max_cpw = std::max(D.max_cpw, t.win_chunk_begin[i + 1] - t.win_chunk_begin[i]);
+  D.sum_slices = 1;
+  for (int c = 0; c < kClasses; ++c) D.cls_sum_slices[c] = 1;
+  for (size_t i = 0; i < b->wins.size(); ++i) {
+    const int64_t ne = partial_elems(b->wins[i].n_free);
+    const int per = sum_slice_entries(wd[i].sum_groups);
+    const int n = (int)((ne + per - 1) / per);
+    const int c = size_class(b->wins[i].n_free);
+    D.cls_sum_slices[c] = std::max(D.cls_sum_slices[c], n);
+    D.sum_slices = std::max(D.sum_slices, n);
+  }
   for (int c = 0; c <= kClasses; ++c) D.cls_begin[c] = t.class_begin[c];
   for (int c = 0; c <= kClasses; ++c) D.cls_win_begin[c] = t.class_win_begin[c];
   for (int c = 0; c < kClasses; ++c) D.cls_win_nf[c] = t.class_win_nf[c];
@@ -506,6 +519,8 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.dims.nc = b->max_nc;
   A.list_bytes = t.list_bytes;
   A.max_cpw = t.max_cpw;
+  for (int c = 0; c < kClasses; ++c) A.cls_sum_slices[c] = t.cls_sum_slices[c];
+  A.sum_slices = t.sum_slices;
   A.stream = stream;
   int n_classes = 0;
   for (int c = 0; c < kClasses; ++c) n_classes += t.cls_win_begin[c + 1] > t.cls_win_begin[c];

@@ -13,6 +13,7 @@ struct WinDev {
   int32_t n_poses, n_points, n_cams, n_free;
   int32_t pose_off, point_off, cam_off, obs_off;   // first pose / landmark / camera / observation
   int32_t pair_off, chunk_begin, chunk_end, sum_off;   // sum_off: summed system in the workspace
+  int32_t sum_groups;   // chunk groups of k_sum (see sum_groups())
 };
 
 // Per-window LM state, in the workspace.
@@ -92,8 +93,20 @@ struct DevSettings {
 };
 
 constexpr int kDpStride = 192;
-constexpr int kSumSlice = 1024;   // entries of the summed system per workgroup of k_sum
-constexpr int kSumSlices = (528 * kBS + 12 * 32 + kSumSlice - 1) / kSumSlice;
+
+// k_sum: a 256-thread workgroup sums kSumE entries per thread of a window's
+// chunk partials, split into G groups of 256 / G threads; group g adds the
+// window's chunks g, g + G, g + 2G, ... in that order and the G group sums are
+// added in group order.  G depends only on the window's chunk count (so a
+// window sums in the same order alone or in any batch): about 16 chunks per
+// group, a power of two up to 16.
+constexpr int kSumE = 4;
+inline int sum_groups(int n_chunks) {
+  int g = 1;
+  while (g < 16 && g * 16 < n_chunks) g *= 2;
+  return g;
+}
+inline int sum_slice_entries(int groups) { return 256 / groups * kSumE; }
 
 constexpr int kSideStreams = 2;   // side streams of the size classes
 
@@ -116,6 +129,8 @@ struct LaunchArgs {
   LdsDims dims;                  // largest pose / camera count of the batch
   int list_bytes;                // largest per-tile product list (segments + products)
   int max_cpw;                   // largest number of chunks of one window
+  int cls_sum_slices[kClasses];  // k_sum workgroups per window of each class
+  int sum_slices;                // the same over all windows
   void* stream;                  // hipStream_t
   // The side streams of the size classes (hipStream_t[kSideStreams], or NULL
   // to run everything on `stream`), the event that forks them from `stream`

@@ -328,6 +328,39 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 }
 
 // Exclusive scan of n (<= NT) ints in LDS, in place, total at a[n].
+// Per-chunk flags and costs of a window's chunks [c0, c1), reduced by one
+// wave: lane l takes chunks c0 + l, c0 + l + 64, ... in order (four loads in
+// flight), then an xor butterfly adds the lanes.  The result used is lane 0's,
+// whose order of additions is fixed, so the sum is the same on every run.
+__device__ __forceinline__ void wave_chunk_sums(const int32_t* flag, const double* cost, int c0, int c1,
+                                                bool need_cost, int lane, int& f_out, double& F_out) {
+  int f = 0;
+  double F = 0.0;
+  for (int c = c0 + lane; c < c1; c += 4 * 64) {
+    int fl[4];
+    double cs[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int cc = c + 64 * b;
+      const bool in = cc < c1;
+      fl[b] = in ? flag[cc] : 0;
+      cs[b] = in && need_cost ? cost[cc] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      f |= fl[b];
+      F += cs[b];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    f |= __shfl_xor(f, o, 64);
+    F += __shfl_xor(F, o, 64);
+  }
+  f_out = __builtin_amdgcn_readfirstlane(f);
+  F_out = wave_bcast(F, 0);
+}
+
 template <int NT>
 __device__ __forceinline__ void block_scan(int* a, int n, int* scratch) {
   const int t = threadIdx.x;
@@ -961,51 +994,74 @@ __device__ __forceinline__ void upper_pair(int e, int n, int& i, int& j) {
   j = e - (r * n - r * (r - 1) / 2) + r;
 }
 
-// Sum of a window's chunk partials in FP64, in chunk order.  Grid: (window,
-// slice of kSumSlice entries); every thread keeps 4 entries and reads four
-// chunks per step (16 loads in flight), so the sum runs at memory speed
-// instead of one workgroup per window.
+// Sum of a window's chunk partials in FP64 (grid: windows x slices).  The
+// workgroup's 256 threads form G = W.sum_groups groups of 256 / G entry
+// lanes; each thread keeps kSumE entries of its slice, group g adds chunks
+// g, g + G, ... (four in flight per step) and the groups' sums are added in
+// group order through LDS.  The partials of a window are contiguous, one
+// per chunk, so the chunk addresses need no table lookup.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_sum(DevPlan P, DevTiles T, DevWork<Real> K, int wbase) {
+  __shared__ double sG[kSumE][256];
   const int wi = T.win_order[wbase + blockIdx.x];
   const WinDev W = P.win[wi];
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2;
   const int ne = nblk * kBS + 12 * nf;
-  const int e0 = blockIdx.y * kSumSlice;
+  const int G = W.sum_groups, L = 256 / G;
+  const int g = threadIdx.x / L, l = threadIdx.x - g * L;
+  const int e0 = blockIdx.y * (L * kSumE);
   if (e0 >= ne) return;
-  constexpr int E = kSumSlice / 256;
-  double acc[E];
+  const int nch = W.chunk_end - W.chunk_begin;
+  const Real* base = K.part + (nch > 0 ? T.chunk_part_off[W.chunk_begin] : 0);
+  // loads are unconditional (entries past the end read the last entry and
+  // are dropped), so a step's 16 loads are all in flight before the first
+  // is waited for
+  int ec[kSumE];
+  bool in[kSumE];
 #pragma unroll
-  for (int k = 0; k < E; ++k) acc[k] = 0.0;
-  int c = W.chunk_begin;
-  for (; c + 3 < W.chunk_end; c += 4) {
-    Real v[4][E];
+  for (int k = 0; k < kSumE; ++k) {
+    const int e = e0 + l + L * k;
+    in[k] = e < ne;
+    ec[k] = in[k] ? e : ne - 1;
+  }
+  double acc[kSumE];
+#pragma unroll
+  for (int k = 0; k < kSumE; ++k) acc[k] = 0.0;
+  int c = g;
+  for (; c + 3 * G < nch; c += 4 * G) {
+    Real v[4][kSumE];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const Real* a = K.part + T.chunk_part_off[c + j];
+      const Real* a = base + (int64_t)(c + j * G) * ne;
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const int e = e0 + threadIdx.x + 256 * k;
-        v[j][k] = e < ne ? a[e] : (Real)0;
-      }
+      for (int k = 0; k < kSumE; ++k) v[j][k] = a[ec[k]];
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k)
+    for (int k = 0; k < kSumE; ++k)
       acc[k] += (((double)v[0][k] + (double)v[1][k]) + (double)v[2][k]) + (double)v[3][k];
   }
-  for (; c < W.chunk_end; ++c) {
-    const Real* a = K.part + T.chunk_part_off[c];
+  for (; c < nch; c += G) {
+    const Real* a = base + (int64_t)c * ne;
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const int e = e0 + threadIdx.x + 256 * k;
-      if (e < ne) acc[k] += (double)a[e];
-    }
+    for (int k = 0; k < kSumE; ++k) acc[k] += (double)a[ec[k]];
   }
   double* dst = K.ssum + W.sum_off;
+  if (G == 1) {
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int e = e0 + threadIdx.x + 256 * k;
-    if (e < ne) dst[e] = acc[k];
+    for (int k = 0; k < kSumE; ++k)
+      if (in[k]) dst[ec[k]] = acc[k];
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kSumE; ++k) sG[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < kSumE; ++k) {
+      double t = sG[k][l];
+      for (int h = 1; h < G; ++h) t += sG[k][h * L + l];
+      if (in[k]) dst[ec[k]] = t;
+    }
   }
 }
 
@@ -1025,31 +1081,20 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   int* sFail = reinterpret_cast<int*>(sInv + nS); // 1
   const int c0 = W.chunk_begin, c1 = W.chunk_end;
   const int ne = nblk * kBS + 2 * nS;
-  if (tid == 0) {
-    // chunk flags and costs, eight loads in flight, summed in chunk order
+  {
+    // chunk flags and costs (wave 0)
     const bool need_cost = !ADJ && it == 0;
     int f = 0;
     double F = 0.0;
-    for (int c = c0; c < c1; c += 8) {
-      int fl[8];
-      double cs[8];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        fl[b] = c + b < c1 ? K.part_flag_a[c + b] : 0;
-        cs[b] = need_cost && c + b < c1 ? K.part_cost_a[c + b] : 0.0;
+    if (tid < 64) wave_chunk_sums(K.part_flag_a, K.part_cost_a, c0, c1, need_cost, tid, f, F);
+    if (tid == 0) {
+      sFail[0] = f;
+      if (need_cost) {
+        F *= 0.5;
+        st.cost = F;
+        st.init_cost = F;
+        if (!isfinite(F)) st.status = 1;
       }
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        f |= fl[b];
-        F += cs[b];
-      }
-    }
-    sFail[0] = f;
-    if (need_cost) {
-      F *= 0.5;
-      st.cost = F;
-      st.init_cost = F;
-      if (!isfinite(F)) st.status = 1;
     }
   }
   {
@@ -1499,10 +1544,17 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
 template <typename Real>
 __global__ void k_accept(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U, DevSettings S, int it, int wbase,
                          int nwin) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // one wave per window: the lanes sum the candidate's chunk costs and depth
+  // flags, lane 0 decides
+  const int i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= nwin) return;
   const int wi = T.win_order[wbase + i];
   const WinDev W = P.win[wi];
+  int depth = 0;
+  double F = 0.0;
+  wave_chunk_sums(K.part_flag_b, K.part_cost_b, W.chunk_begin, W.chunk_end, true, lane, depth, F);
+  if (lane != 0) return;
   WinState st = K.state[wi];
   ba_iter_trace tr;
   tr.cost = st.cost;
@@ -1515,22 +1567,6 @@ __global__ void k_accept(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U, DevS
     tr.status = 1;
     st.chol_failures++;
   } else {
-    int depth = 0;
-    double F = 0.0;
-    for (int c = W.chunk_begin; c < W.chunk_end; c += 8) {   // eight loads in flight, chunk order
-      int fl[8];
-      double cs[8];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        fl[b] = c + b < W.chunk_end ? K.part_flag_b[c + b] : 0;
-        cs[b] = c + b < W.chunk_end ? K.part_cost_b[c + b] : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        depth |= fl[b];
-        F += cs[b];
-      }
-    }
     if (depth) {
       tr.status = 2;
       st.depth_rejects++;
@@ -1569,14 +1605,16 @@ __global__ void k_finalize(DevPlan P, DevWork<Real> K, DevUser U, int need_cost)
     for (int k = threadIdx.x; k < 3 * W.n_points; k += blockDim.x)
       U.points[3 * W.point_off + k] = K.points_b[3 * W.point_off + k];
   }
+  // no attempt ran: the cost comes from the pass-A partials, summed as the
+  // first attempt's reduce sums them
+  int fdummy = 0;
+  double F = 0.0;
+  if (need_cost && threadIdx.x < 64)
+    wave_chunk_sums(K.part_flag_a, K.part_cost_a, W.chunk_begin, W.chunk_end, true, threadIdx.x, fdummy, F);
   if (threadIdx.x == 0) {
     ba_report r;
     double c0 = st.init_cost, cf = st.cost;
-    if (need_cost) {   // no attempt ran: the cost comes from the pass-A partials
-      double F = 0.0;
-      for (int c = W.chunk_begin; c < W.chunk_end; ++c) F += K.part_cost_a[c];
-      c0 = cf = 0.5 * F;
-    }
+    if (need_cost) c0 = cf = 0.5 * F;
     r.initial_cost = c0;
     r.final_cost = cf;
     r.final_lambda = st.lambda;
@@ -1687,28 +1725,23 @@ hipError_t launch_pass_a(const LaunchArgs& A, const DevWork<Real>& K, int it) {
   return hipGetLastError();
 }
 
-// Workgroups along y of k_sum for windows of at most nf free poses.
-inline int sum_slices(int nf) {
-  const int n = (nf * (nf + 1) / 2 * kBS + 12 * nf + kSumSlice - 1) / kSumSlice;
-  return n > 0 ? n : 1;
-}
 
 // The stages after pass A of one LM attempt for the windows [wb, wb + nwin) of
 // win_order (at most nf free poses each) and their chunks [cb, cb + nch) of
 // chunk_order, on stream st.
 template <typename Real, int TP, bool ADJ>
 void launch_stages(const LaunchArgs& A, const DevWork<Real>& K, int it, int wb, int nwin, int cb, int nch, int nf,
-                   hipStream_t st) {
+                   int slices, hipStream_t st) {
   if (nwin <= 0) return;
   const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(nf);
-  hipLaunchKernelGGL(k_sum<Real>, dim3(nwin, sum_slices(nf)), dim3(256), 0, st, A.plan, A.tiles, K, wb);
+  hipLaunchKernelGGL(k_sum<Real>, dim3(nwin, slices), dim3(256), 0, st, A.plan, A.tiles, K, wb);
   hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, ADJ>), dim3(nwin), dim3(kReduceThreads), lr, st, A.plan, A.tiles,
                      K, A.user, A.settings, it, wb);
   if (nch > 0)
     hipLaunchKernelGGL((k_pass_b<Real, TP, ADJ>), dim3(nch), dim3(TP), lb, st, A.plan, A.tiles, K, A.user, A.settings,
                        it, cb);
   if (!ADJ)
-    hipLaunchKernelGGL(k_accept<Real>, dim3((nwin + 63) / 64), dim3(64), 0, st, A.plan, A.tiles, K, A.user,
+    hipLaunchKernelGGL(k_accept<Real>, dim3((nwin + 3) / 4), dim3(256), 0, st, A.plan, A.tiles, K, A.user,
                        A.settings, it, wb, nwin);
 }
 
@@ -1780,7 +1813,8 @@ void launch_class_attempt(const LaunchArgs& A, const DevWork<Real>& K, int it, c
   const int c = C.cls[k];
   launch_pass_a_class<Real, TP, ADJ>(A, K, it, c, C.st[k]);
   launch_stages<Real, TP, ADJ>(A, K, it, A.cls_win_begin[c], A.cls_win_begin[c + 1] - A.cls_win_begin[c],
-                               A.cls_begin[c], A.cls_begin[c + 1] - A.cls_begin[c], A.cls_win_nf[c], C.st[k]);
+                               A.cls_begin[c], A.cls_begin[c + 1] - A.cls_begin[c], A.cls_win_nf[c],
+                               A.cls_sum_slices[c], C.st[k]);
 }
 
 template <typename Real, int TP>
@@ -1800,7 +1834,7 @@ hipError_t run_solve(const LaunchArgs& A, const DevWork<Real>& K) {
   } else {
     for (int it = 0; it < iters; ++it) {
       if ((e = launch_pass_a<Real, TP, false>(A, K, it)) != hipSuccess) return e;
-      launch_stages<Real, TP, false>(A, K, it, 0, nw, 0, nc, A.max_nf, main);
+      launch_stages<Real, TP, false>(A, K, it, 0, nw, 0, nc, A.max_nf, A.sum_slices, main);
     }
   }
   if (iters == 0 && (e = launch_pass_a<Real, TP, false>(A, K, 0)) != hipSuccess)   // the report still needs the input cost
@@ -1824,7 +1858,7 @@ hipError_t run_adjoint(const LaunchArgs& A, const DevWork<Real>& K) {
     if ((e = join_chains(A, C)) != hipSuccess) return e;
   } else {
     if ((e = launch_pass_a<Real, TP, true>(A, K, 0)) != hipSuccess) return e;
-    launch_stages<Real, TP, true>(A, K, 0, 0, nw, 0, nc, A.max_nf, main);
+    launch_stages<Real, TP, true>(A, K, 0, 0, nw, 0, nc, A.max_nf, A.sum_slices, main);
   }
   return hipGetLastError();
 }
@@ -1850,14 +1884,14 @@ hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* 
   for (int it = 0; it < iters && e == hipSuccess; ++it) {
     e = launch_pass_a<Real, TP, false>(A, K, it);
     (void)hipEventRecord(ev[4 * it + 1], main);
-    hipLaunchKernelGGL(k_sum<Real>, dim3(nw, sum_slices(A.max_nf)), dim3(256), 0, main, A.plan, A.tiles, K, 0);
+    hipLaunchKernelGGL(k_sum<Real>, dim3(nw, A.sum_slices), dim3(256), 0, main, A.plan, A.tiles, K, 0);
     hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, false>), dim3(nw), dim3(kReduceThreads), lr, main, A.plan,
                        A.tiles, K, A.user, A.settings, it, 0);
     (void)hipEventRecord(ev[4 * it + 2], main);
     hipLaunchKernelGGL((k_pass_b<Real, TP, false>), dim3(nc), dim3(TP), lb, main, A.plan, A.tiles, K, A.user,
                        A.settings, it, 0);
     (void)hipEventRecord(ev[4 * it + 3], main);
-    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 63) / 64), dim3(64), 0, main, A.plan, A.tiles, K, A.user,
+    hipLaunchKernelGGL(k_accept<Real>, dim3((nw + 3) / 4), dim3(256), 0, main, A.plan, A.tiles, K, A.user,
                        A.settings, it, 0, nw);
     (void)hipEventRecord(ev[4 * it + 4], main);
   }

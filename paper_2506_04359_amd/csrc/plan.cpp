@@ -110,57 +110,85 @@ std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int6
     }
   }
 
-  // landmark-major order: (landmark, fixed, free slot or pose, camera, user index)
+  // landmark-major order: (landmark, fixed, free slot or pose, camera, user
+  // index).  Each observation gets a 64-bit key (pose key, camera, user
+  // index) in one sequential pass; a stable counting sort by landmark puts
+  // the keys in landmark runs (user order inside a run), and each run, short
+  // and contiguous, is sorted by key.  Everything after reads the sorted keys
+  // in order.
   auto cam_of = [&](int64_t o) { return obs_cam ? obs_cam[o] : 0; };
+  int32_t pose_of_key[2 * kMaxPoses];
   auto pose_key = [&](int32_t i) {
     return w.fixed[i] ? (int32_t)(kMaxPoses + i) : w.free_slot[i];
   };
-  std::vector<int32_t> order(n_obs);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (obs_point[a] != obs_point[b]) return obs_point[a] < obs_point[b];
-    const int32_t ka = pose_key(obs_pose[a]), kb = pose_key(obs_pose[b]);
-    if (ka != kb) return ka < kb;
-    if (cam_of(a) != cam_of(b)) return cam_of(a) < cam_of(b);
-    return a < b;
-  });
-  w.perm = order;
+  for (int i = 0; i < n_poses; ++i) pose_of_key[pose_key(i)] = i;
+  std::vector<int64_t> start((size_t)n_points + 1, 0);
+  std::vector<uint64_t> key(n_obs);
+  {
+    for (int64_t o = 0; o < n_obs; ++o) start[obs_point[o] + 1]++;
+    for (int32_t j = 0; j < n_points; ++j) start[j + 1] += start[j];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t o = 0; o < n_obs; ++o) {
+      const uint64_t k = ((uint64_t)pose_key(obs_pose[o]) << 40) | ((uint64_t)cam_of(o) << 32) | (uint64_t)o;
+      key[fill[obs_point[o]]++] = k;
+    }
+    for (int32_t j = 0; j < n_points; ++j) {
+      uint64_t* b = key.data() + start[j];
+      const int64_t len = start[j + 1] - start[j];
+      if (len <= 32) {
+        for (int64_t x = 1; x < len; ++x) {   // insertion sort
+          const uint64_t v = b[x];
+          int64_t y = x;
+          for (; y > 0 && v < b[y - 1]; --y) b[y] = b[y - 1];
+          b[y] = v;
+        }
+      } else {
+        std::sort(b, b + len);
+      }
+    }
+  }
+  w.perm.resize(n_obs);
   w.obs_cam.resize(n_obs);
-  for (int64_t k = 0; k < n_obs; ++k) w.obs_cam[k] = (uint8_t)cam_of(order[k]);
+  for (int64_t k = 0; k < n_obs; ++k) {
+    w.perm[k] = (int32_t)(key[k] & 0xffffffffu);
+    w.obs_cam[k] = (uint8_t)((key[k] >> 32) & 0xff);
+  }
 
   // pairs and landmark ranges
   w.pair_obs_begin.clear();
   w.pair_lm.clear();
   w.pair_pose.clear();
+  w.pair_obs_begin.reserve((size_t)n_obs + 1);
+  w.pair_lm.reserve((size_t)n_obs);
+  w.pair_pose.reserve((size_t)n_obs);
   w.lm_pair_begin.assign((size_t)n_points + 1, 0);
   w.lm_nfree.assign(n_points, 0);
-  std::vector<int32_t> lm_obs(n_points, 0);
-  std::vector<uint64_t> lm_views(n_points, 0);   // distinct (pose, cam) count, capped
-  for (int64_t k = 0; k < n_obs; ++k) {
-    const int32_t o = order[k];
-    const int32_t j = obs_point[o], i = obs_pose[o];
-    const bool new_pair = (k == 0) || obs_point[order[k - 1]] != j || obs_pose[order[k - 1]] != i;
-    const bool new_view = new_pair || cam_of(order[k - 1]) != cam_of(o);
-    if (new_pair) {
-      w.pair_obs_begin.push_back((int32_t)k);
-      w.pair_lm.push_back(j);
-      w.pair_pose.push_back((uint8_t)i);
-      w.lm_pair_begin[j + 1]++;
-      if (!w.fixed[i]) w.lm_nfree[j]++;
+  for (int32_t j = 0; j < n_points; ++j) {
+    int views = 0;
+    for (int64_t k = start[j]; k < start[j + 1]; ++k) {
+      const uint32_t pk = (uint32_t)(key[k] >> 40), cm = (uint32_t)(key[k] >> 32) & 0xff;
+      const bool new_pair = k == start[j] || (uint32_t)(key[k - 1] >> 40) != pk;
+      const bool new_view = new_pair || ((uint32_t)(key[k - 1] >> 32) & 0xff) != cm;
+      if (new_pair) {
+        const int32_t i = pose_of_key[pk];
+        w.pair_obs_begin.push_back((int32_t)k);
+        w.pair_lm.push_back(j);
+        w.pair_pose.push_back((uint8_t)i);
+        w.lm_pair_begin[j + 1]++;
+        if (!w.fixed[i]) w.lm_nfree[j]++;
+      }
+      if (new_view) views++;
     }
-    if (new_view) lm_views[j]++;
-    lm_obs[j]++;
-  }
-  w.pair_obs_begin.push_back((int32_t)n_obs);
-  for (int j = 0; j < n_points; ++j) {
-    if (lm_views[j] < 2) {
+    if (views < 2) {
       std::ostringstream s;
       s << "landmark " << j << " has fewer than 2 distinct (pose, camera) views";
       return fail(code, -1, s.str());
     }
-    if (lm_obs[j] > kMaxObsPerLandmark) return fail(code, -5, "too many observations of one landmark");
+    if (start[j + 1] - start[j] > kMaxObsPerLandmark)
+      return fail(code, -5, "too many observations of one landmark");
     w.lm_pair_begin[j + 1] += w.lm_pair_begin[j];
   }
+  w.pair_obs_begin.push_back((int32_t)n_obs);
   w.schur_blocks = 0;
   w.n_free_pairs = 0;
   for (int j = 0; j < n_points; ++j) {
@@ -207,20 +235,27 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
     }
     const int32_t first_tile = (int32_t)t.tile_lm_begin.size();
     for (int32_t s : tiles) t.tile_lm_begin.push_back(lm_base + s);
-    // per-tile pair order and Schur product lists
+    // per-tile pair order and Schur product lists, by counting sorts (keys
+    // are small: free slots, target blocks, product counts)
     const int nblk = w.n_free * (w.n_free + 1) / 2;
-    std::vector<std::vector<uint16_t>> by_blk(nblk);
+    std::vector<int32_t> blk_count(nblk), blk_fill(nblk), ord, slot_start(kMaxFree + 3);
+    std::vector<uint16_t> prod_blk_q, prods;   // products in landmark order, then grouped
+    std::vector<int32_t> prod_blk;
+    std::vector<int32_t> order, size_start(kTileLarge / 2 + 2);
     for (size_t ti = 0; ti < tiles.size(); ++ti) {
       const int32_t la = tiles[ti];
       const int32_t lb = ti + 1 < tiles.size() ? tiles[ti + 1] : w.n_points;
       const int32_t p0 = w.lm_pair_begin[la], p1 = w.lm_pair_begin[lb];
-      std::vector<int32_t> ord(p1 - p0);
-      std::iota(ord.begin(), ord.end(), 0);
+      // pairs stably by free slot (fixed pairs last)
       auto key = [&](int32_t q) {
         const int sl = w.free_slot[w.pair_pose[p0 + q]];
         return sl >= 0 ? sl : kMaxFree + 1;
       };
-      std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+      std::fill(slot_start.begin(), slot_start.end(), 0);
+      for (int32_t q = 0; q < p1 - p0; ++q) slot_start[key(q) + 1]++;
+      for (int k = 0; k + 1 < (int)slot_start.size(); ++k) slot_start[k + 1] += slot_start[k];
+      ord.resize(p1 - p0);
+      for (int32_t q = 0; q < p1 - p0; ++q) ord[slot_start[key(q)]++] = q;
       for (int32_t q : ord) {
         const int32_t wp = p0 + q;   // window-local pair
         const int32_t nobs = w.pair_obs_begin[wp + 1] - w.pair_obs_begin[wp];
@@ -229,32 +264,45 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
         t.pair_rec.push_back((int32_t)w.pair_pose[wp] | (q << 8) | (nobs << 16));
         t.pair_rec.push_back(w.free_slot[w.pair_pose[wp]]);
       }
-      for (auto& v : by_blk) v.clear();
+      // products (a, b), a < b, of each landmark's free pairs, with their
+      // target block; (a, a) is summed per pair in the kernels
+      prod_blk_q.clear();
+      prod_blk.clear();
+      std::fill(blk_count.begin(), blk_count.end(), 0);
       for (int32_t l = la; l < lb; ++l) {
         const int32_t q0 = w.lm_pair_begin[l] - p0;
         const int nfp = w.lm_nfree[l];
         for (int a = 0; a < nfp; ++a)
-          for (int b = a + 1; b < nfp; ++b) {   // (a, a) is summed per pair in the kernels
+          for (int b = a + 1; b < nfp; ++b) {
             const int sa = w.free_slot[w.pair_pose[p0 + q0 + a]];
             const int sb = w.free_slot[w.pair_pose[p0 + q0 + b]];
             const int blk = sa * w.n_free - (sa * (sa - 1)) / 2 + (sb - sa);
-            by_blk[blk].push_back((uint16_t)((q0 + a) | ((q0 + b) << 8)));
+            prod_blk_q.push_back((uint16_t)((q0 + a) | ((q0 + b) << 8)));
+            prod_blk.push_back(blk);
+            blk_count[blk]++;
           }
       }
-      std::vector<int> order;
+      // target blocks by product count, largest first, ties in block order
+      std::fill(size_start.begin(), size_start.end(), 0);
+      int nseg = 0;
       for (int k = 0; k < nblk; ++k)
-        if (!by_blk[k].empty()) order.push_back(k);
-      std::stable_sort(order.begin(), order.end(),
-                       [&](int a, int b) { return by_blk[a].size() > by_blk[b].size(); });
+        if (blk_count[k] > 0) {
+          size_start[kTileLarge / 2 + 1 - blk_count[k]]++;
+          ++nseg;
+        }
+      for (int k = 0; k + 1 < (int)size_start.size(); ++k) size_start[k + 1] += size_start[k];
+      order.resize(nseg);
+      for (int k = 0; k < nblk; ++k)
+        if (blk_count[k] > 0) order[size_start[kTileLarge / 2 - blk_count[k]]++] = k;
       const int32_t word_first = (int32_t)t.lists.size();
       int start = 0;
       for (int k : order) {
-        t.lists.push_back(seg_word(k, start, (int)by_blk[k].size()));
-        start += (int)by_blk[k].size();
+        t.lists.push_back(seg_word(k, start, blk_count[k]));
+        blk_fill[k] = start;
+        start += blk_count[k];
       }
-      std::vector<uint16_t> prods;
-      for (int k : order)
-        for (uint16_t v : by_blk[k]) prods.push_back(v);
+      prods.resize(start);
+      for (size_t x = 0; x < prod_blk.size(); ++x) prods[blk_fill[prod_blk[x]]++] = prod_blk_q[x];
       for (size_t k = 0; k < prods.size(); k += 2)
         t.lists.push_back((uint32_t)prods[k] | ((k + 1 < prods.size() ? (uint32_t)prods[k + 1] : 0u) << 16));
       t.max_tile_prods = std::max(t.max_tile_prods, start);
