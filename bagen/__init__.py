@@ -33,7 +33,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Tuple
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -883,3 +883,105 @@ def make_vi_window(seed: int = 9000, n_kf: int = 10, n_lm: int = 400, kf_dt: flo
     vel_init = vels + (rng.normal(scale=0.05, size=vels.shape) if init_noise else 0.0)
     return ViWindow(window=w, gravity=g, dt=dt, gyro=gyros, accel=accels, vel_gt=vels, ba_gt=ba, bg_gt=bg,
                     vel_init=vel_init, ba_init=np.zeros((n_kf, 3)), bg_init=np.zeros((n_kf, 3)), noise=noise)
+
+
+# ---------------------------------------------------------------------------
+# keyframe sequences for the sliding-window local map
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Keyframe:
+    """What the frontend hands the local map at one keyframe: the pose estimate,
+    the landmarks created there (ids and triangulated positions) and the
+    keyframe's observations (all in the newest keyframe of the window)."""
+    pose_gt: np.ndarray         # (3, 4) base-from-world
+    pose_init: np.ndarray       # (3, 4) the frontend's estimate
+    new_ids: np.ndarray         # (n_new,) int64
+    new_points: np.ndarray      # (n_new, 3) triangulated estimates
+    obs_lm: np.ndarray          # (n_obs,) int64 landmark ids
+    obs_cam: np.ndarray         # (n_obs,) int32
+    obs_uv: np.ndarray          # (n_obs, 2) pixels
+
+
+@dataclasses.dataclass
+class Sequence:
+    intrinsics: np.ndarray      # (2, 4)
+    extrinsics: np.ndarray      # (2, 3, 4)
+    points_gt: Dict[int, np.ndarray]
+    keyframes: List[Keyframe]
+
+
+def make_stereo_sequence(n_keyframes: int = 40, births: int = 250, seed: int = 11000,
+                         geom_p: float = 0.14, sigma_px: float = 0.7) -> Sequence:
+    """The stereo rig of the stereo window (1241x376, f = 718, 0.54 m baseline)
+    driving 1 m per keyframe with a small random yaw.  At each keyframe about
+    `births` landmarks are created (depth log-uniform in [3, 60] m along a
+    random pixel of the left image) and tracked forward for 2 + Geom(p) - 1
+    keyframes, at most 15, while both cameras see them; every keyframe observes
+    each of its live landmarks in both cameras (pixel noise sigma_px).  The
+    pose estimate is the truth perturbed by 0.01 rad / 0.05 m (pose 0 exact),
+    a new landmark's estimate the truth plus N(0, (0.02 depth)^2) per axis."""
+    rng = np.random.default_rng(seed)
+    K = np.array([718.0, 718.0, 607.0, 185.0])
+    size = np.array([1241.0, 376.0])
+    ext = np.zeros((2, 3, 4))
+    ext[0, :, :3] = np.eye(3)
+    ext[1, :, :3] = np.eye(3)
+    ext[1, :, 3] = [-0.54, 0.0, 0.0]
+    yaw, c = 0.0, np.zeros(3)
+    poses = []
+    for i in range(n_keyframes):
+        poses.append(_pose_from_cam_to_world(_rot_y(yaw), c.copy()))
+        c = c + _rot_y(yaw) @ np.array([0.0, 0.0, 1.0])
+        yaw += rng.uniform(-1.0, 1.0) * math.pi / 180.0
+    pts: Dict[int, np.ndarray] = {}
+    live: Dict[int, int] = {}   # id -> last keyframe of its track
+    kfs = []
+    next_id = 0
+    for i in range(n_keyframes):
+        new_ids, new_pts = [], []
+        for _ in range(births):
+            for _try in range(50):
+                u, v = rng.uniform(0, size[0]), rng.uniform(0, size[1])
+                depth = math.exp(rng.uniform(math.log(3.0), math.log(60.0)))
+                xc = np.array([(u - K[2]) / K[0] * depth, (v - K[3]) / K[1] * depth, depth])
+                p = poses[i][:, :3].T @ (xc - poses[i][:, 3])
+                if _visible(K, size, _to_cam(poses[i], ext[1], p[None]))[0]:
+                    break
+            else:
+                continue
+            L = min(2 + int(rng.geometric(geom_p)) - 1, 15)
+            lid = next_id
+            next_id += 1
+            pts[lid] = p
+            live[lid] = i + L - 1
+            new_ids.append(lid)
+            new_pts.append(p + rng.normal(scale=0.02 * depth, size=3))
+        o_lm, o_cam, o_uv = [], [], []
+        for lid in list(live):
+            if live[lid] < i:
+                del live[lid]
+                continue
+            p = pts[lid]
+            vis = [_visible(K, size, _to_cam(poses[i], ext[k], p[None]))[0] for k in range(2)]
+            if not all(vis):
+                if lid in new_ids:   # cannot happen for a fresh landmark: both checked
+                    raise AssertionError("new landmark not in view")
+                del live[lid]
+                continue
+            for k in range(2):
+                o_lm.append(lid)
+                o_cam.append(k)
+                o_uv.append(_project(K, _to_cam(poses[i], ext[k], p[None]))[0])
+        o_uv = np.asarray(o_uv).reshape(-1, 2) + rng.normal(scale=sigma_px, size=(len(o_lm), 2))
+        P = poses[i]
+        if i == 0:
+            Pi = P.copy()
+        else:
+            Rd = _rot_axis(_random_unit(rng), 0.01)
+            Pi = np.concatenate([Rd @ P[:, :3], (Rd @ P[:, 3] + 0.05 * _random_unit(rng))[:, None]], axis=1)
+        kfs.append(Keyframe(pose_gt=P, pose_init=Pi, new_ids=np.asarray(new_ids, np.int64),
+                            new_points=np.asarray(new_pts).reshape(-1, 3),
+                            obs_lm=np.asarray(o_lm, np.int64), obs_cam=np.asarray(o_cam, np.int32),
+                            obs_uv=o_uv))
+    return Sequence(intrinsics=np.stack([K, K]), extrinsics=ext, points_gt=pts, keyframes=kfs)

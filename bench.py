@@ -18,6 +18,8 @@ Printed as one JSON line:
   pnp                motion-only refinement of 4096 stereo frames (300 landmarks
                      each) and of 512 frames of the 32-camera rig: frames and
                      LM attempts per second
+  local_map          a 50-keyframe stereo sequence through a 20-keyframe local map:
+                     per keyframe the insertion, the plan rebuild and the solve
   triangulation      every landmark of the 256 windows re-triangulated from its
                      observations (poses at ground truth): landmarks per second
   pgo                pose-graph optimisation of a 1500-pose, 2988-edge helix
@@ -182,6 +184,7 @@ def main():
     ap.add_argument("--no-pgo", action="store_true", help="skip the pose-graph leg")
     ap.add_argument("--chunk-obs", type=int, default=None,
                     help="fixed observations per work item instead of the autotuned value")
+    ap.add_argument("--no-map", action="store_true", help="skip the sliding-window local map leg")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-window legs (mono, stereo and rig windows)")
     ap.add_argument("--cpu-sample", type=int, default=N_WINDOWS,
@@ -406,6 +409,54 @@ def main():
             log(f"{name}: mixed {leg['mixed']['ms_per_solve']:.3f} ms, fp64 {leg['fp64']['ms_per_solve']:.3f} ms "
                 f"per {w.max_iters}-attempt solve")
             del win, one
+
+    # the sliding-window local map: a stereo keyframe sequence through a
+    # 20-keyframe window, each keyframe inserted (slide, new landmarks and
+    # observations, device gather), the window's plan rebuilt on the host and
+    # the window solved (mixed, 10 attempts)
+    if not args.no_map:
+        seq = bagen.make_stereo_sequence(n_keyframes=50, births=250, seed=11100)
+        NW = 20
+        mp = ba.Map(NW, seq.intrinsics, seq.extrinsics.reshape(-1, 12))
+        sm = ba.Settings(max_iters=10, precision=ba.BA_MIXED, lambda_init=1e-3, huber_delta=1.0)
+        wsm = torch.empty(256, dtype=torch.uint8, device=dev)
+        rows = []
+        for i, kf in enumerate(seq.keyframes):
+            kfi = np.full(kf.obs_lm.shape[0], min(i + 1, NW) - 1, np.int32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mp.add_keyframe(kf.pose_init, kf.new_ids, kf.new_points, kfi, kf.obs_lm, kf.obs_cam, kf.obs_uv)
+            t1 = time.perf_counter()
+            if i == 0:
+                continue
+            Wm = mp.window()
+            t2 = time.perf_counter()
+            need = Wm.workspace_size(sm)
+            if wsm.numel() < need:
+                wsm = torch.empty(2 * need, dtype=torch.uint8, device=dev)
+            torch.cuda.synchronize()
+            m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t3 = time.perf_counter()
+            m0.record()
+            mp.solve(sm, workspace=wsm)
+            m1.record()
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            K_, M_, n_ = mp.info()
+            rows.append((t1 - t0, t2 - t1, m0.elapsed_time(m1) / 1e3, t4 - t3, K_, M_, n_))
+        steady = [r for r in rows if r[4] == NW]
+        A = np.array([r[:4] for r in steady])
+        per_kf = float(A[:, 0].mean() + A[:, 1].mean() + A[:, 3].mean())
+        out["local_map"] = {
+            "workload": "stereo-sequence-50kf-window20", "keyframes": len(seq.keyframes), "window": NW,
+            "steady_keyframes": len(steady), "mean_points": float(np.mean([r[5] for r in steady])),
+            "mean_observations": float(np.mean([r[6] for r in steady])),
+            "insert_ms": 1e3 * float(A[:, 0].mean()), "plan_ms": 1e3 * float(A[:, 1].mean()),
+            "solve_ms": 1e3 * float(A[:, 2].mean()), "solve_wall_ms": 1e3 * float(A[:, 3].mean()),
+            "keyframes_per_s": 1.0 / per_kf, "lm_attempts_per_window": 10, "precision": "mixed"}
+        log(f"local map: insert {out['local_map']['insert_ms']:.2f} ms, plan {out['local_map']['plan_ms']:.2f} ms, "
+            f"solve {out['local_map']['solve_ms']:.2f} ms per keyframe ({out['local_map']['mean_observations']:.0f} obs)")
+        del mp
 
     # adjoint on 64 windows of 10 keyframes / 2000 landmarks
     if not args.no_adjoint:

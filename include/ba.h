@@ -414,6 +414,80 @@ ba_status ba_pgo_solve(ba_graph g, const ba_settings* s, double* poses, const do
                        const double* edge_w, void* workspace, size_t ws_bytes, ba_report* report,
                        ba_iter_trace* traces, void* stream);
 
+/* -------------------------------------------------------------------------
+ * Sliding-window local map (paper Sec. 2.1: the frontend keeps the last N
+ * keyframe poses with the landmarks visible from them and their
+ * observations; Sec. 2.2: at a keyframe, triangulated landmarks enter the map
+ * with their observations and the sparse bundle adjustment refines it).
+ * Rules (the paper gives none):
+ *   - inserting a keyframe into a full map (max_keyframes) first drops the
+ *     oldest keyframe with all its observations, then every landmark left
+ *     with fewer than two distinct (keyframe, camera) views, with its
+ *     remaining observations (no marginalisation);
+ *   - an insertion brings the keyframe's pose, the landmarks created at it
+ *     (caller ids and positions) and observations; each observation names a
+ *     keyframe of the window after the insertion (0 = oldest), so a new
+ *     landmark may also be seen in earlier keyframes;
+ *   - every new landmark needs two distinct views; ids are unique in the map;
+ *     an invalid insertion returns INVALID_ARG and leaves the map unchanged;
+ *   - the solver's window: keyframes oldest first with the oldest fixed,
+ *     landmarks in order of creation, observations in order of insertion.
+ * Values (poses, points, pixels, weights) live on the map's device in the
+ * window's order, so a solve refines them in place and the next insertion
+ * carries the refined values over.  Not thread-safe: calls on one map must be
+ * ordered by the caller.
+ * ------------------------------------------------------------------------- */
+typedef struct ba_map_s* ba_map;
+
+/* n_cams cameras (intrinsics HOST n_cams x 4, extrinsics HOST n_cams x 12 or
+ * NULL, as ba_window_create); 2 <= max_keyframes <= 64; flags 0 or
+ * BA_CREATE_HOST_ONLY (index lists only, no device values: for inspection).
+ * The device is the current one.  Errors: INVALID_ARG. */
+ba_status ba_map_create(int32_t max_keyframes, int32_t n_cams, const double* intrinsics,
+                        const double* extrinsics, int32_t flags, ba_map* out);
+void ba_map_destroy(ba_map m);
+
+/* Insert a keyframe.  HOST arrays: pose (12, base-from-world), new_ids
+ * (n_new), new_points (n_new x 3 world), obs_kf (n_obs, keyframe index in the
+ * window after the insertion), obs_lm (n_obs landmark ids), obs_cam (n_obs or
+ * NULL: camera 0), obs_uv (n_obs x 2), obs_w (n_obs or NULL: 1).  Writes the
+ * number of landmarks the slide dropped to *n_dropped (may be NULL).  Device
+ * work (staging copies and one gather kernel per array) runs on `stream`;
+ * the call waits for it, and may allocate device memory when the window
+ * grows.  Errors: INVALID_ARG (map unchanged), OOM, HIP. */
+ba_status ba_map_add_keyframe(ba_map m, const double* pose, int32_t n_new, const int64_t* new_ids,
+                              const double* new_points, int64_t n_obs, const int32_t* obs_kf,
+                              const int64_t* obs_lm, const int32_t* obs_cam, const double* obs_uv,
+                              const double* obs_w, int32_t* n_dropped, void* stream);
+
+/* Sizes of the current window (any output may be NULL). */
+ba_status ba_map_info(ba_map m, int32_t* n_keyframes, int32_t* n_points, int64_t* n_obs);
+
+/* HOST copies of the window's index lists in the solver's layout (any may be
+ * NULL; sized by ba_map_info): obs_pose, obs_point, obs_cam (int32, n_obs),
+ * landmark_ids (int64, n_points). */
+ba_status ba_map_lists(ba_map m, int32_t* obs_pose, int32_t* obs_point, int32_t* obs_cam,
+                       int64_t* landmark_ids);
+
+/* DEVICE arrays of the window's values, owned by the map and valid until the
+ * next insertion or destroy: poses (n_keyframes x 12), points (n_points x 3),
+ * obs_uv (n_obs x 2), obs_w (n_obs).  Errors: STATE for a host-only map. */
+ba_status ba_map_arrays(ba_map m, double** poses, double** points, const double** obs_uv,
+                        const double** obs_w);
+
+/* HOST copies of the window's values (any may be NULL; sized by ba_map_info);
+ * synchronous (waits for the device).  Errors: STATE for a host-only map. */
+ba_status ba_map_read(ba_map m, double* poses, double* points, double* obs_uv, double* obs_w);
+
+/* The plan of the current window (rebuilt after an insertion; owned by the
+ * map, valid until the next insertion or destroy): for ba_workspace_size and
+ * ba_solve.  Errors: STATE (fewer than two keyframes), as ba_window_create. */
+ba_status ba_map_window(ba_map m, ba_window* window);
+
+/* ba_solve of the current window on the map's device arrays, in place. */
+ba_status ba_map_solve(ba_map m, const ba_settings* s, void* workspace, size_t ws_bytes,
+                       ba_report* report, ba_iter_trace* trace, void* stream);
+
 const char* ba_status_string(ba_status s);
 const char* ba_last_error(void);
 

@@ -29,6 +29,7 @@ from ._binding import (  # noqa: F401
     pnp_solve,
     triangulate,
     Graph,
+    Map,
     pgo_solve,
     solve,
     solve_batched,

@@ -101,6 +101,17 @@ def lib():
                                      vp, vp, vp, vp]
         L.ba_pnp_solve.argtypes = [vp, ctypes.POINTER(_Settings), i32, i64, i64, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp, vp]
+        L.ba_map_create.argtypes = [i32, i32, vp, vp, i32, ctypes.POINTER(vp)]
+        L.ba_map_destroy.argtypes = [vp]
+        L.ba_map_add_keyframe.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(i32), vp]
+        L.ba_map_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.ba_map_lists.argtypes = [vp, vp, vp, vp, vp]
+        L.ba_map_arrays.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp)]
+        L.ba_map_window.argtypes = [vp, ctypes.POINTER(vp)]
+        L.ba_map_read.argtypes = [vp, vp, vp, vp, vp]
+        L.ba_map_solve.argtypes = [vp, ctypes.POINTER(_Settings), vp, sz, vp, vp, vp]
         L.ba_status_string.argtypes = [i32]
         L.ba_status_string.restype = ctypes.c_char_p
         L.ba_last_error.restype = ctypes.c_char_p
@@ -108,7 +119,9 @@ def lib():
                   "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_noalloc", "ba_solve_batched",
                   "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
                   "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate", "ba_graph_create", "ba_graph_info",
-                  "ba_graph_plan_array", "ba_graph_workspace_size", "ba_pgo_solve"):
+                  "ba_graph_plan_array", "ba_graph_workspace_size", "ba_pgo_solve", "ba_map_create",
+                  "ba_map_add_keyframe", "ba_map_info", "ba_map_lists", "ba_map_arrays", "ba_map_window", "ba_map_read",
+                  "ba_map_solve"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -476,3 +489,102 @@ def pgo_solve(graph: Graph, settings: Settings, poses, deltas, workspace, edge_w
     _check(lib().ba_pgo_solve(graph._h, ctypes.byref(settings.c()), _ptr(poses), _ptr(deltas), _ptr(edge_w),
                               _ptr(workspace), workspace.numel(), _ptr(report), _ptr(traces), _stream(stream)))
     return report, traces
+
+
+class _BorrowedWindow(Window):
+    """A plan owned by a map (not destroyed by this object)."""
+
+    def __init__(self, handle, n_poses, n_points, n_obs):
+        self._h = ctypes.c_void_p(handle)
+        self.n_poses, self.n_points, self.n_obs = n_poses, n_points, n_obs
+
+    def close(self):
+        self._h = ctypes.c_void_p()
+
+
+class Map:
+    """Sliding-window local map (ba_map_*): host index lists, device values."""
+
+    def __init__(self, max_keyframes, intrinsics, extrinsics=None, host_only=False):
+        K = _host(intrinsics, np.float64).reshape(-1, 4)
+        E = None if extrinsics is None else _host(extrinsics, np.float64).reshape(-1, 12)
+        h = ctypes.c_void_p()
+        _check(lib().ba_map_create(int(max_keyframes), int(K.shape[0]), K.ctypes.data_as(ctypes.c_void_p),
+                                   None if E is None else E.ctypes.data_as(ctypes.c_void_p),
+                                   BA_CREATE_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        self._h = h
+        self.host_only = bool(host_only)
+
+    def add_keyframe(self, pose, new_ids=(), new_points=None, obs_kf=(), obs_lm=(), obs_cam=None, obs_uv=None,
+                     obs_w=None, stream=None) -> int:
+        P = _host(pose, np.float64).reshape(12)
+        ni = _host(np.asarray(new_ids, np.int64).reshape(-1), np.int64)
+        npts = _host(np.zeros((0, 3)) if new_points is None else new_points, np.float64).reshape(-1, 3)
+        ok = _host(np.asarray(obs_kf, np.int32).reshape(-1), np.int32)
+        ol = _host(np.asarray(obs_lm, np.int64).reshape(-1), np.int64)
+        n = ok.shape[0]
+        oc = None if obs_cam is None else _host(obs_cam, np.int32)
+        ouv = _host(np.zeros((0, 2)) if obs_uv is None else obs_uv, np.float64).reshape(-1, 2)
+        ow = None if obs_w is None else _host(obs_w, np.float64)
+        vp = lambda a: None if a is None or a.size == 0 else a.ctypes.data_as(ctypes.c_void_p)
+        nd = ctypes.c_int32()
+        st = None if self.host_only else _stream(stream)
+        _check(lib().ba_map_add_keyframe(self._h, vp(P), int(ni.shape[0]), vp(ni), vp(npts), int(n), vp(ok),
+                                         vp(ol), vp(oc), vp(ouv), vp(ow), ctypes.byref(nd), st))
+        return nd.value
+
+    def info(self):
+        k, p, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().ba_map_info(self._h, ctypes.byref(k), ctypes.byref(p), ctypes.byref(o)))
+        return k.value, p.value, o.value
+
+    def lists(self):
+        k, p, o = self.info()
+        op, oj, oc = (np.empty(o, np.int32) for _ in range(3))
+        ids = np.empty(p, np.int64)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+        _check(lib().ba_map_lists(self._h, vp(op), vp(oj), vp(oc), vp(ids)))
+        return dict(obs_pose=op, obs_point=oj, obs_cam=oc, landmark_ids=ids)
+
+    def arrays(self):
+        """Device addresses of the values: (poses, points, obs_uv, obs_w), valid
+        until the next insertion."""
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        _check(lib().ba_map_arrays(self._h, *[ctypes.byref(x) for x in ptrs]))
+        return tuple(p.value for p in ptrs)
+
+    def read(self):
+        """Host copies of the values: poses (K, 3, 4), points (M, 3), obs_uv (n, 2), obs_w (n,)."""
+        k, p, o = self.info()
+        P, L, uv, w = np.empty((k, 3, 4)), np.empty((p, 3)), np.empty((o, 2)), np.empty(o)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+        _check(lib().ba_map_read(self._h, vp(P), vp(L), vp(uv), vp(w)))
+        return P, L, uv, w
+
+    def window(self) -> Window:
+        h = ctypes.c_void_p()
+        _check(lib().ba_map_window(self._h, ctypes.byref(h)))
+        k, p, o = self.info()
+        return _BorrowedWindow(h.value, k, p, o)
+
+    def solve(self, settings: Settings, workspace=None, report=None, trace=None, stream=None):
+        import torch
+        w = self.window()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        workspace = _workspace(w, settings, workspace, dev)
+        if report is None:
+            report = torch.zeros(REPORT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        _check(lib().ba_map_solve(self._h, ctypes.byref(settings.c()), _ptr(workspace), workspace.numel(),
+                                  _ptr(report), _ptr(trace), _stream(stream)))
+        return report, trace, workspace
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ba_map_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
