@@ -20,6 +20,10 @@ Printed as one JSON line:
                      LM attempts per second
   local_map          a 50-keyframe stereo sequence through a 20-keyframe local map:
                      per keyframe the insertion, the plan rebuild and the solve
+  visual_inertial    a 10-keyframe mono window with 200 Hz IMU samples: the
+                     preintegration and the visual-inertial solve beside the
+                     visual-only solve of the same window, with the trajectory's
+                     scale against ground truth
   triangulation      every landmark of the 256 windows re-triangulated from its
                      observations (poses at ground truth): landmarks per second
   pgo                pose-graph optimisation of a 1500-pose, 2988-edge helix
@@ -185,6 +189,7 @@ def main():
     ap.add_argument("--chunk-obs", type=int, default=None,
                     help="fixed observations per work item instead of the autotuned value")
     ap.add_argument("--no-map", action="store_true", help="skip the sliding-window local map leg")
+    ap.add_argument("--no-vi", action="store_true", help="skip the visual-inertial window leg")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-window legs (mono, stereo and rig windows)")
     ap.add_argument("--cpu-sample", type=int, default=N_WINDOWS,
@@ -457,6 +462,89 @@ def main():
         log(f"local map: insert {out['local_map']['insert_ms']:.2f} ms, plan {out['local_map']['plan_ms']:.2f} ms, "
             f"solve {out['local_map']['solve_ms']:.2f} ms per keyframe ({out['local_map']['mean_observations']:.0f} obs)")
         del mp
+
+    # visual-inertial window (Eq. 9): 10 keyframes 0.25 s apart, 400 landmarks,
+    # 200 Hz IMU samples; the preintegration of its 9 factors, the VI solve and
+    # the visual-only solve of the same window (10 attempts each), replayed
+    # from HIP graphs that restore the initial state
+    if not args.no_vi:
+        vw = bagen.make_vi_window(seed=9300, n_kf=10, n_lm=400)
+        wv = vw.window
+        winv = ba.Window.from_problem(wv)
+        nkf = wv.n_poses
+        tv = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        sbv = tv(np.concatenate([[0], np.cumsum([g.shape[0] for g in vw.gyro])]), torch.int32)
+        gyv, acv = tv(np.concatenate(vw.gyro)), tv(np.concatenate(vw.accel))
+        bbv = tv(np.tile(np.concatenate([vw.ba_init[0], vw.bg_init[0]]), (nkf - 1, 1)))
+        pre = torch.empty((nkf - 1, ba.VI_PREINT_DOUBLES), dtype=torch.float64, device=dev)
+        Pv0, Lv0, uvv = tv(wv.poses_init), tv(wv.points_init), tv(wv.obs_uv)
+        Xv0 = tv(np.concatenate([vw.vel_init, vw.ba_init, vw.bg_init], axis=1))
+        Pv, Lv, Xv = Pv0.clone(), Lv0.clone(), Xv0.clone()
+        vi_out = {"workload": f"vi-mono-{nkf}kf-{wv.n_points}lm-200hz", "observations": int(wv.n_obs),
+                  "landmarks": int(wv.n_points), "keyframes": nkf, "imu_samples": int(gyv.shape[0]),
+                  "lm_attempts": 10}
+
+        def graph_ms(fn):
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.synchronize()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=side):
+                fn()
+            torch.cuda.synchronize()
+            for _ in range(args.warmup):
+                gr.replay()
+            torch.cuda.synchronize()
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record()
+            for _ in range(args.steps):
+                gr.replay()
+            c1.record()
+            torch.cuda.synchronize()
+            return c0.elapsed_time(c1) / args.steps
+
+        def centres(Pn):
+            return -np.einsum("kji,kj->ki", Pn[:, :, :3], Pn[:, :, 3])
+
+        cg = centres(wv.poses_gt)
+        vi_out["preintegrate_ms"] = graph_ms(lambda: ba.vi_preintegrate(sbv, gyv, acv, vw.dt, bbv, vw.noise, out=pre))
+        for pname, prec in (("mixed", ba.BA_MIXED), ("fp64", ba.BA_FP64)):
+            sv = ba.Settings(max_iters=10, precision=prec, lambda_init=1e-3, huber_delta=1.0)
+            wkv = torch.empty(ba.vi_workspace_size(winv, sv), dtype=torch.uint8, device=dev)
+            wko = torch.empty(max(winv.workspace_size(sv), 256), dtype=torch.uint8, device=dev)
+            rpv = torch.zeros(48, dtype=torch.uint8, device=dev)
+            rpo = torch.zeros(48, dtype=torch.uint8, device=dev)
+
+            def vstep():
+                Pv.copy_(Pv0)
+                Lv.copy_(Lv0)
+                Xv.copy_(Xv0)
+                ba.vi_solve(winv, sv, pre, vw.gravity, Pv, Lv, Xv, uvv, None, wkv, rpv)
+
+            def ostep():
+                Pv.copy_(Pv0)
+                Lv.copy_(Lv0)
+                ba.solve(winv, sv, Pv, Lv, uvv, None, wko, rpo)
+
+            d = {"vi_ms_per_solve": graph_ms(vstep)}
+            Pn = Pv.cpu().numpy()
+            rr = ba.parse_reports(rpv)[0]
+            c = centres(Pn)
+            d["vi_accepted"] = int(rr["accepted"])
+            d["vi_scale"] = float(np.linalg.norm(c[-1] - c[0]) / np.linalg.norm(cg[-1] - cg[0]))
+            d["vi_centre_rms_m"] = float(np.sqrt(np.mean(np.sum((c - cg) ** 2, axis=1))))
+            d["vi_velocity_rms"] = float(np.sqrt(np.mean((Xv[:, :3].cpu().numpy() - vw.vel_gt) ** 2)))
+            d["visual_ms_per_solve"] = graph_ms(ostep)
+            c = centres(Pv.cpu().numpy())
+            d["visual_scale"] = float(np.linalg.norm(c[-1] - c[0]) / np.linalg.norm(cg[-1] - cg[0]))
+            d["visual_centre_rms_m"] = float(np.sqrt(np.mean(np.sum((c - cg) ** 2, axis=1))))
+            vi_out[pname] = d
+        out["visual_inertial"] = vi_out
+        log(f"visual-inertial: preintegration {vi_out['preintegrate_ms']:.3f} ms; mixed VI "
+            f"{vi_out['mixed']['vi_ms_per_solve']:.3f} ms vs visual {vi_out['mixed']['visual_ms_per_solve']:.3f} ms "
+            f"per 10-attempt solve; scale {vi_out['mixed']['vi_scale']:.4f} (VI) vs "
+            f"{vi_out['mixed']['visual_scale']:.4f} (visual)")
+        del winv
 
     # adjoint on 64 windows of 10 keyframes / 2000 landmarks
     if not args.no_adjoint:

@@ -193,6 +193,9 @@ ba_status ba_solve(ba_window w, const ba_settings* s, double* poses, double* poi
                    const double* obs_uv, const double* obs_w, void* workspace,
                    size_t ws_bytes, ba_report* report, ba_iter_trace* trace, void* stream);
 
+/* Doubles of one preintegrated IMU factor record (ba_vi_preintegrate). */
+#define BA_VI_PREINT_DOUBLES 320
+
 /* Largest workspace of ba_solve_noalloc, in bytes, per device (64 MiB). */
 #define BA_NOALLOC_SCRATCH_BYTES (64u << 20)
 
@@ -413,6 +416,47 @@ ba_status ba_graph_workspace_size(ba_graph g, size_t* bytes);
 ba_status ba_pgo_solve(ba_graph g, const ba_settings* s, double* poses, const double* deltas,
                        const double* edge_w, void* workspace, size_t ws_bytes, ba_report* report,
                        ba_iter_trace* traces, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Visual-inertial window solve (paper Sec. 2.2, "Visual-Inertial", Eq. 9):
+ * the state of keyframe i is S_i = [T_i, v_i, b^a_i, b^w_i] (pose, world-frame
+ * velocity of the base, accelerometer and gyroscope biases), consecutive
+ * states are tied by an IMU factor (on-manifold preintegration of the IMU
+ * samples between them, after Forster et al. 2017, which the paper follows),
+ * and the window minimises the IMU factors plus the visual cost of ba_solve.
+ * The IMU frame is the base frame.  IMU terms are FP64 in both precisions.
+ * ------------------------------------------------------------------------- */
+
+/* Preintegrate the samples of n_factors keyframe intervals.  DEVICE arrays:
+ * sample_begin (n_factors + 1): interval f owns samples [sample_begin[f],
+ * sample_begin[f + 1]); gyro, accel (n_samples x 3): angular rate (rad/s) and
+ * specific force (m/s^2) of each sample, constant over dt seconds; bias_bar
+ * (n_factors x 6: b^a then b^w) the bias estimates to integrate at; preint
+ * (n_factors x BA_VI_PREINT_DOUBLES) out.  noise: HOST 4 densities sigma_g
+ * (rad/s/sqrt(Hz)), sigma_a (m/s^2/sqrt(Hz)), sigma_bg, sigma_ba (bias random
+ * walks) for the information of each factor.  An interval needs at least two
+ * samples: the covariance of one sample is singular, and an interval of fewer
+ * samples gets NaN information (a solve with it reports status 1, non-finite
+ * cost).  One thread per interval; allocates nothing.  Errors: INVALID_ARG. */
+ba_status ba_vi_preintegrate(int32_t n_factors, const int32_t* sample_begin, const double* gyro,
+                             const double* accel, double dt, const double* bias_bar, const double* noise,
+                             double* preint, void* stream);
+
+/* Workspace of ba_vi_solve (2 <= n_poses <= 24).  Errors: as ba_workspace_size,
+ * UNSUPPORTED for other pose counts. */
+ba_status ba_vi_workspace_size(ba_window w, const ba_settings* s, size_t* bytes);
+
+/* ba_solve of one window with the IMU factors between its consecutive poses
+ * (pose f and f + 1, factor f of preint, n_poses - 1 records from
+ * ba_vi_preintegrate).  gravity: HOST 3, world frame (m/s^2).  states: DEVICE
+ * n_poses x 9 (v, b^a, b^w), in/out; every state's velocity and biases are
+ * free (the window's fixed poses stay fixed).  Other arguments as ba_solve.
+ * Per attempt the IMU factors are linearised at the current state and their
+ * velocities and biases are eliminated onto the poses before the reduced
+ * camera system is solved.  Errors: as ba_solve, UNSUPPORTED (pose count). */
+ba_status ba_vi_solve(ba_window w, const ba_settings* s, const double* preint, const double* gravity,
+                      double* poses, double* points, double* states, const double* obs_uv, const double* obs_w,
+                      void* workspace, size_t ws_bytes, ba_report* report, ba_iter_trace* trace, void* stream);
 
 /* -------------------------------------------------------------------------
  * Sliding-window local map (paper Sec. 2.1: the frontend keeps the last N

@@ -21,6 +21,8 @@ from ._binding import (  # noqa: F401
     Batch,
     Rig,
     Settings,
+    REPORT_DTYPE,
+    VI_PREINT_DOUBLES,
     Window,
     adjoint,
     lib,
@@ -34,5 +36,8 @@ from ._binding import (  # noqa: F401
     solve,
     solve_batched,
     solve_noalloc,
+    vi_preintegrate,
+    vi_solve,
+    vi_workspace_size,
 )
 from .autograd import BASolve  # noqa: F401

@@ -22,6 +22,8 @@ BA_ERR_UNSUPPORTED = -5
 BA_ERR_STATE = -6
 
 
+# include/ba.h BA_VI_PREINT_DOUBLES
+VI_PREINT_DOUBLES = 320
 # include/ba.h BA_NOALLOC_SCRATCH_BYTES
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -112,6 +114,9 @@ def lib():
         L.ba_map_window.argtypes = [vp, ctypes.POINTER(vp)]
         L.ba_map_read.argtypes = [vp, vp, vp, vp, vp]
         L.ba_map_solve.argtypes = [vp, ctypes.POINTER(_Settings), vp, sz, vp, vp, vp]
+        L.ba_vi_preintegrate.argtypes = [i32, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp]
+        L.ba_vi_workspace_size.argtypes = [vp, ctypes.POINTER(_Settings), ctypes.POINTER(sz)]
+        L.ba_vi_solve.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
         L.ba_status_string.argtypes = [i32]
         L.ba_status_string.restype = ctypes.c_char_p
         L.ba_last_error.restype = ctypes.c_char_p
@@ -121,7 +126,7 @@ def lib():
                   "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate", "ba_graph_create", "ba_graph_info",
                   "ba_graph_plan_array", "ba_graph_workspace_size", "ba_pgo_solve", "ba_map_create",
                   "ba_map_add_keyframe", "ba_map_info", "ba_map_lists", "ba_map_arrays", "ba_map_window", "ba_map_read",
-                  "ba_map_solve"):
+                  "ba_map_solve", "ba_vi_preintegrate", "ba_vi_workspace_size", "ba_vi_solve"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -588,3 +593,42 @@ class Map:
             self.close()
         except Exception:
             pass
+
+
+def vi_preintegrate(sample_begin, gyro, accel, dt, bias_bar, noise, out=None, stream=None):
+    """Preintegrated IMU factors on the GPU: sample_begin (n + 1) int32, gyro and
+    accel (n_samples, 3), bias_bar (n, 6) float64 device tensors; noise: 4 floats.
+    Returns the (n, VI_PREINT_DOUBLES) float64 records."""
+    import torch
+    n = int(sample_begin.numel()) - 1
+    if out is None:
+        out = torch.empty((max(n, 0), VI_PREINT_DOUBLES), dtype=torch.float64, device=gyro.device)
+    nz = _host(noise, np.float64)
+    _check(lib().ba_vi_preintegrate(n, _ptr(sample_begin), _ptr(gyro), _ptr(accel), float(dt), _ptr(bias_bar),
+                                    nz.ctypes.data_as(ctypes.c_void_p), _ptr(out), _stream(stream)))
+    return out
+
+
+def vi_workspace_size(window: Window, settings: Settings) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().ba_vi_workspace_size(window.handle, ctypes.byref(settings.c()), ctypes.byref(n)))
+    return n.value
+
+
+def vi_solve(window: Window, settings: Settings, preint, gravity, poses, points, states, obs_uv, obs_w=None,
+             workspace=None, report=None, trace=None, stream=None):
+    """Visual-inertial solve of one window in place (poses, points, states
+    n_poses x 9: v, b^a, b^w).  Returns (report, trace, workspace)."""
+    import torch
+    dev = poses.device
+    need = vi_workspace_size(window, settings)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    if report is None:
+        report = torch.zeros(REPORT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    g = _host(gravity, np.float64)
+    _check(lib().ba_vi_solve(window.handle, ctypes.byref(settings.c()), _ptr(preint),
+                             g.ctypes.data_as(ctypes.c_void_p), _ptr(poses), _ptr(points), _ptr(states),
+                             _ptr(obs_uv), _ptr(obs_w), _ptr(workspace), workspace.numel(), _ptr(report),
+                             _ptr(trace), _stream(stream)))
+    return report, trace, workspace

@@ -41,6 +41,8 @@ def build(verbose: bool = False) -> str:
                                                           "-o", os.path.join(obj, "tri.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "pgo.hip"),
                                                           "-o", os.path.join(obj, "pgo.o")],
+        [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "vi.hip"),
+                                                          "-o", os.path.join(obj, "vi.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "map.hip"),
                                                           "-o", os.path.join(obj, "map.o")],
         [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "api.cpp"),
@@ -58,6 +60,7 @@ def build(verbose: bool = False) -> str:
                                    os.path.join(obj, "kernels.o"), os.path.join(obj, "pnp.o"),
                                    os.path.join(obj, "tri.o"), os.path.join(obj, "pgo.o"),
                                    os.path.join(obj, "pgo_plan.o"), os.path.join(obj, "map.o"),
+                                   os.path.join(obj, "vi.o"),
                                    os.path.join(obj, "api.o"),
                                    os.path.join(obj, "plan.o")])
     os.replace(tmp, OUT)

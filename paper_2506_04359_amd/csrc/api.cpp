@@ -21,6 +21,7 @@
 #include "pnp.hpp"
 #include "tri.hpp"
 #include "pgo.hpp"
+#include "vi.hpp"
 
 // Device scratch of ba_solve_noalloc: one copy per GPU the library runs on,
 // held until the process ends.  Host code never passes this name to a kernel
@@ -406,6 +407,10 @@ DevWork<Real> make_work(const Layout& L, void* ws, bool has_w) {
   K.part_cost_b = (double*)(m + L.cost_b);
   K.part_flag_a = (int32_t*)(m + L.flag_a);
   K.part_flag_b = (int32_t*)(m + L.flag_b);
+  K.vi_cost_a = nullptr;
+  K.vi_cost_b = nullptr;
+  K.vi_states = nullptr;
+  K.vi_states_b = nullptr;
   return K;
 }
 
@@ -492,8 +497,21 @@ ba_status ensure_side_stream(ba_batch_s* b, void* stream) {
 
 enum class Op { Solve, Adjoint, Timed };
 
+// Inputs of a visual-inertial solve (ba_vi_solve).
+struct ViInput {
+  const double* preint;
+  const double* gravity;   // host, 3
+  double* states;          // device, 9 per pose
+};
+
+// Workspace bytes of the VI records after the window solve's own layout.
+size_t vi_bytes(const ba_batch_s* b) {
+  const HostWindow& w = b->wins[0];
+  return align_up(sizeof(double) * (9 * (size_t)w.n_poses + 2 + vi_rec_doubles(w.n_poses, w.n_free)));
+}
+
 ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws, size_t ws_bytes,
-                 void* stream, bool has_w, double* stage_ms = nullptr) {
+                 void* stream, bool has_w, double* stage_ms = nullptr, const ViInput* vin = nullptr) {
   int which = 0;
   ba_status st = pick_config(b, s->precision, &which);
   if (st != BA_OK) return st;
@@ -501,7 +519,8 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   const size_t real = s->precision == BA_FP64 ? sizeof(double) : sizeof(float);
   const Layout L = layout(b, t, real);
   if (!ws) return set_error(BA_ERR_INVALID_ARG, "workspace is NULL");
-  if (ws_bytes < L.total) return set_error(BA_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  const size_t need = L.total + (vin ? vi_bytes(b) : 0);
+  if (ws_bytes < need) return set_error(BA_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
   if (((uintptr_t)ws) % 256 != 0) return set_error(BA_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if ((st = ensure_attrs()) != BA_OK) return st;
   LaunchArgs A;
@@ -546,8 +565,41 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   A.side_stream = use_side ? (void*)b->side : nullptr;
   A.ev_fork = b->ev_fork;
   A.ev_join = (void*)b->ev_join;
+  A.vi = nullptr;
+  // visual-inertial: the VI records after the solve's own workspace
+  ViArgs V{};
+  double* vi_base = vin ? (double*)((char*)ws + L.total) : nullptr;
+  if (vin) {
+    const HostWindow& w0 = b->wins[0];
+    V.win = t.win;
+    V.win_order = t.win_order;
+    V.free_slot = b->plan.free_slot;
+    V.poses = U.poses;
+    V.states = vin->states;
+    V.states_b = vi_base;
+    V.cost_a = vi_base + 9 * (size_t)w0.n_poses;
+    V.cost_b = V.cost_a + 1;
+    V.rec = V.cost_b + 1;
+    V.preint = vin->preint;
+    V.max_factors = w0.n_poses - 1;
+    for (int k = 0; k < 3; ++k) V.g[k] = vin->gravity[k];
+    A.vi = &V;
+  }
+  auto vi_work = [&](auto& K) {
+    if (!vin) return;
+    V.state = K.state;
+    V.poses_b = K.poses_b;
+    V.ssum = K.ssum;
+    V.dp = K.dp;
+    V.part_flag_a = K.part_flag_a;
+    K.vi_cost_a = V.cost_a;
+    K.vi_cost_b = V.cost_b;
+    K.vi_states = V.states;
+    K.vi_states_b = V.states_b;
+  };
   if (s->precision == BA_FP64) {
-    const DevWork<double> K = make_work<double>(L, ws, has_w);
+    DevWork<double> K = make_work<double>(L, ws, has_w);
+    vi_work(K);
     if (op == Op::Solve)
       e = t.tp == kTileLarge ? run_solve<double, kTileLarge>(A, K) : run_solve<double, kTileSmall>(A, K);
     else if (op == Op::Timed)
@@ -556,7 +608,8 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
     else
       e = t.tp == kTileLarge ? run_adjoint<double, kTileLarge>(A, K) : run_adjoint<double, kTileSmall>(A, K);
   } else {
-    const DevWork<float> K = make_work<float>(L, ws, has_w);
+    DevWork<float> K = make_work<float>(L, ws, has_w);
+    vi_work(K);
     if (op == Op::Solve)
       e = t.tp == kTileLarge ? run_solve<float, kTileLarge>(A, K) : run_solve<float, kTileSmall>(A, K);
     else if (op == Op::Timed)
@@ -1032,6 +1085,65 @@ ba_status ba_solve_noalloc(ba_window w, const ba_settings* s, double* poses, dou
   if ((st = scratch_on(w->batch->device, &ptr)) != BA_OK) return st;
   return ba_solve_batched(w->batch, s, poses, points, obs_uv, obs_w, ptr,
                           (size_t)BA_NOALLOC_SCRATCH_BYTES, report, trace, stream);
+}
+
+ba_status ba_vi_preintegrate(int32_t n_factors, const int32_t* sample_begin, const double* gyro,
+                             const double* accel, double dt, const double* bias_bar, const double* noise,
+                             double* preint, void* stream) {
+  if (n_factors < 0) return set_error(BA_ERR_INVALID_ARG, "negative factor count");
+  if (n_factors == 0) return BA_OK;
+  if (!sample_begin || !gyro || !accel || !bias_bar || !noise || !preint)
+    return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  if (!(dt > 0) || !std::isfinite(dt)) return set_error(BA_ERR_INVALID_ARG, "dt must be positive");
+  for (int k = 0; k < 4; ++k)
+    if (!(noise[k] > 0) || !std::isfinite(noise[k]))
+      return set_error(BA_ERR_INVALID_ARG, "noise densities must be positive");
+  const hipError_t e = launch_vi_preint(n_factors, sample_begin, gyro, accel, dt, bias_bar, noise, preint,
+                                        (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "preintegration launch");
+  return BA_OK;
+}
+
+ba_status ba_vi_workspace_size(ba_window w, const ba_settings* s, size_t* bytes) {
+  if (!bytes) return set_error(BA_ERR_INVALID_ARG, "bytes is NULL");
+  if (!w) return set_error(BA_ERR_INVALID_ARG, "window is NULL");
+  if (!w->batch) return set_error(BA_ERR_STATE, "host-only window");
+  const HostWindow& h = w->batch->wins[0];
+  if (h.n_poses < 2 || h.n_poses > kViMaxStates)
+    return set_error(BA_ERR_UNSUPPORTED, "visual-inertial windows hold 2 to 24 keyframes");
+  size_t base = 0;
+  ba_status st = ba_workspace_size(w, nullptr, s, &base);
+  if (st != BA_OK) return st;
+  *bytes = base + vi_bytes(w->batch);
+  return BA_OK;
+}
+
+ba_status ba_vi_solve(ba_window w, const ba_settings* s, const double* preint, const double* gravity,
+                      double* poses, double* points, double* states, const double* obs_uv, const double* obs_w,
+                      void* workspace, size_t ws_bytes, ba_report* report, ba_iter_trace* trace, void* stream) {
+  if (!w) return set_error(BA_ERR_INVALID_ARG, "window is NULL");
+  if (!w->batch) return set_error(BA_ERR_STATE, "host-only window cannot be solved");
+  ba_status st = check_settings(s);
+  if (st != BA_OK) return st;
+  ba_batch_s* b = w->batch;
+  const HostWindow& h = b->wins[0];
+  if (h.n_poses < 2 || h.n_poses > kViMaxStates)
+    return set_error(BA_ERR_UNSUPPORTED, "visual-inertial windows hold 2 to 24 keyframes");
+  if (!preint || !gravity || !states || !poses || (!points && b->n_points > 0) || (!obs_uv && b->n_obs > 0) ||
+      !report)
+    return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(gravity[k])) return set_error(BA_ERR_INVALID_ARG, "non-finite gravity");
+  DevUser U{};
+  U.poses = poses;
+  U.points = points;
+  U.obs_uv = obs_uv;
+  U.obs_w = obs_w;
+  U.reports = report;
+  U.traces = trace;
+  ViInput vin{preint, gravity, states};
+  std::lock_guard<std::mutex> lk(b->mu);
+  return launch(b, s, Op::Solve, U, workspace, ws_bytes, stream, obs_w != nullptr, nullptr, &vin);
 }
 
 ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double* poses,

@@ -1,12 +1,30 @@
 // Structures shared by the host launcher and the gfx950 kernels.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 #include "../../include/ba.h"
 #include "plan.hpp"
 
 namespace ba {
+
+// Upper block (i <= j) of an nf x nf block matrix, row-major over the triangle.
+__host__ __device__ __forceinline__ int blk_index(int i, int j, int nf) {
+  return i * nf - (i * (i - 1)) / 2 + (j - i);
+}
+
+// The pair (i, j), i <= j, of upper block e of an n x n block matrix.
+__device__ __forceinline__ void upper_pair(int e, int n, int& i, int& j) {
+  const float b = 2.0f * n + 1.0f;
+  int r = (int)((b - sqrtf(b * b - 8.0f * e)) * 0.5f);
+  r = r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
+  while (r > 0 && r * n - r * (r - 1) / 2 > e) --r;
+  while (r + 1 < n && (r + 1) * n - (r + 1) * r / 2 <= e) ++r;
+  i = r;
+  j = e - (r * n - r * (r - 1) / 2) + r;
+}
 
 // Per-window structure, uploaded once per plan.
 struct WinDev {
@@ -70,6 +88,13 @@ struct DevWork {
   double* part_cost_b;      // per chunk: sum w rho at the candidate
   int32_t* part_flag_a;     // per chunk: a landmark block was not positive definite
   int32_t* part_flag_b;     // per chunk: a candidate depth <= min_depth
+  // visual-inertial solves only (NULL otherwise): per window the IMU cost at
+  // the current state and at the candidate; the velocities and biases (user
+  // buffer and workspace buffer, 9 per pose)
+  double* vi_cost_a;
+  double* vi_cost_b;
+  double* vi_states;
+  double* vi_states_b;
 };
 
 struct DevUser {
@@ -138,6 +163,8 @@ struct LaunchArgs {
   void* side_stream;
   void* ev_fork;
   void* ev_join;
+  // visual-inertial solves: the IMU stages' arguments (const ViArgs*), or NULL
+  const void* vi;
 };
 
 }  // namespace ba

@@ -34,6 +34,7 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "vi.hpp"
 #include "geometry.hpp"
 
 namespace ba {
@@ -50,10 +51,6 @@ __device__ __forceinline__ int xcd_chunk(int b, int G) {
   return x * q + (x < r ? x : r) + k;
 }
 
-__device__ __forceinline__ int blk_index(int i, int j, int nf) {
-  // upper block (i <= j) of an nf x nf block matrix, row-major over the triangle
-  return i * nf - (i * (i - 1)) / 2 + (j - i);
-}
 
 // Block accumulators of one pose-landmark pair.
 template <typename Real>
@@ -984,15 +981,6 @@ __device__ __forceinline__ void factor_diag(double a, double* D, double* inv, in
 
 // Pair (i, j), i <= j < n, of index e in the row-major upper triangle of an
 // n x n grid (row i starts at i*n - i*(i-1)/2).
-__device__ __forceinline__ void upper_pair(int e, int n, int& i, int& j) {
-  const float b = 2.0f * n + 1.0f;
-  int r = (int)((b - sqrtf(b * b - 8.0f * e)) * 0.5f);
-  r = r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
-  while (r > 0 && r * n - r * (r - 1) / 2 > e) --r;
-  while (r + 1 < n && (r + 1) * n - (r + 1) * r / 2 <= e) ++r;
-  i = r;
-  j = e - (r * n - r * (r - 1) / 2) + r;
-}
 
 // Sum of a window's chunk partials in FP64 (grid: windows x slices).  The
 // workgroup's 256 threads form G = W.sum_groups groups of 256 / G entry
@@ -1091,6 +1079,7 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
       sFail[0] = f;
       if (need_cost) {
         F *= 0.5;
+        if (K.vi_cost_a) F += K.vi_cost_a[wi];
         st.cost = F;
         st.init_cost = F;
         if (!isfinite(F)) st.status = 1;
@@ -1572,6 +1561,7 @@ __global__ void k_accept(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U, DevS
       st.depth_rejects++;
     } else {
       F *= 0.5;
+      if (K.vi_cost_b) F += K.vi_cost_b[wi];
       tr.cand_cost = F;
       st.cand_cost = F;
       accept = F < st.cost;
@@ -1602,6 +1592,9 @@ __global__ void k_finalize(DevPlan P, DevWork<Real> K, DevUser U, int need_cost)
   if (st.cur == 1) {
     for (int k = threadIdx.x; k < 12 * W.n_poses; k += blockDim.x)
       U.poses[12 * W.pose_off + k] = K.poses_b[12 * W.pose_off + k];
+    if (K.vi_states)
+      for (int k = threadIdx.x; k < 9 * W.n_poses; k += blockDim.x)
+        K.vi_states[9 * W.pose_off + k] = K.vi_states_b[9 * W.pose_off + k];
     for (int k = threadIdx.x; k < 3 * W.n_points; k += blockDim.x)
       U.points[3 * W.point_off + k] = K.points_b[3 * W.point_off + k];
   }
@@ -1735,8 +1728,10 @@ void launch_stages(const LaunchArgs& A, const DevWork<Real>& K, int it, int wb, 
   if (nwin <= 0) return;
   const size_t lb = pass_b_lds<Real, TP>(), lr = reduce_lds(nf);
   hipLaunchKernelGGL(k_sum<Real>, dim3(nwin, slices), dim3(256), 0, st, A.plan, A.tiles, K, wb);
+  if (!ADJ && A.vi) launch_vi_lin(*static_cast<const ViArgs*>(A.vi), wb, nwin, st);
   hipLaunchKernelGGL((k_reduce<Real, kReduceThreads, ADJ>), dim3(nwin), dim3(kReduceThreads), lr, st, A.plan, A.tiles,
                      K, A.user, A.settings, it, wb);
+  if (!ADJ && A.vi) launch_vi_cand(*static_cast<const ViArgs*>(A.vi), wb, nwin, st);
   if (nch > 0)
     hipLaunchKernelGGL((k_pass_b<Real, TP, ADJ>), dim3(nch), dim3(TP), lb, st, A.plan, A.tiles, K, A.user, A.settings,
                        it, cb);
