@@ -488,10 +488,16 @@ static_assert(6 % kRowsPerUnit == 0, "rows per unit must divide 6");
 constexpr int kPoseSums = 33;
 
 // Upper-triangle entry e (0..20) of a 6x6 block -> row-major offset r*6+c.
-__constant__ int kUpperOff[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
-                                  21, 22, 23, 28, 29, 35};
 constexpr int kUpperOffC[21] = {0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 14, 15, 16, 17,
                                 21, 22, 23, 28, 29, 35};
+
+// The same offset for a run-time e (no table: an indexed table in constant
+// memory would cost a memory access): row r has 6 - r entries.
+__device__ __forceinline__ int upper_off(int e) {
+  const int r = (e >= 6) + (e >= 11) + (e >= 15) + (e >= 18) + (e >= 20);
+  const int start = 6 * r - r * (r - 1) / 2;
+  return 7 * r + (e - start);
+}
 
 // Adds component k of a pose's run sum into the partial: U - Z sigma Z^T
 // (upper triangle of the diagonal block), reduced rhs, diag(U) (LM only).
@@ -499,7 +505,7 @@ template <typename Real, bool ADJ>
 __device__ __forceinline__ void pose_sum_add1(Real* sS, Real* sB, Real* sD, int nf, int s, int k,
                                               Real x) {
   if (k < 21) {
-    sS[kBS * blk_index(s, s, nf) + kUpperOff[k]] += x;
+    sS[kBS * blk_index(s, s, nf) + upper_off(k)] += x;
   } else if (k < 27) {
     sB[6 * s + (k - 21)] += x;
   } else if (!ADJ) {
@@ -599,12 +605,21 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   const int4* trec = reinterpret_cast<const int4*>(T.tile_rec);
   const int4* prec = reinterpret_cast<const int4*>(T.pair_rec);
   const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
-  int4 ta = make_int4(0, 0, 0, 0), tb = make_int4(0, 0, 0, 0);
-  int4 rec = make_int4(0, 0, 0, -1);
+  // The global data of a tile is fetched one tile ahead, in three steps:
+  // tile records two tiles ahead, pair records one tile ahead (both issued
+  // during tile t - 1), and the pairs' points and first observations at the
+  // start of tile t - 1 (their pair records are there by then).
+  int4 ta = make_int4(0, 0, 0, 0), tb = make_int4(0, 0, 0, 0), nta = ta, ntb = tb;
+  int4 rec = make_int4(0, 0, 0, -1), nrec = rec;
   if (t0 < t1) {
     ta = trec[2 * t0];
     tb = trec[2 * t0 + 1];
     if (tid < ta.y) rec = prec[ta.x + tid];
+  }
+  if (t0 + 1 < t1) {
+    nta = trec[2 * (t0 + 1)];
+    ntb = trec[2 * (t0 + 1) + 1];
+    if (tid < nta.y) nrec = prec[nta.x + tid];
   }
 
   for (int k = tid; k < W.n_cams * 16; k += TP) sCam[k] = P.cam[16 * W.cam_off + k];
@@ -614,8 +629,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   if (tid == 0) sFlag[0] = 0;
   __syncthreads();
 
-  // a pair's point and first observation: fetched for the next tile during
-  // the current tile's Schur phase, so their memory latency is hidden
+  // a pair's point and first observation
   double px = 0, py = 0, pz = 0;
   Real du0 = 0, dv0 = 0, wo0 = 1;
   int cam0 = 0;
@@ -637,12 +651,17 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     const int p0 = ta.x, nP = ta.y, l0 = ta.z, nL = ta.w;
     const int lw0 = tb.x, nseg = tb.y, nprod = tb.z;
     const int nwords = nseg + (nprod + 1) / 2;
-    // next tile's record, in flight during this tile
-    int4 nta = ta, ntb = tb;
-    if (t + 1 < t1) {
-      nta = trec[2 * (t + 1)];
-      ntb = trec[2 * (t + 1) + 1];
+    // in flight during this tile: the tile record after the next one, and
+    // the next tile's pairs' points and first observations
+    int4 nnta = nta, nntb = ntb;
+    if (t + 2 < t1) {
+      nnta = trec[2 * (t + 2)];
+      nntb = trec[2 * (t + 2) + 1];
     }
+    double npx = 0, npy = 0, npz = 0;
+    Real ndu = 0, ndv = 0, nwo = 1;
+    int ncam = 0;
+    if (t + 1 < t1 && tid < nta.y) fetch_pair(nrec, npx, npy, npz, ndu, ndv, nwo, ncam);
     // this tile's pair: its pose (point and first observation are here
     // already), and the tile's list words
     const int q = (rec.z >> 8) & 255, pose = rec.z & 255, nobs = rec.z >> 16;
@@ -751,9 +770,10 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
       }
     }
     __syncthreads();
-    // next tile's pair records (its tile record has arrived by now)
-    int4 nrec = make_int4(0, 0, 0, -1);
-    if (t + 1 < t1 && tid < nta.y) nrec = prec[nta.x + tid];
+    // the pair records of the tile after the next one (its tile record has
+    // arrived by now)
+    int4 nnrec = make_int4(0, 0, 0, -1);
+    if (t + 2 < t1 && tid < nnta.y) nnrec = prec[nnta.x + tid];
 
     // ---- phase 3: Z_bar = W L^-T |D|^-1/2 of this pair, its reduced rhs and
     // its own diagonal Schur term U - Z_bar sigma Z_bar^T (the products of a
@@ -824,24 +844,36 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
       }
     }
     __syncthreads();
-    // edge runs of the waves, in wave order, one thread per component (the
-    // targets are diagonal blocks, rhs and diag(U); phase 4 below writes only
+    // edge runs of the waves, one thread per component (the targets are
+    // diagonal blocks, rhs and diag(U); phase 4 below writes only
     // off-diagonal blocks).  The last wave does it: it gets the shortest Schur
-    // units of every round.
+    // units of every round.  A run spanning waves leaves its pieces in
+    // consecutive edge slots: they are summed in wave order in registers and
+    // added to the partial once.
     if (tid >= TP - kPoseSums) {
       const int k = tid - (TP - kPoseSums);
+      int sl[2 * NW];
+      Real x[2 * NW];
 #pragma unroll
       for (int b = 0; b < 2 * NW; ++b) {
-        const int sb = sBndSlot[b];
-        if (sb >= 0) pose_sum_add1<Real, ADJ>(sS, sB, sD, nf, sb, k, sBnd[b * kPoseSums + k]);
+        sl[b] = sBndSlot[b];
+        x[b] = sBnd[b * kPoseSums + k];
       }
+      int cur = -1;
+      Real acc = (Real)0;
+#pragma unroll
+      for (int b = 0; b < 2 * NW; ++b) {
+        if (sl[b] < 0) continue;
+        if (sl[b] == cur) {
+          acc += x[b];
+        } else {
+          if (cur >= 0) pose_sum_add1<Real, ADJ>(sS, sB, sD, nf, cur, k, acc);
+          cur = sl[b];
+          acc = x[b];
+        }
+      }
+      if (cur >= 0) pose_sum_add1<Real, ADJ>(sS, sB, sD, nf, cur, k, acc);
     }
-
-    // next tile's pair data, in flight during the Schur units
-    double npx = 0, npy = 0, npz = 0;
-    Real ndu = 0, ndv = 0, nwo = 1;
-    int ncam = 0;
-    if (t + 1 < t1 && tid < nta.y) fetch_pair(nrec, npx, npy, npz, ndu, ndv, nwo, ncam);
 
     // ---- phase 4: Schur blocks.  Unit (segment, rows r0..r0+kRowsPerUnit-1)
     // owns those rows of one off-diagonal target block for this tile: it sums
@@ -922,7 +954,10 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     __syncthreads();
     ta = nta;
     tb = ntb;
+    nta = nnta;
+    ntb = nntb;
     rec = nrec;
+    nrec = nnrec;
     px = npx;
     py = npy;
     pz = npz;
