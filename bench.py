@@ -240,7 +240,7 @@ def main():
         big = torch.empty(batch.workspace_size(s_mixed) + 256, dtype=torch.uint8, device=dev)
         chunk = batch.autotune(s_mixed, P, L, uv, None, big)
         del big
-        log(f"autotuned chunk_obs = {chunk}")
+        log(f"autotuned launch shape: {batch.get_launch()}")
     ws_bytes = batch.workspace_size(s_mixed)
     work = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
@@ -299,7 +299,7 @@ def main():
         "config": {"workload": bagen.WORKLOAD_NAMES[3], "windows": N_WINDOWS,
                    "observations": int(n_obs.sum()), "landmarks": int(sum(w.n_points for w in ws)),
                    "lm_attempts_per_window": ITERS, "precision": "mixed (FP32 bulk, FP64 Cholesky)",
-                   "graph_captured": True, "chunk_obs": chunk},
+                   "graph_captured": True, "chunk_obs": chunk, "launch": batch.get_launch()},
         "obs_jacobians_per_s": obs_jac,
         "stage_ms_per_attempt": {k: v / ITERS for k, v in stages.items()},
     }

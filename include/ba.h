@@ -246,16 +246,37 @@ ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double
                      double* grad_w, void* workspace, size_t ws_bytes, ba_report* reports,
                      void* stream);
 
-/* Launch-shape tuning.  ba_autotune times the candidate shapes of the batched
- * Schur kernel on this plan (synchronising the stream; not capturable), keeps
- * the fastest in the plan and returns it; ba_set_launch sets one directly.
- * Shape = observations per work item (chunk target).  Results are cached per
- * (device name, precision, size bucket) in the file named by $BA_TUNE_CACHE
- * when that variable is set. */
+/* Launch shape of a plan's batched solve (the a11 schedule: one launch per
+ * stage and size class).  Defaults: chunk_obs from the plan's size,
+ * tile_pairs 0, every class_chunk_mult 1, class_streams 1. */
+typedef struct {
+  int32_t chunk_obs;            /* target observations per work item, 512..65536 */
+  int32_t tile_pairs;           /* pairs per tile: 0 = 256 when its LDS fits, else 64; or 64 / 256 */
+  int32_t class_chunk_mult[4];  /* per size class (up to 8, 16, 23, 32 free poses): work items of
+                                   about class_chunk_mult x chunk_obs observations, 1..4 */
+  int32_t class_streams;        /* 1: the size classes run as concurrent chains on two side
+                                   streams; 0: every launch on the call's stream */
+} ba_launch_config;
+
+/* Launch-shape tuning.  ba_autotune times candidate shapes of the batched
+ * solve on this plan (3-attempt solves, best of two after a warm-up;
+ * synchronises the stream; not capturable) by coordinate descent: chunk_obs
+ * over 1024..16384, then 64-pair tiles, then four per-class multiplier sets,
+ * then all classes on one stream; it keeps the fastest in the plan and
+ * returns its chunk_obs (ba_get_launch gives the whole shape).  The state
+ * arrays are modified: pass scratch copies.  Shapes whose workspace exceeds
+ * ws_bytes are skipped.  Results are cached per (device name, precision,
+ * window count, size bucket, largest window, windows and size bucket of each
+ * size class) in the file named by $BA_TUNE_CACHE when that variable is set.
+ * ba_set_launch sets chunk_obs (the other fields kept), ba_set_launch_config
+ * the whole shape (INVALID_ARG outside the ranges above, before any change;
+ * on a failed table upload the previous shape is rebuilt). */
 ba_status ba_autotune(ba_batch b, const ba_settings* s, double* poses, double* points,
                       const double* obs_uv, const double* obs_w, void* workspace,
                       size_t ws_bytes, void* stream, int32_t* chosen_chunk_obs);
 ba_status ba_set_launch(ba_batch b, int32_t chunk_obs);
+ba_status ba_set_launch_config(ba_batch b, const ba_launch_config* cfg);
+ba_status ba_get_launch(ba_batch b, ba_launch_config* cfg);
 
 /* Diagnostics: the same solve as ba_solve_batched with HIP events recorded on
  * `stream` between the launches; writes the summed device time in ms of each

@@ -42,6 +42,11 @@ class _Settings(ctypes.Structure):
                 ("min_depth", ctypes.c_double)]
 
 
+class _LaunchConfig(ctypes.Structure):   # include/ba.h ba_launch_config
+    _fields_ = [("chunk_obs", ctypes.c_int32), ("tile_pairs", ctypes.c_int32),
+                ("class_chunk_mult", ctypes.c_int32 * 4), ("class_streams", ctypes.c_int32)]
+
+
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("n_poses", ctypes.c_int32), ("n_points", ctypes.c_int32),
                 ("n_cams", ctypes.c_int32), ("n_free", ctypes.c_int32),
@@ -87,6 +92,8 @@ def lib():
         L.ba_autotune.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
                                   ctypes.POINTER(i32)]
         L.ba_set_launch.argtypes = [vp, i32]
+        L.ba_set_launch_config.argtypes = [vp, ctypes.POINTER(_LaunchConfig)]
+        L.ba_get_launch.argtypes = [vp, ctypes.POINTER(_LaunchConfig)]
         L.ba_profile_stages.argtypes = [vp, ctypes.POINTER(_Settings), vp, vp, vp, vp, vp, sz, vp,
                                         vp, ctypes.POINTER(ctypes.c_double)]
         L.ba_rig_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
@@ -122,7 +129,8 @@ def lib():
         L.ba_last_error.restype = ctypes.c_char_p
         for f in ("ba_window_create", "ba_window_info", "ba_window_order", "ba_batch_create",
                   "ba_batch_info", "ba_workspace_size", "ba_solve", "ba_solve_noalloc", "ba_solve_batched",
-                  "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_profile_stages",
+                  "ba_adjoint", "ba_autotune", "ba_set_launch", "ba_set_launch_config", "ba_get_launch",
+                  "ba_profile_stages",
                   "ba_rig_create", "ba_rig_set_waves_per_frame", "ba_pnp_solve", "ba_triangulate", "ba_graph_create", "ba_graph_info",
                   "ba_graph_plan_array", "ba_graph_workspace_size", "ba_pgo_solve", "ba_map_create",
                   "ba_map_add_keyframe", "ba_map_info", "ba_map_lists", "ba_map_arrays", "ba_map_window", "ba_map_read",
@@ -266,6 +274,19 @@ class Batch:
 
     def set_launch(self, chunk_obs: int):
         _check(lib().ba_set_launch(self._h, int(chunk_obs)))
+
+    def get_launch(self) -> dict:
+        """The plan's launch shape (include/ba.h ba_launch_config) as a dict."""
+        c = _LaunchConfig()
+        _check(lib().ba_get_launch(self._h, ctypes.byref(c)))
+        return dict(chunk_obs=c.chunk_obs, tile_pairs=c.tile_pairs, class_chunk_mult=list(c.class_chunk_mult),
+                    class_streams=c.class_streams)
+
+    def set_launch_config(self, chunk_obs: int, tile_pairs: int = 0, class_chunk_mult=(1, 1, 1, 1),
+                          class_streams: int = 1):
+        c = _LaunchConfig(int(chunk_obs), int(tile_pairs), (ctypes.c_int32 * 4)(*[int(m) for m in class_chunk_mult]),
+                          int(class_streams))
+        _check(lib().ba_set_launch_config(self._h, ctypes.byref(c)))
 
     def autotune(self, settings, poses, points, obs_uv, obs_w, workspace, stream=None) -> int:
         c = ctypes.c_int32()

@@ -111,7 +111,11 @@ struct ba_batch_s {
   void* mem = nullptr;   // plan arrays
   DevPlan plan{};
   DeviceTables tables[2];   // [0]: small tiles, [1]: large tiles
+  // launch shape (ba_launch_config)
   int chunk_obs = 4096;
+  int tile_pairs = 0;                      // 0: the largest tiles whose LDS fits
+  int class_mult[kClasses] = {1, 1, 1, 1};  // work-item size per class, in chunk_obs
+  int class_streams = 1;                   // size classes as concurrent chains
   // Set by the first launch made under stream capture: a graph may then hold
   // the launch tables' device pointers in its kernel arguments, so tables
   // replaced by ba_set_launch / ba_autotune are kept (in `retired`) until the
@@ -154,7 +158,7 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   std::vector<const HostWindow*> ws;
   for (auto& w : b->wins) ws.push_back(&w);
   LaunchTables t;
-  build_tiles(ws, tp, chunk_obs, t);
+  build_tiles(ws, tp, chunk_obs, t, b->class_mult);
   // per-window records with this table's chunk ranges
   std::vector<WinDev> wd(b->wins.size());
   int32_t po = 0, lo = 0, co = 0, oo = 0, pa = 0, so = 0;
@@ -352,9 +356,19 @@ ba_status pick_config(const ba_batch_s* b, int precision, int* which) {
                           : (t.tp == kTileLarge ? pass_b_lds<float, kTileLarge>() : pass_b_lds<float, kTileSmall>());
     return la <= kLdsLimit && lb <= kLdsLimit;
   };
-  if (fits(1)) *which = 1;
-  else if (fits(0)) *which = 0;
-  else return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
+  if (b->tile_pairs == kTileSmall) {
+    if (!fits(0)) return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
+    *which = 0;
+  } else if (b->tile_pairs == kTileLarge) {
+    if (!fits(1)) return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS with 256-pair tiles");
+    *which = 1;
+  } else if (fits(1)) {
+    *which = 1;
+  } else if (fits(0)) {
+    *which = 0;
+  } else {
+    return set_error(BA_ERR_UNSUPPORTED, "window too large for LDS");
+  }
   if (reduce_lds(nf) > kLdsLimit) return set_error(BA_ERR_UNSUPPORTED, "reduced system too large for LDS");
   return BA_OK;
 }
@@ -548,12 +562,12 @@ ba_status launch(ba_batch_s* b, const ba_settings* s, Op op, DevUser U, void* ws
   hipError_t e = hipStreamGetCaptureInfo((hipStream_t)stream, &cs, &cap_id);
   if (e != hipSuccess) return hip_fail(e, "hipStreamGetCaptureInfo");
   if (cs != hipStreamCaptureStatusNone) b->captured = true;
-  if (n_classes >= 2 && (st = ensure_side_stream(b, stream)) != BA_OK) return st;
+  if (n_classes >= 2 && b->class_streams && (st = ensure_side_stream(b, stream)) != BA_OK) return st;
   // The side streams join a capture of `stream` through the fork event and
   // stay in it until that capture ends.  While they belong to another capture
   // (a call on another stream of this plan is being captured) the call runs
   // every class on `stream`, so that nothing is recorded into a foreign graph.
-  bool use_side = b->have_side;
+  bool use_side = b->have_side && b->class_streams;
   for (int k = 0; k < kSideStreams && use_side; ++k) {
     hipStreamCaptureStatus ss = hipStreamCaptureStatusNone;
     unsigned long long sid = 0;
@@ -1192,14 +1206,51 @@ ba_status ba_profile_stages(ba_batch b, const ba_settings* s, double* poses, dou
 }
 
 ba_status ba_set_launch(ba_batch b, int32_t chunk_obs) {
-  if (!b || chunk_obs < kChunkMin || chunk_obs > kChunkMax)
-    return set_error(BA_ERR_INVALID_ARG, "chunk_obs out of range");
+  if (!b) return set_error(BA_ERR_INVALID_ARG, "batch is NULL");
+  ba_launch_config c;
+  ba_status s = ba_get_launch(b, &c);
+  if (s != BA_OK) return s;
+  c.chunk_obs = chunk_obs;
+  return ba_set_launch_config(b, &c);
+}
+
+ba_status ba_get_launch(ba_batch b, ba_launch_config* cfg) {
+  if (!b || !cfg) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(b->mu);
-  ba_status s = upload_tables(b, 0, kTileSmall, chunk_obs);
-  if (s != BA_OK) return s;
-  s = upload_tables(b, 1, kTileLarge, chunk_obs);
-  if (s != BA_OK) return s;
-  b->chunk_obs = chunk_obs;
+  cfg->chunk_obs = b->chunk_obs;
+  cfg->tile_pairs = b->tile_pairs;
+  for (int c = 0; c < kClasses; ++c) cfg->class_chunk_mult[c] = b->class_mult[c];
+  cfg->class_streams = b->class_streams;
+  return BA_OK;
+}
+
+ba_status ba_set_launch_config(ba_batch b, const ba_launch_config* cfg) {
+  if (!b || !cfg) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
+  if (cfg->chunk_obs < kChunkMin || cfg->chunk_obs > kChunkMax)
+    return set_error(BA_ERR_INVALID_ARG, "chunk_obs out of range");
+  if (cfg->tile_pairs != 0 && cfg->tile_pairs != kTileSmall && cfg->tile_pairs != kTileLarge)
+    return set_error(BA_ERR_INVALID_ARG, "tile_pairs must be 0, 64 or 256");
+  for (int c = 0; c < kClasses; ++c)
+    if (cfg->class_chunk_mult[c] < 1 || cfg->class_chunk_mult[c] > 4)
+      return set_error(BA_ERR_INVALID_ARG, "class_chunk_mult out of range (1..4)");
+  if (cfg->class_streams != 0 && cfg->class_streams != 1)
+    return set_error(BA_ERR_INVALID_ARG, "class_streams must be 0 or 1");
+  std::lock_guard<std::mutex> lk(b->mu);
+  const int old_mult[kClasses] = {b->class_mult[0], b->class_mult[1], b->class_mult[2], b->class_mult[3]};
+  const int old_tp = b->tile_pairs;
+  for (int c = 0; c < kClasses; ++c) b->class_mult[c] = cfg->class_chunk_mult[c];
+  b->tile_pairs = cfg->tile_pairs;
+  ba_status s = upload_tables(b, 0, kTileSmall, cfg->chunk_obs);
+  if (s == BA_OK) s = upload_tables(b, 1, kTileLarge, cfg->chunk_obs);
+  if (s != BA_OK) {   // put the previous shape back (best effort: this only fails on OOM)
+    for (int c = 0; c < kClasses; ++c) b->class_mult[c] = old_mult[c];
+    b->tile_pairs = old_tp;
+    (void)upload_tables(b, 0, kTileSmall, b->chunk_obs);
+    (void)upload_tables(b, 1, kTileLarge, b->chunk_obs);
+    return s;
+  }
+  b->chunk_obs = cfg->chunk_obs;
+  b->class_streams = cfg->class_streams;
   return BA_OK;
 }
 
@@ -1210,74 +1261,131 @@ ba_status ba_autotune(ba_batch b, const ba_settings* s, double* poses, double* p
   ba_status st = check_settings(s);
   if (st != BA_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
-  // cache lookup
+  // cache key: device, precision, window count, size bucket, largest window
+  // and the class mix (windows and observation bucket of each size class)
   hipDeviceProp_t prop;
   hipError_t e = hipGetDeviceProperties(&prop, b->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  int bucket = 0;
-  for (int64_t n = b->n_obs; n > 1; n >>= 1) ++bucket;
+  auto bucket_of = [](int64_t n) {
+    int k = 0;
+    for (; n > 1; n >>= 1) ++k;
+    return k;
+  };
+  int64_t cls_win[kClasses] = {0, 0, 0, 0}, cls_obs[kClasses] = {0, 0, 0, 0};
+  for (const HostWindow& w : b->wins) {
+    ++cls_win[size_class(w.n_free)];
+    cls_obs[size_class(w.n_free)] += w.n_obs;
+  }
   std::ostringstream keyss;
-  keyss << prop.gcnArchName << "|" << s->precision << "|" << b->wins.size() << "|" << bucket << "|" << b->max_nf;
+  keyss << prop.gcnArchName << "|" << s->precision << "|" << b->wins.size() << "|" << bucket_of(b->n_obs) << "|"
+        << b->max_nf;
+  for (int c = 0; c < kClasses; ++c) keyss << "|" << cls_win[c] << ":" << bucket_of(cls_obs[c]);
   const std::string key = keyss.str();
   const char* cache = std::getenv("BA_TUNE_CACHE");
   if (cache) {
     std::ifstream in(cache);
-    std::string k;
-    int v;
-    while (in >> k >> v)
-      if (k == key && v >= kChunkMin && v <= kChunkMax) {
-        if ((st = ba_set_launch(b, v)) != BA_OK) return st;
-        if (chosen_chunk_obs) *chosen_chunk_obs = v;
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      ba_launch_config c{};
+      if (!(ls >> k >> c.chunk_obs >> c.tile_pairs >> c.class_chunk_mult[0] >> c.class_chunk_mult[1] >>
+            c.class_chunk_mult[2] >> c.class_chunk_mult[3] >> c.class_streams))
+        continue;
+      if (k != key) continue;
+      if (ba_set_launch_config(b, &c) == BA_OK) {
+        if (chosen_chunk_obs) *chosen_chunk_obs = c.chunk_obs;
         return BA_OK;
       }
+    }
   }
-  // The timed runs solve a copy-free short problem: the state arrays are
-  // modified, so the caller passes scratch copies.
+  // The timed runs solve a short problem (at most 3 attempts) in place: the
+  // caller passes scratch copies of the state.
   ba_settings probe = *s;
   probe.max_iters = std::min(s->max_iters, 3);
   if (probe.max_iters < 1) probe.max_iters = 1;
   ba_report* reports = nullptr;
   e = hipMalloc(&reports, sizeof(ba_report) * b->wins.size());
   if (e != hipSuccess) return set_error(BA_ERR_OOM, "autotune reports");
-  const int cands[] = {1024, 2048, 4096, 8192, 16384};
-  float best_ms = 1e30f;
-  int best = b->chunk_obs;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  for (int c : cands) {
-    if ((st = ba_set_launch(b, c)) != BA_OK) break;
+  // time one configuration: best of two runs after one warm-up; +inf when it
+  // does not fit (LDS or workspace)
+  auto time_cfg = [&](const ba_launch_config& c, float* ms_out) -> ba_status {
+    *ms_out = 1e30f;
+    ba_status r = ba_set_launch_config(b, &c);
+    if (r == BA_ERR_UNSUPPORTED || r == BA_ERR_INVALID_ARG) return BA_OK;
+    if (r != BA_OK) return r;
+    int which = 0;
+    if (pick_config(b, probe.precision, &which) != BA_OK) return BA_OK;
     size_t need = 0;
-    if ((st = ba_workspace_size(nullptr, b, &probe, &need)) != BA_OK) break;
-    if (need > ws_bytes) continue;
-    float ms_best = 1e30f;
+    if ((r = ba_workspace_size(nullptr, b, &probe, &need)) != BA_OK) return r;
+    if (need > ws_bytes) return BA_OK;
     for (int rep = 0; rep < 3; ++rep) {
       (void)hipEventRecord(e0, hs);
-      st = ba_solve_batched(b, &probe, poses, points, obs_uv, obs_w, workspace, ws_bytes, reports,
-                            nullptr, stream);
+      r = ba_solve_batched(b, &probe, poses, points, obs_uv, obs_w, workspace, ws_bytes, reports, nullptr, stream);
       (void)hipEventRecord(e1, hs);
-      if (st != BA_OK) break;
+      if (r != BA_OK) return r;
       (void)hipEventSynchronize(e1);
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0) ms_best = std::min(ms_best, ms);
+      if (rep > 0) *ms_out = std::min(*ms_out, ms);
     }
-    if (st != BA_OK) break;
-    if (ms_best < best_ms) {
-      best_ms = ms_best;
+    return BA_OK;
+  };
+  // coordinate descent over the knobs, in this order: work-item size, tile
+  // size, per-class work-item multipliers, class chains on side streams
+  ba_launch_config best;
+  (void)ba_get_launch(b, &best);
+  best.tile_pairs = 0;
+  best.class_streams = 1;
+  for (int c = 0; c < kClasses; ++c) best.class_chunk_mult[c] = 1;
+  float best_ms = 1e30f;
+  auto consider = [&](const ba_launch_config& c) -> ba_status {
+    float ms = 0;
+    ba_status r = time_cfg(c, &ms);
+    if (r == BA_OK && ms < best_ms) {
+      best_ms = ms;
       best = c;
     }
+    return r;
+  };
+  for (int chunk : {1024, 2048, 4096, 8192, 16384}) {
+    ba_launch_config c = best;
+    c.chunk_obs = chunk;
+    if ((st = consider(c)) != BA_OK) break;
+  }
+  if (st == BA_OK) {
+    ba_launch_config c = best;
+    c.tile_pairs = kTileSmall;
+    st = consider(c);
+  }
+  const int mults[][kClasses] = {{1, 1, 2, 2}, {2, 2, 1, 1}, {1, 1, 1, 2}, {2, 1, 1, 1}};
+  for (const auto& m : mults) {
+    if (st != BA_OK) break;
+    ba_launch_config c = best;
+    for (int k = 0; k < kClasses; ++k) c.class_chunk_mult[k] = m[k];
+    st = consider(c);
+  }
+  if (st == BA_OK) {
+    ba_launch_config c = best;
+    c.class_streams = 0;
+    st = consider(c);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(reports);
   if (st != BA_OK) return st;
-  if ((st = ba_set_launch(b, best)) != BA_OK) return st;
+  if (best_ms >= 1e30f) return set_error(BA_ERR_WORKSPACE_TOO_SMALL, "no launch shape fits the workspace");
+  if ((st = ba_set_launch_config(b, &best)) != BA_OK) return st;
   if (cache) {
     std::ofstream outf(cache, std::ios::app);
-    outf << key << " " << best << "\n";
+    outf << key << " " << best.chunk_obs << " " << best.tile_pairs;
+    for (int k = 0; k < kClasses; ++k) outf << " " << best.class_chunk_mult[k];
+    outf << " " << best.class_streams << "\n";
   }
-  if (chosen_chunk_obs) *chosen_chunk_obs = best;
+  if (chosen_chunk_obs) *chosen_chunk_obs = best.chunk_obs;
   return BA_OK;
 }
 

@@ -200,7 +200,7 @@ std::string build_window(int32_t n_poses, int32_t n_points, int32_t n_cams, int6
 }
 
 void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_obs,
-                 LaunchTables& t) {
+                 LaunchTables& t, const int* class_mult) {
   t.tp = tp;
   t.chunk_obs = chunk_obs;
   t.tile_lm_begin.clear();
@@ -316,7 +316,8 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
     // balanced observation counts; a window always has at least one chunk
     t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
     const int64_t nt = (int64_t)tiles.size();
-    int64_t want = std::max<int64_t>(1, (w.n_obs + chunk_obs / 2) / std::max(1, chunk_obs));
+    const int64_t co = (int64_t)chunk_obs * (class_mult ? class_mult[size_class(w.n_free)] : 1);
+    int64_t want = std::max<int64_t>(1, (w.n_obs + co / 2) / std::max<int64_t>(1, co));
     want = std::min<int64_t>(want, std::max<int64_t>(1, nt));
     int64_t done_obs = 0, k = 0;
     const int64_t pe = partial_elems(w.n_free);

@@ -119,8 +119,11 @@ inline int size_class(int n_free) {
   return kClasses - 1;
 }
 
+// Tiles, product lists and work items of a launch: tiles of at most tp pairs,
+// work items of about chunk_obs x class_mult[size class] observations
+// (class_mult NULL: 1 for every class).
 void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_obs,
-                 LaunchTables& out);
+                 LaunchTables& out, const int* class_mult = nullptr);
 
 // Packed fields of the plan tables and the limits that keep them in range.
 //   segment word : blk (10 bits) | first product (13 bits) | count (9 bits)

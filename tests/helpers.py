@@ -39,7 +39,7 @@ def gpu_solve(w, s, poses=None, points=None, obs_uv=None, obs_w=None, with_trace
     return out
 
 
-def gpu_solve_batched(ws, s, chunk_obs=None):
+def gpu_solve_batched(ws, s, chunk_obs=None, launch=None):
     import torch
     import paper_2506_04359_amd as ba
     dev = torch.device("cuda:0")
@@ -47,6 +47,8 @@ def gpu_solve_batched(ws, s, chunk_obs=None):
     B = ba.Batch(wins)
     if chunk_obs:
         B.set_launch(chunk_obs)
+    if launch:
+        B.set_launch_config(**launch)
     P = torch.tensor(np.concatenate([w.poses_init for w in ws]), dtype=torch.float64, device=dev)
     L = torch.tensor(np.concatenate([w.points_init for w in ws]), dtype=torch.float64, device=dev)
     uv = torch.tensor(np.concatenate([w.obs_uv for w in ws]), dtype=torch.float64, device=dev)
