@@ -1404,6 +1404,37 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
     ta = trec[2 * t0];
     if (tid < ta.y) rec = prec[ta.x + tid];
   }
+  // A tile's global data is fetched during the tile before it: each pair's
+  // point and first observation (after the pair records arrive, behind phase
+  // 3), each landmark's pair range and point (behind the whole tile).
+  double px = 0, py = 0, pz = 0;
+  Real du0 = 0, dv0 = 0, wo0 = 1;
+  int cam0 = 0;
+  auto fetch_pair = [&](const int4& r, double& x, double& y, double& z, Real& du, Real& dv, Real& wo,
+                        int& cam) {
+    const double* pt = points + 3 * (r.y - W.point_off);
+    x = pt[0];
+    y = pt[1];
+    z = pt[2];
+    cam = P.obs_cam[r.x];
+    du = K.du[r.x];
+    dv = K.dv[r.x];
+    wo = K.w ? K.w[r.x] : (Real)1;
+  };
+  int lb0 = 0, lb1 = 0;
+  double lx = 0, ly = 0, lz = 0;
+  auto fetch_lm = [&](int lmt, int& b0, int& b1, double& x, double& y, double& z) {
+    b0 = P.lm_pair_begin[lmt];
+    b1 = P.lm_pair_begin[lmt + 1];
+    const double* pt = points + 3 * (lmt - W.point_off);
+    x = pt[0];
+    y = pt[1];
+    z = pt[2];
+  };
+  if (t0 < t1) {
+    if (tid < ta.y) fetch_pair(rec, px, py, pz, du0, dv0, wo0, cam0);
+    if (tid < ta.w) fetch_lm(ta.z + tid, lb0, lb1, lx, ly, lz);
+  }
   for (int t = t0; t < t1; ++t) {
     // the tile's pairs in the plan's thread order; q is the pair's index in
     // landmark order (the layout of the per-pair LDS rows)
@@ -1413,15 +1444,17 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
     const int j = lm - l0;
     int4 nta = ta;
     if (t + 1 < t1) nta = trec[2 * (t + 1)];
+    // the next tile's landmarks (their tile record is needed first)
+    int nlb0 = 0, nlb1 = 0;
+    double nlx = 0, nly = 0, nlz = 0;
+    if (t + 1 < t1 && tid < nta.w) fetch_lm(nta.z + tid, nlb0, nlb1, nlx, nly, nlz);
 
     // ---- phase 1: per pair: W, V, g at the current state and W^T dp
     if (tid < nP) {
       const double* Rt = sPose + 12 * pose;
-      const double* pt = points + 3 * (lm - W.point_off);
       double xb[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
+      for (int a = 0; a < 3; ++a) xb[a] = Rt[4 * a] * px + Rt[4 * a + 1] * py + Rt[4 * a + 2] * pz + Rt[4 * a + 3];
       Real Rp[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -1429,7 +1462,12 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
         for (int b = 0; b < 3; ++b) Rp[3 * a + b] = (Real)Rt[4 * a + b];
       PairAcc<Real> A;
       pair_zero(A);
-      for (int o = o0; o < o0 + nobs; ++o) {
+      {
+        const double* C = sCam + 16 * cam0;
+        const Lin<Real> L = linearise<Real>(xb, C, (double)du0, (double)dv0, (double)wo0, S.huber_delta);
+        pair_add<Real, ADJ>(A, L, Rp, slot >= 0, C);
+      }
+      for (int o = o0 + 1; o < o0 + nobs; ++o) {
         const double* C = sCam + 16 * P.obs_cam[o];
         const double wo = K.w ? (double)K.w[o] : 1.0;
         const Lin<Real> L = linearise<Real>(xb, C, (double)K.du[o], (double)K.dv[o], wo,
@@ -1454,7 +1492,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
     // ---- phase 2: per landmark: dl = V*^-1 (c_l - sum W^T dp)
     if (tid < nL) {
       const int lmt = l0 + tid;
-      const int q0 = P.lm_pair_begin[lmt] - p0, q1 = P.lm_pair_begin[lmt + 1] - p0;
+      const int q0 = lb0 - p0, q1 = lb1 - p0;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0}, s3[3] = {0, 0, 0};
 #pragma unroll 4
       for (int qq = q0; qq < q1; ++qq) {
@@ -1474,7 +1512,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
       ldl3(V, !ADJ, F);
       Real x[3];
       ldl3_solve(F, c, x);
-      const double* pt = points + 3 * (lmt - W.point_off);
+      const double pt[3] = {lx, ly, lz};
       if (!ADJ) {
         double* cp = cpoints + 3 * (lmt - W.point_off);
         for (int k = 0; k < 3; ++k) {
@@ -1490,6 +1528,11 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
     int4 nrec = make_int4(0, 0, 0, -1);
     if (t + 1 < t1 && tid < nta.y) nrec = prec[nta.x + tid];
     __syncthreads();
+    // the next tile's pairs: points and first observations, behind phase 3
+    double npx = 0, npy = 0, npz = 0;
+    Real ndu = 0, ndv = 0, nwo = 1;
+    int ncam = 0;
+    if (t + 1 < t1 && tid < nta.y) fetch_pair(nrec, npx, npy, npz, ndu, ndv, nwo, ncam);
 
     // ---- phase 3: per pair: candidate cost (LM) / per-observation gradients (ADJ)
     if (tid < nP) {
@@ -1500,24 +1543,23 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
         for (int a = 0; a < 3; ++a)
           xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
         for (int o = o0; o < o0 + nobs; ++o) {
-          const double* C = sCam + 16 * P.obs_cam[o];
+          const bool first = o == o0;   // the first observation is in registers
+          const double* C = sCam + 16 * (first ? cam0 : P.obs_cam[o]);
           const double X = C[4] * xb[0] + C[5] * xb[1] + C[6] * xb[2] + C[13];
           const double Y = C[7] * xb[0] + C[8] * xb[1] + C[9] * xb[2] + C[14];
           const double Z = C[10] * xb[0] + C[11] * xb[1] + C[12] * xb[2] + C[15];
           if (!(Z > S.min_depth)) sFlag[0] = 1;
           const double iz = recip_nr(Z);
-          const double r0 = C[0] * X * iz - (double)K.du[o];
-          const double r1 = C[1] * Y * iz - (double)K.dv[o];
+          const double r0 = C[0] * X * iz - (double)(first ? du0 : K.du[o]);
+          const double r1 = C[1] * Y * iz - (double)(first ? dv0 : K.dv[o]);
           double rho, d1, d2;
           huber(r0 * r0 + r1 * r1, S.huber_delta, rho, d1, d2);
-          cost += (K.w ? (double)K.w[o] : 1.0) * rho;
+          cost += (first ? (double)wo0 : (K.w ? (double)K.w[o] : 1.0)) * rho;
         }
       } else {
         const double* Rt = sPose + 12 * pose;
-        const double* pt = points + 3 * (lm - W.point_off);
         double xb[3];
-        for (int a = 0; a < 3; ++a)
-          xb[a] = Rt[4 * a] * pt[0] + Rt[4 * a + 1] * pt[1] + Rt[4 * a + 2] * pt[2] + Rt[4 * a + 3];
+        for (int a = 0; a < 3; ++a) xb[a] = Rt[4 * a] * px + Rt[4 * a + 1] * py + Rt[4 * a + 2] * pz + Rt[4 * a + 3];
         const double* al = sLP + 3 * j;
         const double zero6[6] = {0, 0, 0, 0, 0, 0};
         const double* ap = slot >= 0 ? sDp + 6 * slot : zero6;
@@ -1551,6 +1593,18 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
     __syncthreads();
     ta = nta;
     rec = nrec;
+    px = npx;
+    py = npy;
+    pz = npz;
+    du0 = ndu;
+    dv0 = ndv;
+    wo0 = nwo;
+    cam0 = ncam;
+    lb0 = nlb0;
+    lb1 = nlb1;
+    lx = nlx;
+    ly = nly;
+    lz = nlz;
   }
   if (!ADJ) {
     const double tot = block_sum<TP>(cost, sRed);
