@@ -17,6 +17,18 @@ a fixed number of solve attempts.  One attempt:
   5. accept iff F(x') < F(x) (strict): x <- x', lam <- max(lam / 10, lam_min);
      otherwise lam <- min(10 lam, lam_max) and H, g are kept.
 
+Per-window freeze (the paper gives no stopping rule; both tests are off at 0):
+  * gradient test, before step 3: with b~ = -g_p + sum_j W_j V*_j^-1 g_l,j (the
+    right-hand side of the reduced camera system, V*_j the damped landmark
+    blocks) and g_l the landmark gradient, the window freezes when
+    max(|b~|_inf, |g_l|_inf) <= grad_tol (not when a V*_j is not positive
+    definite);
+  * step test, after an accepted attempt: the window freezes when the step's
+    max-norm (pose tangents and point moves) is <= step_tol.
+A frozen window runs no more attempts: each remaining one is recorded with
+status "frozen", not accepted, no candidate, cost and lam unchanged, and is
+not counted in ``iters``.
+
 ``backend='dense'`` assembles the sparse Jacobian explicitly and forms J^T W J
 (the plain definition).  ``backend='schur'`` assembles the same H in blocks
 (U per pose, V per landmark, W per pose-landmark pair) and solves it by the
@@ -47,6 +59,8 @@ class LMSettings:
     lambda_max: float = 1e10
     huber_delta: float = 1.0
     min_depth: float = 1e-3
+    grad_tol: float = 0.0
+    step_tol: float = 0.0
 
 
 @dataclasses.dataclass
@@ -59,6 +73,7 @@ class LMResult:
     accepted: int
     chol_failures: int
     trace: List[dict]
+    iters: int = 0
 
 
 def _weights(poses, points, prob, delta):
@@ -215,6 +230,45 @@ def solve_schur(sys: BlockSystem, lam, pp=None):
     return np.concatenate([dp.reshape(-1), dl.reshape(-1)])
 
 
+def reduced_gradient_norm(system, backend, lam, n_free):
+    """max(|b~|_inf, |g_l|_inf) of the freeze test: b~ = -g_p + sum_j W_j V*_j^-1 g_l,j
+    with V*_j = V_j + lam diag(max(V_j,kk, 1e-9)); NaN when a V*_j is not
+    positive definite (the test then never freezes)."""
+    if backend == "dense":
+        H, g = system
+        n = 6 * n_free
+        M = (H.shape[0] - n) // 3
+        gp, gl = g[:n], g[n:].reshape(M, 3)
+        idx = n + 3 * np.arange(M)
+        V = np.stack([H[i:i + 3, i:i + 3] for i in idx]) if M else np.zeros((0, 3, 3))
+        Wt = H[:n, n:]
+    else:
+        gp, gl, V = system.gp.reshape(-1), system.gl, system.V
+    Vs = _damp(V, lam)
+    if _not_pd(Vs):
+        return math.nan
+    y = np.linalg.solve(Vs, gl[..., None])[..., 0] if gl.size else gl
+    if backend == "dense":
+        bt = -gp + Wt @ y.reshape(-1)
+    else:
+        bt = -system.gp.copy()
+        np.add.at(bt, system.pair_pose, np.einsum("pij,pj->pi", system.W, y[system.pair_point]))
+        bt = bt.reshape(-1)
+    parts = [np.abs(bt).max() if bt.size else 0.0, np.abs(gl).max() if gl.size else 0.0]
+    return float(max(parts))
+
+
+def _not_pd(Vs):
+    """True when any block of the batch is not positive definite (or not finite)."""
+    if not np.all(np.isfinite(Vs)):
+        return True
+    try:
+        np.linalg.cholesky(Vs)
+    except np.linalg.LinAlgError:
+        return True
+    return False
+
+
 # ---------------------------------------------------------------------------
 # the LM loop
 # ---------------------------------------------------------------------------
@@ -245,8 +299,13 @@ def lm_solve(poses0, points0, prob, settings: LMSettings = None, backend: str = 
     system = None
     pp = None
     trace = []
-    n_acc = n_chol = 0
+    n_acc = n_chol = n_run = 0
+    frozen = False
     for it in range(st.max_iters):
+        if frozen:
+            trace.append(dict(iter=it, cost=F, lam=lam, cand_cost=math.nan, status="frozen", accepted=False,
+                              cost_after=F, lam_after=lam))
+            continue
         if system is None:
             if backend == "dense":
                 system = normal_equations_dense(poses, points, prob, delta)
@@ -254,6 +313,14 @@ def lm_solve(poses0, points0, prob, settings: LMSettings = None, backend: str = 
                 system = normal_equations_blocks(poses, points, prob, delta)
                 if pp is None:
                     pp = _pairs_of_pairs(system)
+        if st.grad_tol > 0:
+            gn = reduced_gradient_norm(system, backend, lam, prob.n_free)
+            if gn <= st.grad_tol:
+                frozen = True
+                trace.append(dict(iter=it, cost=F, lam=lam, cand_cost=math.nan, status="frozen", accepted=False,
+                                  cost_after=F, lam_after=lam, grad_norm=gn))
+                continue
+        n_run += 1
         if backend == "dense":
             step = solve_dense(system[0], system[1], lam)
         else:
@@ -284,6 +351,9 @@ def lm_solve(poses0, points0, prob, settings: LMSettings = None, backend: str = 
             lam = max(lam / st.lambda_down, st.lambda_min)
             system = None
             n_acc += 1
+            rec["step_norm"] = float(np.abs(step).max()) if step.size else 0.0
+            if st.step_tol > 0 and rec["step_norm"] <= st.step_tol:
+                frozen = True
         else:
             lam = min(lam * st.lambda_up, st.lambda_max)
         rec["accepted"] = accept
@@ -291,4 +361,4 @@ def lm_solve(poses0, points0, prob, settings: LMSettings = None, backend: str = 
         rec["lam_after"] = lam
         trace.append(rec)
     return LMResult(poses=poses, points=points, initial_cost=F0, final_cost=F,
-                    final_lambda=lam, accepted=n_acc, chol_failures=n_chol, trace=trace)
+                    final_lambda=lam, accepted=n_acc, chol_failures=n_chol, trace=trace, iters=n_run)
