@@ -112,6 +112,18 @@ typedef struct {
   double lambda_max;      /* clamp (1e10) */
   double huber_delta;     /* pixels; <= 0 selects plain least squares */
   double min_depth;       /* candidate rejected if any camera depth Z <= min_depth */
+  /* Per-window freeze (0 = off: every window runs max_iters attempts).  A
+   * frozen window runs no more attempts; each remaining one is traced with
+   * status 3, not accepted, cost and lambda unchanged, and not counted in
+   * ba_report.iters.  The launches stay the same (graph-capturable): a frozen
+   * window's work items return at once.  Window solves only (ba_solve,
+   * ba_solve_batched, ba_solve_noalloc, ba_map_solve); ba_vi_solve requires 0. */
+  double grad_tol;        /* before an attempt: freeze when max(|b~|_inf, |g_l|_inf) <= grad_tol,
+                             b~ the reduced camera system's right-hand side at the attempt's
+                             damping, g_l the landmark gradient (never when a landmark block is
+                             not positive definite); >= 0 */
+  double step_tol;        /* after an accepted attempt: freeze when the step's max-norm (pose
+                             tangents, point moves) <= step_tol; >= 0 */
 } ba_settings;
 
 /* Per-window outcome, written by the device at the end of a solve. */
@@ -119,7 +131,7 @@ typedef struct {
   double initial_cost;    /* F at the input state */
   double final_cost;      /* F at the output state */
   double final_lambda;
-  int32_t iters;          /* attempts run */
+  int32_t iters;          /* attempts run (frozen ones excluded) */
   int32_t accepted;       /* accepted attempts */
   int32_t chol_failures;  /* attempts rejected by a non-positive pivot */
   int32_t depth_rejects;  /* attempts rejected by min_depth */
@@ -134,7 +146,7 @@ typedef struct {
   double cand_cost;       /* F at the candidate; NaN when none was formed */
   double lambda;          /* damping used */
   int32_t accepted;
-  int32_t status;         /* 0 = candidate formed, 1 = pivot failure, 2 = depth */
+  int32_t status;         /* 0 = candidate formed, 1 = pivot failure, 2 = depth, 3 = frozen */
 } ba_iter_trace;
 
 /* Plan statistics (host side; usable without a device). */

@@ -39,7 +39,7 @@ class _Settings(ctypes.Structure):
                 ("lambda_init", ctypes.c_double), ("lambda_up", ctypes.c_double),
                 ("lambda_down", ctypes.c_double), ("lambda_min", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("huber_delta", ctypes.c_double),
-                ("min_depth", ctypes.c_double)]
+                ("min_depth", ctypes.c_double), ("grad_tol", ctypes.c_double), ("step_tol", ctypes.c_double)]
 
 
 class _LaunchConfig(ctypes.Structure):   # include/ba.h ba_launch_config
@@ -156,11 +156,13 @@ class Settings:
     lambda_max: float = 1e10
     huber_delta: float = 1.0
     min_depth: float = 1e-3
+    grad_tol: float = 0.0
+    step_tol: float = 0.0
 
     def c(self) -> _Settings:
         return _Settings(self.max_iters, self.precision, self.lambda_init, self.lambda_up,
                          self.lambda_down, self.lambda_min, self.lambda_max, self.huber_delta,
-                         self.min_depth)
+                         self.min_depth, self.grad_tol, self.step_tol)
 
 
 def _host(a, dtype):

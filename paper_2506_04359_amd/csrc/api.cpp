@@ -334,6 +334,8 @@ ba_status check_settings(const ba_settings* s) {
   if (!(s->lambda_init > 0) || !(s->lambda_up > 1) || !(s->lambda_down > 1) ||
       !(s->lambda_min > 0) || !(s->lambda_max >= s->lambda_min) || !std::isfinite(s->lambda_max))
     return set_error(BA_ERR_INVALID_ARG, "invalid lambda settings");
+  if (!(s->grad_tol >= 0) || !std::isfinite(s->grad_tol) || !(s->step_tol >= 0) || !std::isfinite(s->step_tol))
+    return set_error(BA_ERR_INVALID_ARG, "grad_tol and step_tol must be finite and >= 0");
   if (std::isnan(s->huber_delta) || !std::isfinite(s->min_depth))
     return set_error(BA_ERR_INVALID_ARG, "invalid huber_delta or min_depth");
   return BA_OK;
@@ -374,7 +376,7 @@ ba_status pick_config(const ba_batch_s* b, int precision, int* which) {
 }
 
 struct Layout {
-  size_t du, dv, w, poses_b, points_b, state, dp, ssum, part, cost_a, cost_b, flag_a, flag_b, total;
+  size_t du, dv, w, poses_b, points_b, state, dp, ssum, part, cost_a, cost_b, flag_a, flag_b, gmax, smax, total;
 };
 
 Layout layout(const ba_batch_s* b, const DeviceTables& t, size_t real) {
@@ -400,6 +402,8 @@ Layout layout(const ba_batch_s* b, const DeviceTables& t, size_t real) {
   L.cost_b = take(sizeof(double) * t.n_chunks);
   L.flag_a = take(sizeof(int32_t) * t.n_chunks);
   L.flag_b = take(sizeof(int32_t) * t.n_chunks);
+  L.gmax = take(sizeof(double) * t.n_chunks);
+  L.smax = take(sizeof(double) * t.n_chunks);
   L.total = o;
   return L;
 }
@@ -421,6 +425,8 @@ DevWork<Real> make_work(const Layout& L, void* ws, bool has_w) {
   K.part_cost_b = (double*)(m + L.cost_b);
   K.part_flag_a = (int32_t*)(m + L.flag_a);
   K.part_flag_b = (int32_t*)(m + L.flag_b);
+  K.part_gmax = (double*)(m + L.gmax);
+  K.part_smax = (double*)(m + L.smax);
   K.vi_cost_a = nullptr;
   K.vi_cost_b = nullptr;
   K.vi_states = nullptr;
@@ -455,6 +461,8 @@ DevSettings dev_settings(const ba_settings* s) {
   d.lambda_max = s->lambda_max;
   d.huber_delta = s->huber_delta;
   d.min_depth = s->min_depth;
+  d.grad_tol = s->grad_tol;
+  d.step_tol = s->step_tol;
   d.max_iters = s->max_iters;
   d.pad = 0;
   return d;
@@ -1143,6 +1151,8 @@ ba_status ba_vi_solve(ba_window w, const ba_settings* s, const double* preint, c
   const HostWindow& h = b->wins[0];
   if (h.n_poses < 2 || h.n_poses > kViMaxStates)
     return set_error(BA_ERR_UNSUPPORTED, "visual-inertial windows hold 2 to 24 keyframes");
+  if (s->grad_tol != 0 || s->step_tol != 0)
+    return set_error(BA_ERR_UNSUPPORTED, "visual-inertial solves run a fixed number of attempts (tolerances 0)");
   if (!preint || !gravity || !states || !poses || (!points && b->n_points > 0) || (!obs_uv && b->n_obs > 0) ||
       !report)
     return set_error(BA_ERR_INVALID_ARG, "NULL argument");
@@ -1302,6 +1312,7 @@ ba_status ba_autotune(ba_batch b, const ba_settings* s, double* poses, double* p
   // The timed runs solve a short problem (at most 3 attempts) in place: the
   // caller passes scratch copies of the state.
   ba_settings probe = *s;
+  probe.grad_tol = probe.step_tol = 0.0;   // every window runs every timed attempt
   probe.max_iters = std::min(s->max_iters, 3);
   if (probe.max_iters < 1) probe.max_iters = 1;
   ba_report* reports = nullptr;

@@ -42,7 +42,8 @@ struct WinState {
   double init_cost;   // F at the input state
   int32_t cur;        // which buffer holds the current state: 0 user arrays, 1 workspace
   int32_t fail;       // this attempt met a non-positive pivot
-  int32_t accepted, chol_failures, depth_rejects, iters, status, pad;
+  int32_t accepted, chol_failures, depth_rejects, iters, status;
+  int32_t frozen;     // a freeze test has stopped the window (no more attempts)
 };
 
 // Read-only plan arrays (batch-global indices unless stated).
@@ -88,6 +89,8 @@ struct DevWork {
   double* part_cost_b;      // per chunk: sum w rho at the candidate
   int32_t* part_flag_a;     // per chunk: a landmark block was not positive definite
   int32_t* part_flag_b;     // per chunk: a candidate depth <= min_depth
+  double* part_gmax;        // per chunk: largest |landmark gradient| (grad_tol > 0)
+  double* part_smax;        // per chunk: largest |landmark step| (step_tol > 0)
   // visual-inertial solves only (NULL otherwise): per window the IMU cost at
   // the current state and at the candidate; the velocities and biases (user
   // buffer and workspace buffer, 9 per pose)
@@ -113,6 +116,7 @@ struct DevUser {
 struct DevSettings {
   double lambda_init, lambda_up, lambda_down, lambda_min, lambda_max;
   double huber_delta, min_depth;
+  double grad_tol, step_tol;   // freeze tests (0: off)
   int32_t max_iters;
   int32_t pad;
 };

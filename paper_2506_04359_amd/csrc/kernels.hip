@@ -324,6 +324,20 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return t;   // valid in thread 0
 }
 
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* scratch) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) scratch[wv] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NT / 64; ++k) t = fmax(t, scratch[k]);
+  __syncthreads();
+  return t;   // valid in thread 0
+}
+
 // Exclusive scan of n (<= NT) ints in LDS, in place, total at a[n].
 // Per-chunk flags and costs of a window's chunks [c0, c1), reduced by one
 // wave: lane l takes chunks c0 + l, c0 + l + 64, ... in order (four loads in
@@ -418,7 +432,7 @@ __global__ void k_init(DevPlan P, DevWork<Real> K, DevSettings S) {
   st.init_cost = 0.0;
   st.cur = 0;
   st.fail = 0;
-  st.accepted = st.chol_failures = st.depth_rejects = st.iters = st.status = st.pad = 0;
+  st.accepted = st.chol_failures = st.depth_rejects = st.iters = st.status = st.frozen = 0;
   K.state[w] = st;
 }
 
@@ -574,6 +588,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   const int wi = T.chunk_window[chunk];
   const WinDev W = P.win[wi];
   const WinState& st = K.state[wi];
+  if (!ADJ && st.frozen) return;   // the whole work item (every thread of it) returns
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cur = ADJ ? 0 : st.cur;
   const double lam = ADJ ? 0.0 : st.lambda;
@@ -646,7 +661,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   };
   if (t0 < t1 && tid < ta.y) fetch_pair(rec, px, py, pz, du0, dv0, wo0, cam0);
 
-  double cost = 0.0;
+  double cost = 0.0, gmax = 0.0;
   for (int t = t0; t < t1; ++t) {
     const int p0 = ta.x, nP = ta.y, l0 = ta.z, nL = ta.w;
     const int lw0 = tb.x, nseg = tb.y, nprod = tb.z;
@@ -746,6 +761,7 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
       }
       Real c[3];
       if (!ADJ) {
+        gmax = fmax(gmax, fmax(fabs((double)g[0]), fmax(fabs((double)g[1]), fabs((double)g[2]))));
         damp3(V, lam);
         c[0] = -g[0];
         c[1] = -g[1];
@@ -975,6 +991,10 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     K.part_cost_a[chunk] = tot;
     K.part_flag_a[chunk] = sFlag[0];
   }
+  if (!ADJ && S.grad_tol > 0) {
+    const double gm = block_max<TP>(gmax, sRed);
+    if (tid == 0) K.part_gmax[chunk] = gm;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1027,6 +1047,7 @@ template <typename Real>
 __global__ __launch_bounds__(256) void k_sum(DevPlan P, DevTiles T, DevWork<Real> K, int wbase) {
   __shared__ double sG[kSumE][256];
   const int wi = T.win_order[wbase + blockIdx.x];
+  if (K.state[wi].frozen) return;
   const WinDev W = P.win[wi];
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2;
   const int ne = nblk * kBS + 12 * nf;
@@ -1101,9 +1122,11 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   double* sB = sS + nblk * kBS;                   // nS
   double* sD = sB + nS;                           // nS
   double* sInv = sD + nS;                         // nS: 1 / R_pp of the diagonal blocks
-  int* sFail = reinterpret_cast<int*>(sInv + nS); // 1
+  int* sFail = reinterpret_cast<int*>(sInv + nS); // 2 ints (one double): failure, freeze
+  double* sMax = sInv + nS + 1;                   // NT / 64 (<= 8): freeze test
   const int c0 = W.chunk_begin, c1 = W.chunk_end;
   const int ne = nblk * kBS + 2 * nS;
+  if (!ADJ && st.frozen) return;
   {
     // chunk flags and costs (wave 0)
     const bool need_cost = !ADJ && it == 0;
@@ -1140,6 +1163,21 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     }
   }
   __syncthreads();
+  if (!ADJ && S.grad_tol > 0) {
+    // freeze test at this attempt's linearisation and damping: the reduced
+    // right-hand side (summed) and the chunks' landmark gradient maxima; not
+    // when a landmark block failed
+    double m = 0.0;
+    for (int e = tid; e < nS; e += NT) m = fmax(m, fabs(sB[e]));
+    for (int c = c0 + tid; c < c1; c += NT) m = fmax(m, K.part_gmax[c]);
+    const double gm = block_max<NT>(m, sMax);
+    if (tid == 0) {
+      sFail[1] = sFail[0] == 0 && gm <= S.grad_tol;
+      if (sFail[1]) st.frozen = 1;
+    }
+    __syncthreads();
+    if (sFail[1]) return;
+  }
   const double lam = st.lambda;
   const double* poses = (ADJ || st.cur == 0 ? U.poses : K.poses_b) + 12 * W.pose_off;
   if (ADJ) {
@@ -1362,10 +1400,11 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
   const WinDev W = P.win[wi];
   const WinState& st = K.state[wi];
   const int tid = threadIdx.x;
-  if (!ADJ && st.fail) {
+  if (!ADJ && (st.fail || st.frozen)) {
     if (tid == 0) {
       K.part_cost_b[chunk] = 0.0;
       K.part_flag_b[chunk] = 0;
+      K.part_smax[chunk] = 0.0;
     }
     return;
   }
@@ -1394,7 +1433,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
   if (tid == 0) sFlag[0] = 0;
   __syncthreads();
 
-  double cost = 0.0;
+  double cost = 0.0, smax = 0.0;
   const int t0 = T.chunk_tile_begin[chunk], t1 = T.chunk_tile_begin[chunk + 1];
   const int4* trec = reinterpret_cast<const int4*>(T.tile_rec);
   const int4* prec = reinterpret_cast<const int4*>(T.pair_rec);
@@ -1519,6 +1558,7 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
           const double v = pt[k] + (double)x[k];
           sLP[3 * tid + k] = v;
           cp[k] = v;
+          smax = fmax(smax, fabs((double)x[k]));
         }
       } else {
         for (int k = 0; k < 3; ++k) sLP[3 * tid + k] = (double)x[k];
@@ -1612,6 +1652,10 @@ __global__ __launch_bounds__(TP) void k_pass_b(DevPlan P, DevTiles T, DevWork<Re
       K.part_cost_b[chunk] = tot;
       K.part_flag_b[chunk] = sFlag[0];
     }
+    if (S.step_tol > 0) {
+      const double sm = block_max<TP>(smax, sRed);
+      if (tid == 0) K.part_smax[chunk] = sm;
+    }
   }
 }
 
@@ -1632,6 +1676,14 @@ __global__ void k_accept(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U, DevS
   int depth = 0;
   double F = 0.0;
   wave_chunk_sums(K.part_flag_b, K.part_cost_b, W.chunk_begin, W.chunk_end, true, lane, depth, F);
+  // the step's max-norm for the step test: pose tangents and the chunks' point moves
+  double sm = 0.0;
+  if (S.step_tol > 0) {
+    for (int e = lane; e < 6 * W.n_free; e += 64) sm = fmax(sm, fabs(K.dp[kDpStride * wi + e]));
+    for (int c = W.chunk_begin + lane; c < W.chunk_end; c += 64) sm = fmax(sm, K.part_smax[c]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sm = fmax(sm, __shfl_xor(sm, off, 64));
+  }
   if (lane != 0) return;
   WinState st = K.state[wi];
   ba_iter_trace tr;
@@ -1640,6 +1692,11 @@ __global__ void k_accept(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U, DevS
   tr.cand_cost = __builtin_nan("");
   tr.accepted = 0;
   tr.status = 0;
+  if (st.frozen) {   // frozen by an earlier attempt or by this one's gradient test
+    tr.status = 3;
+    if (U.traces) U.traces[(size_t)wi * S.max_iters + it] = tr;
+    return;
+  }
   bool accept = false;
   if (st.fail) {
     tr.status = 1;
@@ -1661,6 +1718,7 @@ __global__ void k_accept(DevPlan P, DevTiles T, DevWork<Real> K, DevUser U, DevS
     st.cur ^= 1;
     st.accepted++;
     st.lambda = fmax(st.lambda / S.lambda_down, S.lambda_min);
+    if (S.step_tol > 0 && sm <= S.step_tol) st.frozen = 1;
   } else {
     st.lambda = fmin(st.lambda * S.lambda_up, S.lambda_max);
   }
@@ -1728,7 +1786,7 @@ size_t pass_b_lds() {
 // The reduce kernel's LDS: the reduced system of the largest window.
 size_t reduce_lds(int max_nf) {
   const int nblk = max_nf * (max_nf + 1) / 2;
-  return (size_t)(nblk * kBS + 18 * max_nf + 2) * sizeof(double);
+  return (size_t)(nblk * kBS + 18 * max_nf + 11) * sizeof(double);
 }
 
 constexpr int kReduceThreads = 512;

@@ -18,7 +18,8 @@ def oracle_settings(s):
     return oracle.LMSettings(max_iters=s.max_iters, lambda_init=s.lambda_init,
                              lambda_up=s.lambda_up, lambda_down=s.lambda_down,
                              lambda_min=s.lambda_min, lambda_max=s.lambda_max,
-                             huber_delta=s.huber_delta, min_depth=s.min_depth)
+                             huber_delta=s.huber_delta, min_depth=s.min_depth,
+                             grad_tol=getattr(s, "grad_tol", 0.0), step_tol=getattr(s, "step_tol", 0.0))
 
 
 def gpu_solve(w, s, poses=None, points=None, obs_uv=None, obs_w=None, with_trace=True):
@@ -85,6 +86,9 @@ def check_decisions(ref, gpu_trace, tie=1e-12):
     """Every accept flag equals the oracle's own decision, or the oracle's own
     comparison was a near-tie (|F' - F| / F < tie)."""
     for t, g in zip(ref.trace, gpu_trace):
+        if t["status"] == "frozen" or int(g["status"]) == 3:
+            assert t["status"] == "frozen" and int(g["status"]) == 3, (t, g)
+            continue
         if t["own_decision"] != bool(g["accepted"]):
             assert math.isfinite(t["cand_cost"]), (t, g)
             assert abs(t["cand_cost"] - t["cost"]) <= tie * abs(t["cost"]), (t, g)
