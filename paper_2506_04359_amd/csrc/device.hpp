@@ -89,7 +89,7 @@ struct DevWork {
   double* part_cost_b;      // per chunk: sum w rho at the candidate
   int32_t* part_flag_a;     // per chunk: a landmark block was not positive definite
   int32_t* part_flag_b;     // per chunk: a candidate depth <= min_depth
-  double* part_gmax;        // per chunk: largest |landmark gradient| (grad_tol > 0)
+  double* part_gmax;        // per chunk: largest |landmark gradient| (LM solves)
   double* part_smax;        // per chunk: largest |landmark step| (step_tol > 0)
   // visual-inertial solves only (NULL otherwise): per window the IMU cost at
   // the current state and at the candidate; the velocities and biases (user

@@ -324,6 +324,31 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return t;   // valid in thread 0
 }
 
+// Sum of v and maximum of m over the workgroup (both valid in thread 0);
+// scratch holds 2 NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum_max(double v, double& m, double* scratch) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v += __shfl_down(v, off, 64);
+    m = fmax(m, __shfl_down(m, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    scratch[wv] = v;
+    scratch[NT / 64 + wv] = m;
+  }
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NT / 64; ++k) t += scratch[k];
+    m = scratch[NT / 64];
+    for (int k = 1; k < NT / 64; ++k) m = fmax(m, scratch[NT / 64 + k]);
+  }
+  __syncthreads();
+  return t;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_max(double v, double* scratch) {
 #pragma unroll
@@ -752,12 +777,25 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     if (tid < nL) {
       const int lmg = l0 + tid;
       Real V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
-#pragma unroll 4
-      for (int qq = lq0; qq < lq1; ++qq) {
+      // the landmark's pairs summed in order; the next pair's values are read
+      // while the current ones are added (at the end the last pair is read
+      // again, not used)
+      if (lq0 < lq1) {
+        Real x[9];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) V[k] += sPV[9 * qq + k];
+        for (int k = 0; k < 9; ++k) x[k] = sPV[9 * lq0 + k];
+        for (int qq = lq0; qq < lq1; ++qq) {
+          const int nq = qq + 1 < lq1 ? qq + 1 : qq;
+          Real y[9];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g[k] += sPV[9 * qq + 6 + k];
+          for (int k = 0; k < 9; ++k) y[k] = sPV[9 * nq + k];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) V[k] += x[k];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) g[k] += x[6 + k];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) x[k] = y[k];
+        }
       }
       Real c[3];
       if (!ADJ) {
@@ -986,14 +1024,13 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   // ---- chunk partial out (the last tile's phase 4 ended with a barrier)
   Real* part = K.part + T.chunk_part_off[chunk];
   for (int k = tid; k < nblk * kBS + 2 * nS; k += TP) part[k] = sS[k];
-  const double tot = block_sum<TP>(cost, sRed);
+  // the cost sum and the landmark-gradient maximum in one reduction
+  double gm = gmax;
+  const double tot = block_sum_max<TP>(cost, gm, sRed);
   if (tid == 0) {
     K.part_cost_a[chunk] = tot;
     K.part_flag_a[chunk] = sFlag[0];
-  }
-  if (!ADJ && S.grad_tol > 0) {
-    const double gm = block_max<TP>(gmax, sRed);
-    if (tid == 0) K.part_gmax[chunk] = gm;
+    if (!ADJ) K.part_gmax[chunk] = gm;
   }
 }
 
