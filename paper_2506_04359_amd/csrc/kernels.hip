@@ -673,35 +673,28 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
   double px = 0, py = 0, pz = 0;
   Real du0 = 0, dv0 = 0, wo0 = 1;
   int cam0 = 0;
-  auto fetch_pair = [&](const int4& r, double& x, double& y, double& z, Real& du, Real& dv, Real& wo,
+  // (threads without a pair read the window's first point and observation 0:
+  // the loads are issued on every path, so the counter waits stay exact)
+  auto fetch_pair = [&](const int4& r, bool on, double& x, double& y, double& z, Real& du, Real& dv, Real& wo,
                         int& cam) {
-    const double* pt = points + 3 * (r.y - W.point_off);
+    const int o = on ? r.x : 0;
+    const double* pt = points + 3 * (on ? r.y - W.point_off : 0);
     x = pt[0];
     y = pt[1];
     z = pt[2];
-    cam = P.obs_cam[r.x];
-    du = K.du[r.x];
-    dv = K.dv[r.x];
-    wo = K.w ? K.w[r.x] : (Real)1;
+    cam = P.obs_cam[o];
+    du = K.du[o];
+    dv = K.dv[o];
+    const Real wv = (K.w ? K.w : K.du)[o];   // a load on every path (the value is dropped without weights)
+    wo = K.w ? wv : (Real)1;
   };
-  if (t0 < t1 && tid < ta.y) fetch_pair(rec, px, py, pz, du0, dv0, wo0, cam0);
+  if (t0 < t1) fetch_pair(rec, tid < ta.y, px, py, pz, du0, dv0, wo0, cam0);
 
   double cost = 0.0, gmax = 0.0;
   for (int t = t0; t < t1; ++t) {
     const int p0 = ta.x, nP = ta.y, l0 = ta.z, nL = ta.w;
     const int lw0 = tb.x, nseg = tb.y, nprod = tb.z;
     const int nwords = nseg + (nprod + 1) / 2;
-    // in flight during this tile: the tile record after the next one, and
-    // the next tile's pairs' points and first observations
-    int4 nnta = nta, nntb = ntb;
-    if (t + 2 < t1) {
-      nnta = trec[2 * (t + 2)];
-      nntb = trec[2 * (t + 2) + 1];
-    }
-    double npx = 0, npy = 0, npz = 0;
-    Real ndu = 0, ndv = 0, nwo = 1;
-    int ncam = 0;
-    if (t + 1 < t1 && tid < nta.y) fetch_pair(nrec, npx, npy, npz, ndu, ndv, nwo, ncam);
     // this tile's pair: its pose (point and first observation are here
     // already), and the tile's list words
     const int q = (rec.z >> 8) & 255, pose = rec.z & 255, nobs = rec.z >> 16;
@@ -713,20 +706,33 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
 #pragma unroll
       for (int k = 0; k < 12; ++k) Rt[k] = pp[k];
     }
-    int lq0 = 0, lq1 = 0;
-    if (tid < nL) {
-      lq0 = P.lm_pair_begin[l0 + tid] - p0;
-      lq1 = P.lm_pair_begin[l0 + tid + 1] - p0;
-    }
+    // (unconditional, clamped to the tile's last landmark: loads issued on
+    // every path keep the counter waits exact)
+    const int lt = l0 + min(tid, nL > 0 ? nL - 1 : 0);
+    const int lq0 = P.lm_pair_begin[lt] - p0, lq1 = P.lm_pair_begin[lt + 1] - p0;
     const bool lregs = nwords <= LR * TP;
     uint32_t lwv[LR];
     if (lregs) {
+      // unconditional loads (clamped to the tile's last word; the table ends
+      // with a padding word), so that waiting for them never waits for the
+      // prefetches issued after them
+      const int last = nwords > 0 ? nwords - 1 : 0;
 #pragma unroll
-      for (int k = 0; k < LR; ++k) {
-        const int i = tid + k * TP;
-        lwv[k] = i < nwords ? T.lists[lw0 + i] : 0u;
-      }
+      for (int k = 0; k < LR; ++k) lwv[k] = T.lists[lw0 + min(tid + k * TP, last)];
     }
+    // In flight during this tile (issued after this tile's own loads: the
+    // load counter retires in order, so waiting for the list words does not
+    // wait for these): the tile record after the next one, and the next
+    // tile's pairs' points and first observations.
+    int4 nnta = nta, nntb = ntb;
+    if (t + 2 < t1) {
+      nnta = trec[2 * (t + 2)];
+      nntb = trec[2 * (t + 2) + 1];
+    }
+    double npx = 0, npy = 0, npz = 0;
+    Real ndu = 0, ndv = 0, nwo = 1;
+    int ncam = 0;
+    fetch_pair(nrec, t + 1 < t1 && tid < nta.y, npx, npy, npz, ndu, ndv, nwo, ncam);
 
     // ---- phase 1: thread t linearises its pair (free pairs sorted by slot)
     PairAcc<Real> A;
@@ -826,8 +832,8 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
     __syncthreads();
     // the pair records of the tile after the next one (its tile record has
     // arrived by now)
-    int4 nnrec = make_int4(0, 0, 0, -1);
-    if (t + 2 < t1 && tid < nnta.y) nnrec = prec[nnta.x + tid];
+    // (unconditional, clamped: the values of threads without a pair are not used)
+    const int4 nnrec = prec[nnta.x + min(tid, nnta.y > 0 ? nnta.y - 1 : 0)];
 
     // ---- phase 3: Z_bar = W L^-T |D|^-1/2 of this pair, its reduced rhs and
     // its own diagonal Schur term U - Z_bar sigma Z_bar^T (the products of a

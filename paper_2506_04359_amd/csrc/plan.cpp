@@ -339,6 +339,7 @@ void build_tiles(const std::vector<const HostWindow*>& wins, int tp, int chunk_o
     pair_base += (int32_t)w.n_pairs();
     obs_base += (int32_t)w.n_obs;
   }
+  t.lists.push_back(0u);   // padding: the kernels read a tile's words unconditionally, clamped to its last
   t.tile_lm_begin.push_back(lm_base);
   t.chunk_tile_begin.push_back((int32_t)t.tile_lm_begin.size() - 1);
   t.win_chunk_begin.push_back((int32_t)t.chunk_window.size());
