@@ -1045,36 +1045,58 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
 // ---------------------------------------------------------------------------
 
 
-// Upper Cholesky of one symmetric 6x6 block spread over a wave: lane l < 36
-// holds entry (l / 6, l % 6).  Writes the upper triangle of R to D and 1 / R_pp
-// to inv; raises *fail on a non-positive or non-finite pivot.  Every lane of
-// the wave takes part (pivots and pivot rows are broadcast by readlane).
+// Upper Cholesky of one symmetric 6x6 block, by one wave: lane l < 36 brings
+// entry (l / 6, l % 6).  Writes the upper triangle of R to D and 1 / R_pp to
+// inv; raises *fail on a non-positive or non-finite pivot.  The lanes put
+// their entries into D, then every lane factors the whole block in registers
+// (the same values in every lane): the serial pivot chain has no cross-lane
+// traffic.
 __device__ __forceinline__ void factor_diag(double a, double* D, double* inv, int* fail) {
   const int lane = threadIdx.x & 63;
   const int r = lane / 6, c = lane - 6 * (lane / 6);
+  if (lane < 36) D[lane] = a;
+  __builtin_amdgcn_wave_barrier();
+  double R[21];   // upper triangle, row-major: row p starts at 6 p - p (p - 1) / 2
+#pragma unroll
+  for (int p = 0, e = 0; p < 6; ++p)
+#pragma unroll
+    for (int q = p; q < 6; ++q, ++e) R[e] = D[6 * p + q];
+  __builtin_amdgcn_wave_barrier();
+  double ir6[6];
 #pragma unroll
   for (int p = 0; p < 6; ++p) {
-    const double d = wave_bcast(a, 7 * p);
-    if (!(d > 0.0) || !isfinite(d)) {
+    const int rp = 6 * p - p * (p - 1) / 2;   // (p, p)
+    const double d = R[rp];
+    if (!(d > 0.0) || !isfinite(d)) {   // the same in every lane
       if (lane == 0) *fail = 1;
       return;
     }
-    const double ir = rsqrt(d), s = d * ir;
-    if (r == p) a = c == p ? s : a * ir;
-    // row p of R (its entries right of the pivot) to every lane
-    double rp[6];
+    const double ir = rsqrt(d), sd = d * ir;
+    ir6[p] = ir;
+    R[rp] = sd;
 #pragma unroll
-    for (int x = p + 1; x < 6; ++x) rp[x] = wave_bcast(a, 6 * p + x);
-    double rr = 0.0, rc = 0.0;   // R[p][r], R[p][c]
+    for (int q = p + 1; q < 6; ++q) R[rp + q - p] *= ir;
 #pragma unroll
     for (int x = p + 1; x < 6; ++x) {
-      if (r == x) rr = rp[x];
-      if (c == x) rc = rp[x];
+      const int rx = 6 * x - x * (x - 1) / 2;
+#pragma unroll
+      for (int q = x; q < 6; ++q) R[rx + q - x] -= R[rp + x - p] * R[rp + q - p];
     }
-    if (r > p && c > p) a -= rr * rc;
-    if (lane == p) inv[p] = ir;
   }
-  if (lane < 36 && c >= r) D[lane] = a;
+  if (lane < 6) {
+    double v = ir6[0];
+#pragma unroll
+    for (int p = 1; p < 6; ++p) v = lane == p ? ir6[p] : v;
+    inv[lane] = v;
+  }
+  if (lane < 36 && c >= r) {
+    double v = 0.0;
+#pragma unroll
+    for (int p = 0, e = 0; p < 6; ++p)
+#pragma unroll
+      for (int q = p; q < 6; ++q, ++e) v = (r == p && c == q) ? R[e] : v;
+    D[lane] = v;
+  }
 }
 
 // Pair (i, j), i <= j < n, of index e in the row-major upper triangle of an
