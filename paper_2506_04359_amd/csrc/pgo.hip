@@ -448,7 +448,8 @@ __device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, i
 // finishes the forward step, then the lanes solve the column's panel rows.
 // With SUM the chunk partials are subtracted here (the wide levels).
 template <bool SUM>
-__device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, int l, int w0, int nw, int lane) {
+__device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, int l, int w0, int nw, int lane,
+                                            int* sfail = nullptr) {
   const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
   const double* fpart = W.part + 36 * (long long)G.n_chunks;
   for (int c = c0 + w0; c < c1; c += nw) {
@@ -485,7 +486,10 @@ __device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, i
       }
     }
     if (!ok) {
-      if (lane == 0) W.istate[4] = 1;
+      if (lane == 0) {
+        W.istate[4] = 1;
+        if (sfail) *sfail = 1;
+      }
       continue;
     }
 #pragma unroll
@@ -540,66 +544,88 @@ __global__ __launch_bounds__(kPgoStepThreads) void k_pgo_factor(PgoArgs A, int l
   const int tid = threadIdx.x;
   const PgoDev& G = A.G;
   const PgoWork& W = A.W;
+  // a failed pivot of the wide levels (earlier launches) or of this one,
+  // mirrored in LDS so that the level loop reads no flag from memory
+  __shared__ int sFail;
+  if (tid == 0) sFail = W.istate[4];
+  __syncthreads();
   for (int l = l0; l < G.n_levels; ++l) {
-    if (W.istate[4]) break;
+    if (sFail) break;
     pgo_phase1(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
     pgo_phase1b(G, W, l, tid, kPgoStepThreads);
     __syncthreads();
-    pgo_phase23<false>(G, W, l, tid >> 6, kPgoStepThreads / 64, tid & 63);
+    pgo_phase23<false>(G, W, l, tid >> 6, kPgoStepThreads / 64, tid & 63, &sFail);
     __syncthreads();
   }
-  if (W.istate[4]) {
+  if (sFail) {
     if (tid == 0) {
       W.istate[1] = 0;
       W.istate[3] += 1;
     }
     return;
   }
+  // back substitution, x_c = L_cc^-T (y_c - sum over the column's
+  // off-diagonal blocks of L_rc^T x_r), the blocks in order: six threads per
+  // column, one per row of x_c, each summing its row with two blocks' loads in
+  // flight; then every thread of the column's group solves the 6x6 triangle
+  // from the six sums (through LDS) and keeps its own row
+  __shared__ double sV[kPgoStepThreads];
+  constexpr int kCols = kPgoStepThreads / 6;   // columns per pass
   for (int l = G.n_levels - 1; l >= 0; --l) {
     const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-    const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
-    for (int b = b0 + tid; b < b1; b += kPgoStepThreads) {
-      const int c = G.blk_col[b];
-      if (G.blk_ptr[c] == b) continue;
-      const double* Lb = W.L + 36 * (long long)b;
-      const double* xr = W.x + 6 * G.blk_row[b];
-      double lb[36], xv[6];
+    for (int base = c0; base < c1; base += kCols) {
+      const int a = tid % 6, c = base + tid / 6;
+      const bool act = tid < 6 * kCols && c < c1;
+      double v = 0.0;
+      if (act) {
+        v = W.y[6 * c + a];
+        const int b0 = G.blk_ptr[c] + 1, b1 = G.blk_ptr[c + 1];
+        for (int b = b0; b < b1; b += 2) {
+          int bk[2], rk[2];
 #pragma unroll
-      for (int k = 0; k < 36; ++k) lb[k] = Lb[k];
+          for (int k = 0; k < 2; ++k) {
+            bk[k] = min(b + k, b1 - 1);
+            rk[k] = G.blk_row[bk[k]];
+          }
+          double lv[2][6], xv[2][6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) xv[m] = xr[m];
+          for (int k = 0; k < 2; ++k)
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        double v = 0.0;
+            for (int m = 0; m < 6; ++m) {
+              lv[k][m] = W.L[36 * (long long)bk[k] + 6 * m + a];
+              xv[k][m] = W.x[6 * rk[k] + m];
+            }
 #pragma unroll
-        for (int m = 0; m < 6; ++m) v += lb[6 * m + a] * xv[m];
-        W.bpart[6 * (long long)b + a] = v;
+          for (int k = 0; k < 2; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) t += lv[k][m] * xv[k][m];
+            if (b + k < b1) v -= t;
+          }
+        }
       }
-    }
-    __syncthreads();
-    for (int c = c0 + tid; c < c1; c += kPgoStepThreads) {
-      double v[6];
+      sV[tid] = v;
+      __syncthreads();
+      if (act) {
+        double vv[6];
 #pragma unroll
-      for (int a = 0; a < 6; ++a) v[a] = W.y[6 * c + a];
-      for (int b = G.blk_ptr[c] + 1; b < G.blk_ptr[c + 1]; ++b)
+        for (int q = 0; q < 6; ++q) vv[q] = sV[tid - a + q];
+        const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) v[a] -= W.bpart[6 * (long long)b + a];
-      const double* Lc = W.L + 36 * (long long)G.blk_ptr[c];
-      double m[36];
+        for (int k = 5; k >= 0; --k) {
+          double s = vv[k];
 #pragma unroll
-      for (int k = 0; k < 36; ++k) m[k] = Lc[k];
+          for (int q = k + 1; q < 6; ++q) s -= Lc[6 * q + k] * vv[q];
+          vv[k] = s / Lc[7 * k];
+        }
+        double mine = vv[0];
 #pragma unroll
-      for (int k = 5; k >= 0; --k) {
-        double s = v[k];
-#pragma unroll
-        for (int q = k + 1; q < 6; ++q) s -= m[6 * q + k] * v[q];
-        v[k] = s / m[7 * k];
+        for (int q = 1; q < 6; ++q) mine = a == q ? vv[q] : mine;
+        W.x[6 * c + a] = mine;
       }
-#pragma unroll
-      for (int a = 0; a < 6; ++a) W.x[6 * c + a] = v[a];
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (tid == 0) W.istate[1] = 1;
 }

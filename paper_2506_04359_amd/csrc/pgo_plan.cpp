@@ -309,8 +309,7 @@ size_t pgo_workspace_bytes(const PgoPlan& P) {
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   return 2 * up((size_t)P.n_edges * 28 * 8) + up((size_t)P.n_poses * 12 * 8) +
          up((size_t)P.n_blocks() * 36 * 8) + 2 * up((size_t)P.n_free * 6 * 8) +
-         up(((size_t)P.chunk_blk.size() * 36 + P.fchunk_col.size() * 6) * 8) +
-         up((size_t)P.n_blocks() * 6 * 8) + up(8 * 8) + up(8 * 4);
+         up(((size_t)P.chunk_blk.size() * 36 + P.fchunk_col.size() * 6) * 8) + up(8 * 8) + up(8 * 4);
 }
 
 PgoWork pgo_carve(const PgoPlan& P, void* ws) {
@@ -331,8 +330,6 @@ PgoWork pgo_carve(const PgoPlan& P, void* ws) {
   p += up((size_t)P.n_free * 6 * 8);
   W.part = (double*)p;
   p += up(((size_t)P.chunk_blk.size() * 36 + P.fchunk_col.size() * 6) * 8);
-  W.bpart = (double*)p;
-  p += up((size_t)P.n_blocks() * 6 * 8);
   W.state = (double*)p;
   p += up(8 * 8);
   W.istate = (int32_t*)p;

@@ -57,7 +57,6 @@ struct PgoWork {
   double* y;          // n_free * 6 right-hand side / forward solution
   double* x;          // n_free * 6 step
   double* part;       // n_chunks * 36 + n_fchunks * 6 partial sums of the update chunks
-  double* bpart;      // n_blocks * 6 back-substitution terms L_rc^T x_r
   double* state;      // 8: F, lambda, F0, ...
   int32_t* istate;    // 8: current edge buffer, candidate valid, accepted, chol failures, pivot failed
 };
