@@ -1,7 +1,8 @@
 // gfx950 pose-graph optimisation (paper Sec. 2.3, Eq. 15): LM over the
 // world-from-base poses T_i minimising 1/2 sum_e w_e |Log(D_ij^-1 T_i^-1 T_j)|^2.
 //
-// Per LM attempt five launches:
+// Per LM attempt (besides one k_pgo_wide launch per wide level of the
+// elimination tree):
 //   k_pgo_edges  one thread per edge at the candidate poses: r = Log(E),
 //                E = D^-1 T_i^-1 T_j, B = J_l(r)^-1 Ad(D^-1 T_i^-1) (so dr/dxi_j
 //                = B, dr/dxi_i = -B for the left perturbation), and w B^T B,
@@ -11,11 +12,11 @@
 //                    accept iff it strictly drops, lambda, trace
 //   k_pgo_assemble   the damped normal equations gathered from the current
 //                    edge buffer into the factor's blocks, -g into y
-//   k_pgo_factor     one 1024-thread workgroup: the sparse block Cholesky
-//                    level by level of the elimination tree (left-looking:
-//                    each column gathers its updates, factors its diagonal
-//                    block in registers, solves its panel; the forward
-//                    substitution rides along), then back substitution
+//   k_pgo_wide       the wide levels of the sparse block Cholesky (see below)
+//   k_pgo_factor     one 1024-thread workgroup: the narrow levels (left-
+//                    looking: each column gathers its updates, factors its
+//                    diagonal block in registers, solves its panel; the
+//                    forward substitution rides along), then back substitution
 //   k_pgo_candidate  the next candidate Exp(d_i) T_i
 // Every sum has a fixed order and nothing uses atomics.
 #include <hip/hip_runtime.h>
@@ -353,16 +354,14 @@ __global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_assemble(PgoArgs A) {
 // forward updates L_ck y_k of a right-hand side) is summed by its own thread
 // into a partial; (2) one wave per column subtracts its partials in chunk
 // order, factors the diagonal block in registers, finishes the forward step
-// and solves the column's panel rows.  Wide levels run each of the two phases
-// as a launch over the whole GPU; the narrow ones run in one workgroup, where
-// the partials are first subtracted entry-parallel.  A failed pivot sets
-// istate[4].  Back substitution from the top level down: each off-diagonal
-// block forms L_rc^T x_r, then each column sums them in order and solves.
-__device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
-  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
-  const int q0 = G.chunk_ptr[b0], q1 = G.chunk_ptr[b1];
-  const int f0 = G.fchunk_ptr[c0], f1 = G.fchunk_ptr[c1];
+// and solves the column's panel rows.  A wide level is one launch with a
+// workgroup per column (its chunks, then its first wave does the rest); the
+// narrow ones run in one workgroup, where the partials are first subtracted
+// entry-parallel.  A failed pivot sets istate[4].  Back substitution from the
+// top level down, six threads per column.
+// Phase (1) over the update chunks [q0, q1) and forward chunks [f0, f1).
+__device__ __forceinline__ void pgo_phase1_range(const PgoDev& G, const PgoWork& W, int q0, int q1, int f0, int f1,
+                                                 int t0, int stride) {
   double* fpart = W.part + 36 * (long long)G.n_chunks;
   const int nq = (q1 - q0) * 36;
   for (int t = t0; t < nq + (f1 - f0) * 6; t += stride) {
@@ -414,6 +413,13 @@ __device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, in
       fpart[6 * (long long)fq + a] = acc;
     }
   }
+}
+
+// Phase (1) of level l (all its columns' chunks).
+__device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
+  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+  pgo_phase1_range(G, W, G.chunk_ptr[b0], G.chunk_ptr[b1], G.fchunk_ptr[c0], G.fchunk_ptr[c1], t0, stride);
 }
 
 // The level's partials subtracted from its blocks and right-hand sides, one
@@ -530,13 +536,18 @@ __device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, i
   }
 }
 
-// One phase of one wide level over the whole grid.
-__global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_wide(PgoArgs A, int l, int phase) {
-  const int t0 = blockIdx.x * kPgoEdgeThreads + threadIdx.x, stride = gridDim.x * kPgoEdgeThreads;
-  if (phase == 1)
-    pgo_phase1(A.G, A.W, l, t0, stride);
-  else
-    pgo_phase23<true>(A.G, A.W, l, t0 >> 6, stride >> 6, threadIdx.x & 63);
+// One wide level, one workgroup per column: its update and forward chunks
+// (phase 1), then its first wave subtracts them, factors and solves the
+// panel (phases 2 and 3).  Columns of a level are independent, so a level is
+// one launch.
+__global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_wide(PgoArgs A, int l) {
+  const PgoDev& G = A.G;
+  const int c = G.lev_ptr[l] + blockIdx.x;
+  const int bA = G.blk_ptr[c], bB = G.blk_ptr[c + 1];
+  pgo_phase1_range(G, A.W, G.chunk_ptr[bA], G.chunk_ptr[bB], G.fchunk_ptr[c], G.fchunk_ptr[c + 1], threadIdx.x,
+                   kPgoEdgeThreads);
+  __syncthreads();
+  if (threadIdx.x < 64) pgo_phase23<true>(G, A.W, l, blockIdx.x, gridDim.x, threadIdx.x);
 }
 
 // Levels [l0, n_levels) in one workgroup, then the back substitution.
@@ -659,11 +670,8 @@ hipError_t run_pgo(const PgoArgs& A) {
     // there is nothing to gather
     hipLaunchKernelGGL(k_pgo_assemble, dim3(ab > 0 ? ab : 1), dim3(kPgoEdgeThreads), 0, s, A);
     for (int l = 0; l < A.G.n_wide; ++l) {
-      const int* w = A.wide_tasks + 3 * l;
-      const int b1 = (w[0] + kPgoEdgeThreads - 1) / kPgoEdgeThreads;          // update tasks
-      const int b2 = (64 * w[1] + kPgoEdgeThreads - 1) / kPgoEdgeThreads;     // one wave per column
-      if (b1 > 0) hipLaunchKernelGGL(k_pgo_wide, dim3(b1), dim3(kPgoEdgeThreads), 0, s, A, l, 1);
-      if (b2 > 0) hipLaunchKernelGGL(k_pgo_wide, dim3(b2), dim3(kPgoEdgeThreads), 0, s, A, l, 2);
+      const int* w = A.wide_tasks + 3 * l;   // w[1]: the level's columns
+      if (w[1] > 0) hipLaunchKernelGGL(k_pgo_wide, dim3(w[1]), dim3(kPgoEdgeThreads), 0, s, A, l);
     }
     hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(kPgoStepThreads), 0, s, A, A.G.n_wide);
     hipLaunchKernelGGL(k_pgo_candidate, dim3(pb), dim3(kPgoEdgeThreads), 0, s, A);
