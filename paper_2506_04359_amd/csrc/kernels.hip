@@ -1045,6 +1045,21 @@ __global__ __launch_bounds__(TP, (sizeof(Real) == 4 ? 2 : 1)) void k_pass_a(DevP
 // ---------------------------------------------------------------------------
 
 
+// LDS stride of a 6x6 block in the reduction workgroup: dense, so every row
+// pair of a block starts 16 bytes aligned and is read with one 128-bit LDS
+// read (the chunk partials keep the odd stride kBS, which spreads the banks of
+// the accumulating workgroups).
+constexpr int kRS = 36;
+
+// Waits for the LDS reads that produced v before anything that uses v: the
+// reads of a step are issued together and waited for once, instead of the
+// compiler's interleaving of each read with its first use.
+template <int N>
+__device__ __forceinline__ void lds_fence(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) __asm__ volatile("" : "+v"(v[i]));
+}
+
 // Upper Cholesky of one symmetric 6x6 block, by one wave: lane l < 36 brings
 // entry (l / 6, l % 6).  Writes the upper triangle of R to D and 1 / R_pp to
 // inv; raises *fail on a non-positive or non-finite pivot.  The lanes put
@@ -1061,6 +1076,7 @@ __device__ __forceinline__ void factor_diag(double a, double* D, double* inv, in
   for (int p = 0, e = 0; p < 6; ++p)
 #pragma unroll
     for (int q = p; q < 6; ++q, ++e) R[e] = D[6 * p + q];
+  lds_fence(R);
   __builtin_amdgcn_wave_barrier();
   double ir6[6];
 #pragma unroll
@@ -1183,8 +1199,8 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   WinState& st = K.state[wi];
   const int tid = threadIdx.x;
   const int nf = W.n_free, nblk = nf * (nf + 1) / 2, nS = 6 * nf;
-  double* sS = reinterpret_cast<double*>(smem);   // nblk * kBS
-  double* sB = sS + nblk * kBS;                   // nS
+  double* sS = reinterpret_cast<double*>(smem);   // nblk * kRS
+  double* sB = sS + nblk * kRS;                   // nS
   double* sD = sB + nS;                           // nS
   double* sInv = sD + nS;                         // nS: 1 / R_pp of the diagonal blocks
   int* sFail = reinterpret_cast<int*>(sInv + nS); // 2 ints (one double): failure, freeze
@@ -1210,8 +1226,10 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     }
   }
   {
-    // eight loads in flight per thread (the system is up to 160 KB)
+    // eight loads in flight per thread (the system is up to 160 KB); the
+    // blocks move from the summed partials' stride kBS to the dense kRS
     const double* src = K.ssum + W.sum_off;
+    const int nb = nblk * kBS;
     constexpr int B = 8;
     for (int base = 0; base < ne; base += B * NT) {
       double v[B];
@@ -1223,7 +1241,13 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int e = base + tid + b * NT;
-        if (e < ne) sS[e] = v[b];
+        if (e >= ne) continue;
+        if (e < nb) {
+          const int blk = e / kBS, r = e - kBS * blk;
+          if (r < 36) sS[kRS * blk + r] = v[b];
+        } else {
+          sS[nblk * kRS + (e - nb)] = v[b];
+        }
       }
     }
   }
@@ -1268,7 +1292,7 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     for (int e = tid; e < nS; e += NT) {
       const int f = e / 6, r = e % 6;
       const double d = sD[e];
-      sS[kBS * blk_index(f, f, nf) + 7 * r] += lam * (d > 1e-9 ? d : 1e-9);
+      sS[kRS * blk_index(f, f, nf) + 7 * r] += lam * (d > 1e-9 ? d : 1e-9);
     }
   }
   __syncthreads();
@@ -1276,7 +1300,7 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   for (int e = tid; e < nf * 36; e += NT) {
     const int f = e / 36, r = (e % 36) / 6, c = e % 6;
     if (c < r) {
-      double* D = sS + kBS * blk_index(f, f, nf);
+      double* D = sS + kRS * blk_index(f, f, nf);
       D[6 * r + c] = D[6 * c + r];
     }
   }
@@ -1291,13 +1315,13 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
   const int lr = lane / 6, lc = lane - 6 * (lane / 6);   // entry of a 6x6 block (lanes 0..35)
   bool failed = sFail[0] != 0;
   if (!failed && nf > 0 && wave == 0) {
-    double a = lane < 36 ? sS[kBS * blk_index(0, 0, nf) + lane] : 0.0;
-    factor_diag(a, sS + kBS * blk_index(0, 0, nf), sInv, sFail);
+    double a = lane < 36 ? sS[kRS * blk_index(0, 0, nf) + lane] : 0.0;
+    factor_diag(a, sS + kRS * blk_index(0, 0, nf), sInv, sFail);
   }
   __syncthreads();
   failed = sFail[0] != 0;
   for (int k = 0; k < nf && !failed; ++k) {
-    const double* Dk = sS + kBS * blk_index(k, k, nf);
+    const double* Dk = sS + kRS * blk_index(k, k, nf);
     const double* ik = sInv + 6 * k;
     const int nt = nf - k - 1;
     // panel: R_kj = R_kk^-T S_kj for j > k, one thread per column; the last
@@ -1306,19 +1330,31 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
       double* B;
       int stride;
       if (e < 6 * nt) {
-        B = sS + kBS * blk_index(k, k + 1 + e / 6, nf) + e % 6;
+        B = sS + kRS * blk_index(k, k + 1 + e / 6, nf) + e % 6;
         stride = 6;
       } else {
         B = sB + 6 * k;
         stride = 1;
       }
+      double col[6], dku[15], iv[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) col[i] = B[stride * i];
+#pragma unroll
+      for (int i = 1, q = 0; i < 6; ++i)
+#pragma unroll
+        for (int m = 0; m < i; ++m, ++q) dku[q] = Dk[6 * m + i];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) iv[i] = ik[i];
+      lds_fence(col);
+      lds_fence(dku);
+      lds_fence(iv);
       double y[6];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        double v = B[stride * i];
+      for (int i = 0, q = 0; i < 6; ++i) {
+        double v = col[i];
 #pragma unroll
-        for (int m = 0; m < i; ++m) v -= Dk[6 * m + i] * y[m];
-        y[i] = v * ik[i];
+        for (int m = 0; m < i; ++m, ++q) v -= dku[q] * y[m];
+        y[i] = v * iv[i];
       }
 #pragma unroll
       for (int i = 0; i < 6; ++i) B[stride * i] = y[i];
@@ -1327,58 +1363,105 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     if (wave == 0) {
       // look-ahead: update and factor the next diagonal block
       if (nt > 0) {
-        const double* R = sS + kBS * blk_index(k, k + 1, nf);
-        double* Dn = sS + kBS * blk_index(k + 1, k + 1, nf);
+        const double* R = sS + kRS * blk_index(k, k + 1, nf);
+        double* Dn = sS + kRS * blk_index(k + 1, k + 1, nf);
         double a = 0.0;
         if (lane < 36) {
+          double ra[6], rb[6], dn[1];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            ra[m] = R[6 * m + lr];
+            rb[m] = R[6 * m + lc];
+          }
+          dn[0] = Dn[lane];
+          lds_fence(ra);
+          lds_fence(rb);
+          lds_fence(dn);
           double acc = 0.0;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) acc += R[6 * m + lr] * R[6 * m + lc];
-          a = Dn[lane] - acc;
+          for (int m = 0; m < 6; ++m) acc += ra[m] * rb[m];
+          a = dn[0] - acc;
         }
         factor_diag(a, Dn, sInv + 6 * (k + 1), sFail);
       }
     } else {
       // trailing update S_ij -= R_ki^T R_kj over the upper pairs k < i <= j
-      // except the next diagonal block, then b_i -= R_ki^T y_k
+      // except the next diagonal block, then b_i -= R_ki^T y_k.  An item is
+      // three rows of one block, rows 4h, 4h + 1 and 2 + h of half h (so a
+      // row pair is one 128-bit read), two items per block; each item issues
+      // all of its reads before its first product.
       const int npair = nt * (nt + 1) / 2 - 1;
-      for (int e = tid - 64; e < npair + nt; e += NT - 64) {
-        if (e < npair) {
-          int i, j;
-          upper_pair(e + 1, nt, i, j);
-          const double* A = sS + kBS * blk_index(k, k + 1 + i, nf);
-          const double* Bm = sS + kBS * blk_index(k, k + 1 + j, nf);
-          double acc[36];
+      for (int e = tid - 64; e < 2 * (npair + nt); e += NT - 64) {
+        const int h = e & 1;
+        const int r0 = 4 * h, r2 = 2 + h;
+        int i, j;
+        const bool rhs = e >= 2 * npair;
+        if (rhs) {
+          i = (e - 2 * npair) >> 1;
+          j = 0;
+        } else {
+          upper_pair((e >> 1) + 1, nt, i, j);
+        }
+        const double* A = sS + kRS * blk_index(k, k + 1 + i, nf);
+        double u[6][3];
 #pragma unroll
-          for (int x = 0; x < 36; ++x) acc[x] = 0.0;
+        for (int m = 0; m < 6; ++m) {
+          const double2 a01 = *reinterpret_cast<const double2*>(A + 6 * m + r0);
+          u[m][0] = a01.x;
+          u[m][1] = a01.y;
+          u[m][2] = A[6 * m + r2];
+        }
+        if (!rhs) {
+          const double* Bm = sS + kRS * blk_index(k, k + 1 + j, nf);
+          double* D = sS + kRS * blk_index(k + 1 + i, k + 1 + j, nf);
+          double v[6][6], d[18];
 #pragma unroll
-          for (int m = 0; m < 6; ++m) {
-            double u[6], v[6];
+          for (int m = 0; m < 6; ++m)
 #pragma unroll
-            for (int x = 0; x < 6; ++x) {
-              u[x] = A[6 * m + x];
-              v[x] = Bm[6 * m + x];
+            for (int c = 0; c < 6; c += 2) {
+              const double2 b2 = *reinterpret_cast<const double2*>(Bm + 6 * m + c);
+              v[m][c] = b2.x;
+              v[m][c + 1] = b2.y;
             }
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-              for (int c = 0; c < 6; ++c) acc[6 * r + c] += u[r] * v[c];
+          for (int c = 0; c < 12; c += 2) {
+            const double2 d2 = *reinterpret_cast<const double2*>(D + 6 * r0 + c);
+            d[c] = d2.x;
+            d[c + 1] = d2.y;
           }
-          double* D = sS + kBS * blk_index(k + 1 + i, k + 1 + j, nf);
 #pragma unroll
-          for (int x = 0; x < 36; ++x) D[x] -= acc[x];
+          for (int c = 0; c < 6; c += 2) {
+            const double2 d2 = *reinterpret_cast<const double2*>(D + 6 * r2 + c);
+            d[12 + c] = d2.x;
+            d[13 + c] = d2.y;
+          }
+          double acc[18];
+#pragma unroll
+          for (int x = 0; x < 18; ++x) acc[x] = 0.0;
+#pragma unroll
+          for (int m = 0; m < 6; ++m)
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) acc[6 * r + c] += u[m][r] * v[m][c];
+#pragma unroll
+          for (int c = 0; c < 12; c += 2)
+            *reinterpret_cast<double2*>(D + 6 * r0 + c) = make_double2(d[c] - acc[c], d[c + 1] - acc[c + 1]);
+#pragma unroll
+          for (int c = 0; c < 6; c += 2)
+            *reinterpret_cast<double2*>(D + 6 * r2 + c) =
+                make_double2(d[12 + c] - acc[12 + c], d[13 + c] - acc[13 + c]);
         } else {
-          const int i = e - npair;
-          const double* A = sS + kBS * blk_index(k, k + 1 + i, nf);
           double yk[6];
 #pragma unroll
           for (int m = 0; m < 6; ++m) yk[m] = sB[6 * k + m];
+          double* bi = sB + 6 * (k + 1 + i);
 #pragma unroll
-          for (int r = 0; r < 6; ++r) {
+          for (int r = 0; r < 3; ++r) {
             double v = 0.0;
 #pragma unroll
-            for (int m = 0; m < 6; ++m) v += A[6 * m + r] * yk[m];
-            sB[6 * (k + 1 + i) + r] -= v;
+            for (int m = 0; m < 6; ++m) v += u[m][r] * yk[m];
+            bi[r == 0 ? r0 : (r == 1 ? r0 + 1 : r2)] -= v;
           }
         }
       }
@@ -1386,42 +1469,61 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
     __syncthreads();
     failed = sFail[0] != 0;
   }
-  if (!failed && wave == 0) {
-    // back substitution R x = y in one wave: lane l keeps rows l, l + 64, l + 128
-    double y0 = lane < nS ? sB[lane] : 0.0;
-    double y1 = lane + 64 < nS ? sB[lane + 64] : 0.0;
-    double y2 = lane + 128 < nS ? sB[lane + 128] : 0.0;
+  if (!failed && wave == 0 && nf > 0) {
+    // back substitution R x = y in one wave.  Lane l keeps rows 3 l .. 3 l + 2
+    // (all three in block row l / 2), so the rows of block k sit in lanes
+    // 2 k and 2 k + 1 at register positions known at compile time, and x
+    // replaces y there.  A block issues its reads and broadcasts together and
+    // waits for them once; the column reads are waited for only after the
+    // block's serial chain.
+    double y[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) y[t] = 3 * lane + t < nS ? sB[3 * lane + t] : 0.0;
     for (int k = nf - 1; k >= 0; --k) {
-      const double* Dk = sS + kBS * blk_index(k, k, nf);
+      const double* Dk = sS + kRS * blk_index(k, k, nf);
+      double dku[15], iv[6], yv[6], bv[18];
+#pragma unroll
+      for (int i = 0, q = 0; i < 6; ++i)
+#pragma unroll
+        for (int m = i + 1; m < 6; ++m, ++q) dku[q] = Dk[6 * i + m];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) iv[i] = sInv[6 * k + i];
+      {
+        // lanes at or past block row k are not updated; they read block row 0
+        const int l = lane < 2 * k ? lane : 0;
+        const double* B = sS + kRS * blk_index(l >> 1, k, nf) + 18 * (l & 1);
+#pragma unroll
+        for (int m = 0; m < 18; m += 2) {
+          const double2 b2 = *reinterpret_cast<const double2*>(B + m);
+          bv[m] = b2.x;
+          bv[m + 1] = b2.y;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) yv[i] = wave_bcast(y[i % 3], 2 * k + i / 3);
+      lds_fence(dku);
+      lds_fence(iv);
+      lds_fence(yv);
       double x[6];
 #pragma unroll
       for (int i = 5; i >= 0; --i) {
-        const int row = 6 * k + i;
-        const int sel = row >> 6;
-        const double own = sel == 0 ? y0 : (sel == 1 ? y1 : y2);
-        double v = wave_bcast(own, row & 63);
+        double v = yv[i];
+        // dku holds row i's entries m = i + 1 .. 5 at q0(i) .. q0(i) + 4 - i
+        const int q0 = 5 * i - i * (i - 1) / 2;
 #pragma unroll
-        for (int m = i + 1; m < 6; ++m) v -= Dk[6 * i + m] * x[m];
-        x[i] = v * sInv[row];
+        for (int m = i + 1; m < 6; ++m) v -= dku[q0 + m - i - 1] * x[m];
+        x[i] = v * iv[i];
       }
-      const int lim = 6 * k;
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        const int row = lane + 64 * t;
-        if (row < lim) {
-          const double* B = sS + kBS * blk_index(row / 6, k, nf) + 6 * (row % 6);
-          const double d = B[0] * x[0] + B[1] * x[1] + B[2] * x[2] + B[3] * x[3] + B[4] * x[4] +
-                           B[5] * x[5];
-          if (t == 0) y0 -= d;
-          else if (t == 1) y1 -= d;
-          else y2 -= d;
-        }
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) sB[6 * k + i] = x[i];
+        const double d = bv[6 * t] * x[0] + bv[6 * t + 1] * x[1] + bv[6 * t + 2] * x[2] +
+                         bv[6 * t + 3] * x[3] + bv[6 * t + 4] * x[4] + bv[6 * t + 5] * x[5];
+        y[t] = lane < 2 * k ? y[t] - d : (lane == 2 * k ? x[t] : (lane == 2 * k + 1 ? x[3 + t] : y[t]));
       }
     }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (3 * lane + t < nS) sB[3 * lane + t] = y[t];
   }
   __syncthreads();
   double* dp = K.dp + kDpStride * wi;
@@ -1851,7 +1953,7 @@ size_t pass_b_lds() {
 // The reduce kernel's LDS: the reduced system of the largest window.
 size_t reduce_lds(int max_nf) {
   const int nblk = max_nf * (max_nf + 1) / 2;
-  return (size_t)(nblk * kBS + 18 * max_nf + 11) * sizeof(double);
+  return (size_t)(nblk * kRS + 18 * max_nf + 11) * sizeof(double);
 }
 
 constexpr int kReduceThreads = 512;
