@@ -1068,7 +1068,6 @@ __device__ __forceinline__ void lds_fence(double (&v)[N]) {
 // traffic.
 __device__ __forceinline__ void factor_diag(double a, double* D, double* inv, int* fail) {
   const int lane = threadIdx.x & 63;
-  const int r = lane / 6, c = lane - 6 * (lane / 6);
   if (lane < 36) D[lane] = a;
   __builtin_amdgcn_wave_barrier();
   double R[21];   // upper triangle, row-major: row p starts at 6 p - p (p - 1) / 2
@@ -1099,24 +1098,111 @@ __device__ __forceinline__ void factor_diag(double a, double* D, double* inv, in
       for (int q = x; q < 6; ++q) R[rx + q - x] -= R[rp + x - p] * R[rp + q - p];
     }
   }
-  if (lane < 6) {
-    double v = ir6[0];
-#pragma unroll
-    for (int p = 1; p < 6; ++p) v = lane == p ? ir6[p] : v;
-    inv[lane] = v;
-  }
-  if (lane < 36 && c >= r) {
-    double v = 0.0;
+  // every lane holds the same factor: lane 0 stores it (27 stores instead of
+  // a per-lane selection of its entry)
+  if (lane == 0) {
 #pragma unroll
     for (int p = 0, e = 0; p < 6; ++p)
 #pragma unroll
-      for (int q = p; q < 6; ++q, ++e) v = (r == p && c == q) ? R[e] : v;
-    D[lane] = v;
+      for (int q = p; q < 6; ++q, ++e) D[6 * p + q] = R[e];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) inv[p] = ir6[p];
   }
 }
 
-// Pair (i, j), i <= j < n, of index e in the row-major upper triangle of an
-// n x n grid (row i starts at i*n - i*(i-1)/2).
+// One item of the trailing update of step k of the blocked Cholesky in the
+// reduction workgroup: RG rows of one block of the upper pairs k < i <= j
+// (S_ij -= R_ki^T R_kj; the next diagonal block is excluded), or, past the
+// npair blocks, of the right-hand side (b_i -= R_ki^T y_k).  A block splits
+// into 6 / RG items: rows 4s, 4s + 1, 2 + s for RG = 3, rows 2s, 2s + 1 for
+// RG = 2, row s for RG = 1, so a row pair is one 128-bit read.  Every read is
+// issued before the first product; each entry is summed over m in order and
+// then subtracted, whatever RG.
+template <int RG>
+__device__ __forceinline__ void trail_item(double* sS, double* sB, int k, int nf, int nt, int npair, int e) {
+  constexpr int G = 6 / RG;
+  const int sub = e % G, blkno = e / G;
+  int rows[3];
+  if (RG == 3) {
+    rows[0] = 4 * sub;
+    rows[1] = 4 * sub + 1;
+    rows[2] = 2 + sub;
+  } else if (RG == 2) {
+    rows[0] = 2 * sub;
+    rows[1] = 2 * sub + 1;
+    rows[2] = 0;
+  } else {
+    rows[0] = sub;
+    rows[1] = rows[2] = 0;
+  }
+  const bool rhs = blkno >= npair;
+  int i, j = 0;
+  if (rhs) i = blkno - npair;
+  else upper_pair(blkno + 1, nt, i, j);
+  const double* A = sS + kRS * blk_index(k, k + 1 + i, nf);
+  double u[6][RG];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    if (RG >= 2) {
+      const double2 a01 = *reinterpret_cast<const double2*>(A + 6 * m + rows[0]);
+      u[m][0] = a01.x;
+      u[m][1] = a01.y;
+      if (RG == 3) u[m][RG - 1] = A[6 * m + rows[2]];
+    } else {
+      u[m][0] = A[6 * m + rows[0]];
+    }
+  }
+  if (!rhs) {
+    const double* Bm = sS + kRS * blk_index(k, k + 1 + j, nf);
+    double* D = sS + kRS * blk_index(k + 1 + i, k + 1 + j, nf);
+    double v[6][6], d[RG][6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int c = 0; c < 6; c += 2) {
+        const double2 b2 = *reinterpret_cast<const double2*>(Bm + 6 * m + c);
+        v[m][c] = b2.x;
+        v[m][c + 1] = b2.y;
+      }
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; c += 2) {
+        const double2 d2 = *reinterpret_cast<const double2*>(D + 6 * rows[r] + c);
+        d[r][c] = d2.x;
+        d[r][c + 1] = d2.y;
+      }
+    double acc[RG][6];
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[r][c] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[r][c] += u[m][r] * v[m][c];
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; c += 2)
+        *reinterpret_cast<double2*>(D + 6 * rows[r] + c) =
+            make_double2(d[r][c] - acc[r][c], d[r][c + 1] - acc[r][c + 1]);
+  } else {
+    double yk[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) yk[m] = sB[6 * k + m];
+    double* bi = sB + 6 * (k + 1 + i);
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) v += u[m][r] * yk[m];
+      bi[rows[r]] -= v;
+    }
+  }
+}
 
 // Sum of a window's chunk partials in FP64 (grid: windows x slices).  The
 // workgroup's 256 threads form G = W.sum_groups groups of 256 / G entry
@@ -1385,86 +1471,10 @@ __global__ __launch_bounds__(NT) void k_reduce(DevPlan P, DevTiles T, DevWork<Re
         factor_diag(a, Dn, sInv + 6 * (k + 1), sFail);
       }
     } else {
-      // trailing update S_ij -= R_ki^T R_kj over the upper pairs k < i <= j
-      // except the next diagonal block, then b_i -= R_ki^T y_k.  An item is
-      // three rows of one block, rows 4h, 4h + 1 and 2 + h of half h (so a
-      // row pair is one 128-bit read), two items per block; each item issues
-      // all of its reads before its first product.
+      // trailing update over the npair upper blocks and the nt right-hand
+      // side blocks, two items of three rows per block
       const int npair = nt * (nt + 1) / 2 - 1;
-      for (int e = tid - 64; e < 2 * (npair + nt); e += NT - 64) {
-        const int h = e & 1;
-        const int r0 = 4 * h, r2 = 2 + h;
-        int i, j;
-        const bool rhs = e >= 2 * npair;
-        if (rhs) {
-          i = (e - 2 * npair) >> 1;
-          j = 0;
-        } else {
-          upper_pair((e >> 1) + 1, nt, i, j);
-        }
-        const double* A = sS + kRS * blk_index(k, k + 1 + i, nf);
-        double u[6][3];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          const double2 a01 = *reinterpret_cast<const double2*>(A + 6 * m + r0);
-          u[m][0] = a01.x;
-          u[m][1] = a01.y;
-          u[m][2] = A[6 * m + r2];
-        }
-        if (!rhs) {
-          const double* Bm = sS + kRS * blk_index(k, k + 1 + j, nf);
-          double* D = sS + kRS * blk_index(k + 1 + i, k + 1 + j, nf);
-          double v[6][6], d[18];
-#pragma unroll
-          for (int m = 0; m < 6; ++m)
-#pragma unroll
-            for (int c = 0; c < 6; c += 2) {
-              const double2 b2 = *reinterpret_cast<const double2*>(Bm + 6 * m + c);
-              v[m][c] = b2.x;
-              v[m][c + 1] = b2.y;
-            }
-#pragma unroll
-          for (int c = 0; c < 12; c += 2) {
-            const double2 d2 = *reinterpret_cast<const double2*>(D + 6 * r0 + c);
-            d[c] = d2.x;
-            d[c + 1] = d2.y;
-          }
-#pragma unroll
-          for (int c = 0; c < 6; c += 2) {
-            const double2 d2 = *reinterpret_cast<const double2*>(D + 6 * r2 + c);
-            d[12 + c] = d2.x;
-            d[13 + c] = d2.y;
-          }
-          double acc[18];
-#pragma unroll
-          for (int x = 0; x < 18; ++x) acc[x] = 0.0;
-#pragma unroll
-          for (int m = 0; m < 6; ++m)
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-              for (int c = 0; c < 6; ++c) acc[6 * r + c] += u[m][r] * v[m][c];
-#pragma unroll
-          for (int c = 0; c < 12; c += 2)
-            *reinterpret_cast<double2*>(D + 6 * r0 + c) = make_double2(d[c] - acc[c], d[c + 1] - acc[c + 1]);
-#pragma unroll
-          for (int c = 0; c < 6; c += 2)
-            *reinterpret_cast<double2*>(D + 6 * r2 + c) =
-                make_double2(d[12 + c] - acc[12 + c], d[13 + c] - acc[13 + c]);
-        } else {
-          double yk[6];
-#pragma unroll
-          for (int m = 0; m < 6; ++m) yk[m] = sB[6 * k + m];
-          double* bi = sB + 6 * (k + 1 + i);
-#pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            double v = 0.0;
-#pragma unroll
-            for (int m = 0; m < 6; ++m) v += u[m][r] * yk[m];
-            bi[r == 0 ? r0 : (r == 1 ? r0 + 1 : r2)] -= v;
-          }
-        }
-      }
+      for (int e = tid - 64; e < 2 * (npair + nt); e += NT - 64) trail_item<3>(sS, sB, k, nf, nt, npair, e);
     }
     __syncthreads();
     failed = sFail[0] != 0;
