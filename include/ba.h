@@ -262,7 +262,7 @@ ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double
  * stage and size class).  Defaults: chunk_obs from the plan's size,
  * tile_pairs 0, every class_chunk_mult 1, class_streams 1. */
 typedef struct {
-  int32_t chunk_obs;            /* target observations per work item, 512..65536 */
+  int32_t chunk_obs;            /* target observations per work item, 128..65536 */
   int32_t tile_pairs;           /* pairs per tile: 0 = 256 when its LDS fits, else 64; or 64 / 256 */
   int32_t class_chunk_mult[4];  /* per size class (up to 8, 16, 23, 32 free poses): work items of
                                    about class_chunk_mult x chunk_obs observations, 1..4 */

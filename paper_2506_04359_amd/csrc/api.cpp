@@ -47,7 +47,7 @@ template <typename Real, int TP>
 hipError_t run_solve_timed(const LaunchArgs& A, const DevWork<Real>& K, double* stage_ms);
 
 constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kChunkMin = 512;
+constexpr int kChunkMin = 128;
 constexpr int kChunkMax = 65536;
 
 thread_local std::string g_error;
@@ -250,7 +250,13 @@ ba_status upload_tables(ba_batch_s* b, int which, int tp, int chunk_obs) {
   return BA_OK;
 }
 
-int default_chunk_obs(int64_t n_obs) {
+// Work-item size of a new plan.  Many windows fill the GPU with whole windows,
+// so their work items aim at n_obs / 1024 observations (1024 .. 8192).  A
+// plan of one window has nothing to run beside it: its work items aim at one
+// per CU (n_obs / 256, 128 .. 8192 observations; a work item is at least one
+// tile), which spreads the window's latency-bound tiles over the chip.
+int default_chunk_obs(int64_t n_obs, size_t n_windows) {
+  if (n_windows == 1) return (int)std::min<int64_t>(8192, std::max<int64_t>(128, n_obs / 256));
   const int64_t c = n_obs / 1024;
   return (int)std::min<int64_t>(8192, std::max<int64_t>(1024, c));
 }
@@ -317,7 +323,7 @@ ba_status batch_build(std::vector<HostWindow>&& wins, ba_batch_s** out) {
   b->plan.obs_cam = (const uint8_t*)(m + o_oc);
   b->plan.obs_perm = (const int32_t*)(m + o_op);
   b->plan.n_windows = (int32_t)b->wins.size();
-  b->chunk_obs = default_chunk_obs(b->n_obs);
+  b->chunk_obs = default_chunk_obs(b->n_obs, b->wins.size());
   ba_status s = upload_tables(b.get(), 0, kTileSmall, b->chunk_obs);
   if (s != BA_OK) return s;
   s = upload_tables(b.get(), 1, kTileLarge, b->chunk_obs);
@@ -1010,7 +1016,7 @@ ba_status ba_window_info(ba_window w, ba_plan_info* info) {
   if (!w || !info) return set_error(BA_ERR_INVALID_ARG, "NULL argument");
   std::vector<const HostWindow*> one{&w->host};
   LaunchTables t;
-  build_tiles(one, kTileLarge, default_chunk_obs(w->host.n_obs), t);
+  build_tiles(one, kTileLarge, default_chunk_obs(w->host.n_obs, 1), t);
   fill_info(w->host, t.n_tiles(), t.n_chunks(), info);
   return BA_OK;
 }
