@@ -511,24 +511,78 @@ __global__ __launch_bounds__(64) void k_vi_fac(ViArgs V, int wbase) {
 __device__ inline int hx_row(int q) { return q < 6 ? q : 9 + q; }
 __device__ inline int hy_col(int c) { return c < 9 ? 6 + c : 12 + c; }
 
-// x = L^-1 x and x = L^-T x for a 9x9 Cholesky factor with its reciprocal diagonal
-__device__ void lsolve9(const double* L, const double* inv, double* x) {
+// Cholesky of a 9x9 block held in registers (lower part), the pivots by the
+// refined rsqrt: L_jj = d rsqrt(d) and inv_j = rsqrt(d) (no square root or
+// division on the pivot chain).  False on a non-positive or non-finite pivot.
+__device__ __forceinline__ bool chol9_regs(double (&A)[81], double (&inv)[9]) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    double d = A[10 * j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= A[9 * j + k] * A[9 * j + k];
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    const double ir = rsqrt(d);
+    A[10 * j] = d * ir;
+    inv[j] = ir;
+#pragma unroll
+    for (int i = j + 1; i < 9; ++i) {
+      double v = A[9 * i + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= A[9 * i + k] * A[9 * j + k];
+      A[9 * i + j] = v * ir;
+    }
+  }
+  return true;
+}
+
+// Waits for the LDS reads that produced v before anything that uses v (the
+// reads are issued together and waited for once).
+template <int N>
+__device__ __forceinline__ void vi_lds_fence(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) __asm__ volatile("" : "+v"(v[i]));
+}
+
+// A 9x9 Cholesky factor's strictly lower entries (row i, column k < i at
+// i (i - 1) / 2 + k) and reciprocal diagonal, read from LDS together and
+// waited for once, then the two triangular solves on registers.
+struct L9 {
+  double l[36], inv[9];
+};
+__device__ __forceinline__ void load_l9(const double* L, const double* inv, L9& F) {
+#pragma unroll
+  for (int i = 1, q = 0; i < 9; ++i)
+#pragma unroll
+    for (int k = 0; k < i; ++k, ++q) F.l[q] = L[9 * i + k];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) F.inv[i] = inv[i];
+  vi_lds_fence(F.l);
+  vi_lds_fence(F.inv);
+}
+__device__ __forceinline__ void lsolve9r(const L9& F, double (&x)[9]) {
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     double v = x[i];
-    for (int k = 0; k < i; ++k) v -= L[9 * i + k] * x[k];
-    x[i] = v * inv[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= F.l[i * (i - 1) / 2 + k] * x[k];
+    x[i] = v * F.inv[i];
   }
 }
-
-__device__ void ltsolve9(const double* L, const double* inv, double* x) {
+__device__ __forceinline__ void ltsolve9r(const L9& F, double (&x)[9]) {
+#pragma unroll
   for (int i = 8; i >= 0; --i) {
     double v = x[i];
-    for (int k = i + 1; k < 9; ++k) v -= L[9 * k + i] * x[k];
-    x[i] = v * inv[i];
+#pragma unroll
+    for (int k = i + 1; k < 9; ++k) v -= F.l[k * (k - 1) / 2 + i] * x[k];
+    x[i] = v * F.inv[i];
   }
 }
 
-__global__ __launch_bounds__(256) void k_vi_lin(ViArgs V, int wbase) {
+constexpr int kViLinThreads = 256;   // threads of the elimination workgroup
+
+template <bool XL>
+__global__ __launch_bounds__(kViLinThreads) void k_vi_lin(ViArgs V, int wbase) {
+  extern __shared__ __align__(16) double sXd[];     // X when it fits in LDS (XL)
   __shared__ double sA[kViMaxStates * 81];          // A_kk (damped), then its Cholesky factor L_k
   __shared__ double sO[(kViMaxStates - 1) * 81];    // A_{k,k+1}
   __shared__ double sC[kViMaxStates * 81];          // C_k = A_{k,k-1} L_{k-1}^-T, k >= 1
@@ -543,66 +597,132 @@ __global__ __launch_bounds__(256) void k_vi_lin(ViArgs V, int wbase) {
   const int tid = threadIdx.x;
   const int N = W.n_poses, nf = N - 1, nS = 6 * W.n_free, ncol = nS + 1;
   const double* F = V.rec;                           // per factor records
-  double* X = V.rec + (size_t)kViFactorStride * nf;  // 9N x (nS + 1): A^-1 H_yx, then z = A^-1 g_y
+  // 9N x (nS + 1): A^-1 H_yx, then z = A^-1 g_y; worked on in LDS when it
+  // fits (XL) and copied out at the end, since k_vi_cand reads it
+  double* Xg = V.rec + (size_t)kViFactorStride * nf;
+  double* X = XL ? sXd : Xg;
   const int* fs = V.free_slot + W.pose_off;
   if (tid < N && fs[tid] >= 0) sPose[fs[tid]] = tid;
   if (tid == 0) sOk = 1;
-  // 1. stage A = H_yy + damping (block tridiagonal), H_xy and g_y
+  // 1. stage A = H_yy + damping (block tridiagonal), A_{k,k+1}, H_xy and g_y:
+  //    one index space over the four arrays, eight elements per thread and
+  //    round, a round's reads (two per element, unconditional: an unused one
+  //    reads F[0]) all in flight before its first LDS store
   const double lam = st.lambda;
-  for (int e = tid; e < N * 81; e += blockDim.x) {
-    const int k = e / 81, x = (e % 81) / 9, y = e % 9;
-    double v = 0.0;
-    if (k >= 1) v += F[(size_t)kViFactorStride * (k - 1) + kFH + 30 * (21 + x) + 21 + y];
-    if (k < nf) v += F[(size_t)kViFactorStride * k + kFH + 30 * (6 + x) + 6 + y];
-    if (x == y) v += lam * fmax(v, 1e-9);
-    sA[e] = v;
-  }
-  for (int e = tid; e < nf * 81; e += blockDim.x) {
-    const int f = e / 81, x = (e % 81) / 9, y = e % 9;
-    sO[e] = F[(size_t)kViFactorStride * f + kFH + 30 * (6 + x) + 21 + y];
-  }
-  for (int e = tid; e < nf * 216; e += blockDim.x) {
-    const int f = e / 216, q = (e % 216) / 18, c = e % 18;
-    sH[e] = F[(size_t)kViFactorStride * f + kFH + 30 * hx_row(q) + hy_col(c)];
-  }
-  for (int e = tid; e < N * 9; e += blockDim.x) {
-    const int k = e / 9, x = e % 9;
-    double v = 0.0;
-    if (k >= 1) v += F[(size_t)kViFactorStride * (k - 1) + kFg + 21 + x];
-    if (k < nf) v += F[(size_t)kViFactorStride * k + kFg + 6 + x];
-    sG[e] = v;
+  {
+    const int nA = N * 81, nO = nf * 81, nH = nf * 216, nG = N * 9, ntot = nA + nO + nH + nG;
+    constexpr int R = 8;
+    for (int base = 0; base < ntot; base += R * blockDim.x) {
+      long long i0[R], i1[R];
+      double v0[R], v1[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = base + tid + r * (int)blockDim.x;
+        i0[r] = -1;
+        i1[r] = -1;
+        if (e < nA) {
+          const int k = e / 81, x = (e % 81) / 9, y = e % 9;
+          if (k >= 1) i0[r] = (long long)kViFactorStride * (k - 1) + kFH + 30 * (21 + x) + 21 + y;
+          if (k < nf) i1[r] = (long long)kViFactorStride * k + kFH + 30 * (6 + x) + 6 + y;
+        } else if (e < nA + nO) {
+          const int t = e - nA, f = t / 81, x = (t % 81) / 9, y = t % 9;
+          i0[r] = (long long)kViFactorStride * f + kFH + 30 * (6 + x) + 21 + y;
+        } else if (e < nA + nO + nH) {
+          const int t = e - nA - nO, f = t / 216, q = (t % 216) / 18, c = t % 18;
+          i0[r] = (long long)kViFactorStride * f + kFH + 30 * hx_row(q) + hy_col(c);
+        } else if (e < ntot) {
+          const int t = e - nA - nO - nH, k = t / 9, x = t % 9;
+          if (k >= 1) i0[r] = (long long)kViFactorStride * (k - 1) + kFg + 21 + x;
+          if (k < nf) i1[r] = (long long)kViFactorStride * k + kFg + 6 + x;
+        }
+        v0[r] = F[i0[r] >= 0 ? i0[r] : 0];
+        v1[r] = F[i1[r] >= 0 ? i1[r] : 0];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = base + tid + r * (int)blockDim.x;
+        double v = 0.0;
+        if (i0[r] >= 0) v += v0[r];
+        if (i1[r] >= 0) v += v1[r];
+        if (e < nA) {
+          const int x = (e % 81) / 9, y = e % 9;
+          if (x == y) v += lam * fmax(v, 1e-9);
+          sA[e] = v;
+        } else if (e < nA + nO) {
+          sO[e - nA] = v;
+        } else if (e < nA + nO + nH) {
+          sH[e - nA - nO] = v;
+        } else if (e < ntot) {
+          sG[e - nA - nO - nH] = v;
+        }
+      }
+    }
   }
   // 2. the IMU cost at the current state (fixed order), for the first attempt
   if (tid == 0) {
+    double cf[kViMaxStates - 1];   // every factor's cost read before the sum
+#pragma unroll
+    for (int f = 0; f < kViMaxStates - 1; ++f) cf[f] = f < nf ? F[(size_t)kViFactorStride * f + kFc] : 0.0;
     double c = 0.0;
-    for (int f = 0; f < nf; ++f) c += F[(size_t)kViFactorStride * f + kFc];
+#pragma unroll
+    for (int f = 0; f < kViMaxStates - 1; ++f)
+      if (f < nf) c += cf[f];
     V.cost_a[wi] = c;
   }
   // pose-pose terms into the summed reduced system: upper entries of the
   // diagonal blocks, whole off-diagonal blocks (a, a + 1), -g into the rhs,
-  // the diagonal into diag(U) (the damping uses the whole diagonal)
+  // the diagonal into diag(U) (the damping uses the whole diagonal); every
+  // read of a thread's elements goes out before its first update
   const int nblk = W.n_free * (W.n_free + 1) / 2;
   double* S = V.ssum + W.sum_off;
-  double* sB = S + nblk * kBS;
-  double* sD = sB + nS;
-  for (int e = tid; e < N * 36; e += blockDim.x) {
-    const int a = e / 36, r = (e % 36) / 6, c = e % 6;
-    const int sa = fs[a];
-    if (sa < 0) continue;
-    // diagonal block (a, a): factor a - 1 as j (columns 15..20), factor a as i (0..5)
-    double v = 0.0;
-    if (a >= 1) v += F[(size_t)kViFactorStride * (a - 1) + kFH + 30 * (15 + r) + 15 + c];
-    if (a < nf) v += F[(size_t)kViFactorStride * a + kFH + 30 * r + c];
-    if (c >= r) S[kBS * blk_index(sa, sa, W.n_free) + 6 * r + c] += v;
-    if (c == r) sD[6 * sa + r] += v;
-    // off-diagonal block (a, a + 1) from factor a (rows x_i, columns x_j)
-    if (a < nf && fs[a + 1] >= 0)
-      S[kBS * blk_index(sa, fs[a + 1], W.n_free) + 6 * r + c] += F[(size_t)kViFactorStride * a + kFH + 30 * r + 15 + c];
-    if (c == 0) {
-      double gg = 0.0;
-      if (a >= 1) gg += F[(size_t)kViFactorStride * (a - 1) + kFg + 15 + r];
-      if (a < nf) gg += F[(size_t)kViFactorStride * a + kFg + r];
-      sB[6 * sa + r] -= gg;
+  double* sB = S + nblk * kBS;   // the reduced right-hand side (global)
+  for (int base = 0; base < N * 36; base += 2 * blockDim.x) {
+    double fv[2][5], sv[2][4];
+    long long so[2][4];
+    int sa_[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = base + tid + r * (int)blockDim.x;
+      const bool in = e < N * 36;
+      const int a = in ? e / 36 : 0, rr = (e % 36) / 6, c = e % 6;
+      const int sa = in ? fs[a] : -1;
+      sa_[r] = sa;
+      // F reads: diagonal-block terms of factors a - 1 and a, the off-diagonal
+      // block of factor a, the rhs terms of factors a - 1 and a
+      const long long fo[5] = {
+          a >= 1 ? (long long)kViFactorStride * (a - 1) + kFH + 30 * (15 + rr) + 15 + c : 0,
+          a < nf ? (long long)kViFactorStride * a + kFH + 30 * rr + c : 0,
+          a < nf ? (long long)kViFactorStride * a + kFH + 30 * rr + 15 + c : 0,
+          a >= 1 ? (long long)kViFactorStride * (a - 1) + kFg + 15 + rr : 0,
+          a < nf ? (long long)kViFactorStride * a + kFg + rr : 0};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) fv[r][q] = F[fo[q]];
+      const int sb = (sa >= 0 && a < nf) ? fs[a + 1] : -1;
+      so[r][0] = sa >= 0 && c >= rr ? (long long)kBS * blk_index(sa, sa, W.n_free) + 6 * rr + c : -1;
+      so[r][1] = sa >= 0 && sb >= 0 ? (long long)kBS * blk_index(sa, sb, W.n_free) + 6 * rr + c : -1;
+      so[r][2] = sa >= 0 && c == 0 ? (long long)(nblk * kBS + 6 * sa + rr) : -1;
+      so[r][3] = sa >= 0 && c == rr ? (long long)(nblk * kBS + nS + 6 * sa + rr) : -1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sv[r][q] = S[so[r][q] >= 0 ? so[r][q] : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = base + tid + r * (int)blockDim.x;
+      const int sa = sa_[r];
+      if (e >= N * 36 || sa < 0) continue;
+      const int a = e / 36, rr = (e % 36) / 6, c = e % 6;
+      double v = 0.0;
+      if (a >= 1) v += fv[r][0];
+      if (a < nf) v += fv[r][1];
+      if (so[r][0] >= 0) S[so[r][0]] = sv[r][0] + v;
+      if (so[r][3] >= 0) S[so[r][3]] = sv[r][3] + v;
+      if (so[r][1] >= 0) S[so[r][1]] = sv[r][1] + fv[r][2];
+      if (so[r][2] >= 0) {
+        double gg = 0.0;
+        if (a >= 1) gg += fv[r][3];
+        if (a < nf) gg += fv[r][4];
+        S[so[r][2]] = sv[r][2] - gg;
+      }
     }
   }
   __syncthreads();
@@ -610,9 +730,14 @@ __global__ __launch_bounds__(256) void k_vi_lin(ViArgs V, int wbase) {
   for (int k = 0; k < N; ++k) {
     if (k >= 1) {
       if (tid < 9) {   // row tid of C_k: L_{k-1} c = column tid of A_{k-1,k}
+        L9 F;
+        load_l9(sA + 81 * (k - 1), sInv + 9 * (k - 1), F);
         double row[9];
+#pragma unroll
         for (int y = 0; y < 9; ++y) row[y] = sO[81 * (k - 1) + 9 * y + tid];
-        lsolve9(sA + 81 * (k - 1), sInv + 9 * (k - 1), row);
+        vi_lds_fence(row);
+        lsolve9r(F, row);
+#pragma unroll
         for (int y = 0; y < 9; ++y) sC[81 * k + 9 * tid + y] = row[y];
       }
       __syncthreads();
@@ -625,11 +750,15 @@ __global__ __launch_bounds__(256) void k_vi_lin(ViArgs V, int wbase) {
       __syncthreads();
     }
     if (tid == 0) {
-      double Ak[81];
+      double Ak[81], iv[9];
+#pragma unroll
       for (int e = 0; e < 81; ++e) Ak[e] = sA[81 * k + e];
-      if (chol_n(Ak, 9)) {
+      vi_lds_fence(Ak);
+      if (chol9_regs(Ak, iv)) {
+#pragma unroll
         for (int e = 0; e < 81; ++e) sA[81 * k + e] = Ak[e];
-        for (int x = 0; x < 9; ++x) sInv[9 * k + x] = 1.0 / Ak[10 * x];
+#pragma unroll
+        for (int x = 0; x < 9; ++x) sInv[9 * k + x] = iv[x];
       } else {
         sOk = 0;
       }
@@ -641,57 +770,92 @@ __global__ __launch_bounds__(256) void k_vi_lin(ViArgs V, int wbase) {
     if (tid == 0) V.part_flag_a[W.chunk_begin] = 1;   // the reduce rejects the attempt
     return;
   }
-  // 4. one column of [H_yx | g_y] per thread: forward sweep
-  //    w_k = L_k^-1 (u_k - C_k w_{k-1}), backward u_k = L_k^-T (w_k - C_{k+1}^T u_{k+1});
-  //    a pose's column is zero above the state before it
-  for (int col = tid; col < ncol; col += blockDim.x) {
-    int a = 0, r = 0, k0 = 0;
-    if (col < nS) {
-      a = sPose[col / 6];
-      r = col % 6;
-      k0 = a >= 1 ? a - 1 : 0;
+  // 4. X = A^-1 [H_yx | g_y] by a forward sweep w_k = L_k^-1 (u_k - C_k w_{k-1})
+  //    and a backward sweep u_k = L_k^-T (w_k - C_{k+1}^T u_{k+1}) over the
+  //    states, all columns at once: per state, the coupling product (one
+  //    entry per thread) and then the triangular solve (one column per
+  //    thread), a barrier after each.  Columns above a pose's first state
+  //    stay exactly zero.  sO (A_{k,k+1}) is no longer needed and holds the
+  //    9 x ncol products.
+  double* sT = sO;
+  auto u_entry = [&](int k, int x, int col) -> double {
+    double v = 0.0;
+    if (col == nS) {
+      v = sG[9 * k + x];
+    } else {
+      // factor a - 1 holds pose a as x_j (rows 6 + r), factor a as x_i (rows r)
+      const int a = sPose[col / 6], r = col % 6;
+      if (a >= 1 && k == a - 1) v += sH[216 * (a - 1) + 18 * (6 + r) + x];
+      if (a >= 1 && k == a) v += sH[216 * (a - 1) + 18 * (6 + r) + 9 + x];
+      if (a < nf && k == a) v += sH[216 * a + 18 * r + x];
+      if (a < nf && k == a + 1) v += sH[216 * a + 18 * r + 9 + x];
     }
-    double w[9];
-    for (int x = 0; x < 9; ++x) w[x] = 0.0;
-    for (int k = k0; k < N; ++k) {
-      double u[9];
-      for (int x = 0; x < 9; ++x) {
-        double v = 0.0;
-        if (col == nS) {
-          v = sG[9 * k + x];
-        } else {
-          // factor a - 1 holds pose a as x_j (rows 6 + r), factor a as x_i (rows r)
-          if (a >= 1 && k == a - 1) v += sH[216 * (a - 1) + 18 * (6 + r) + x];
-          if (a >= 1 && k == a) v += sH[216 * (a - 1) + 18 * (6 + r) + 9 + x];
-          if (a < nf && k == a) v += sH[216 * a + 18 * r + x];
-          if (a < nf && k == a + 1) v += sH[216 * a + 18 * r + 9 + x];
+    return v;
+  };
+  for (int k = 0; k < N; ++k) {
+    for (int e = tid; e < 9 * ncol; e += blockDim.x) {
+      const int x = e / ncol, col = e - ncol * x;
+      double v = u_entry(k, x, col);
+      if (k >= 1) {
+        double c[9], wp[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          c[m] = sC[81 * k + 9 * x + m];
+          wp[m] = X[(size_t)ncol * (9 * (k - 1) + m) + col];
         }
-        if (k > k0)
-          for (int m = 0; m < 9; ++m) v -= sC[81 * k + 9 * x + m] * w[m];
-        u[x] = v;
+        vi_lds_fence(c);
+        vi_lds_fence(wp);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) v -= c[m] * wp[m];
       }
-      lsolve9(sA + 81 * k, sInv + 9 * k, u);
-      for (int x = 0; x < 9; ++x) {
-        w[x] = u[x];
-        X[(size_t)ncol * (9 * k + x) + col] = u[x];
-      }
+      sT[e] = v;
     }
-    for (int k = N - 1; k >= 0; --k) {
-      double v[9];
-      for (int x = 0; x < 9; ++x) {
-        double t = k >= k0 ? X[(size_t)ncol * (9 * k + x) + col] : 0.0;
-        if (k + 1 < N)
-          for (int m = 0; m < 9; ++m) t -= sC[81 * (k + 1) + 9 * m + x] * w[m];
-        v[x] = t;
-      }
-      ltsolve9(sA + 81 * k, sInv + 9 * k, v);
-      for (int x = 0; x < 9; ++x) {
-        w[x] = v[x];
-        X[(size_t)ncol * (9 * k + x) + col] = v[x];
-      }
+    __syncthreads();
+    for (int col = tid; col < ncol; col += blockDim.x) {
+      L9 F;
+      load_l9(sA + 81 * k, sInv + 9 * k, F);
+      double w[9];
+#pragma unroll
+      for (int x = 0; x < 9; ++x) w[x] = sT[ncol * x + col];
+      vi_lds_fence(w);
+      lsolve9r(F, w);
+#pragma unroll
+      for (int x = 0; x < 9; ++x) X[(size_t)ncol * (9 * k + x) + col] = w[x];
     }
+    __syncthreads();
   }
-  __syncthreads();
+  for (int k = N - 1; k >= 0; --k) {
+    for (int e = tid; e < 9 * ncol; e += blockDim.x) {
+      const int x = e / ncol, col = e - ncol * x;
+      double t = X[(size_t)ncol * (9 * k + x) + col];
+      if (k + 1 < N) {
+        double c[9], un[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          c[m] = sC[81 * (k + 1) + 9 * m + x];
+          un[m] = X[(size_t)ncol * (9 * (k + 1) + m) + col];
+        }
+        vi_lds_fence(c);
+        vi_lds_fence(un);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) t -= c[m] * un[m];
+      }
+      sT[e] = t;
+    }
+    __syncthreads();
+    for (int col = tid; col < ncol; col += blockDim.x) {
+      L9 F;
+      load_l9(sA + 81 * k, sInv + 9 * k, F);
+      double v[9];
+#pragma unroll
+      for (int x = 0; x < 9; ++x) v[x] = sT[ncol * x + col];
+      vi_lds_fence(v);
+      ltsolve9r(F, v);
+#pragma unroll
+      for (int x = 0; x < 9; ++x) X[(size_t)ncol * (9 * k + x) + col] = v[x];
+    }
+    __syncthreads();
+  }
   // 5. S <- S - H_xy X (upper blocks), rhs <- rhs + H_xy z; one row of a block
   //    (or of the rhs) per task
   auto hxy = [&](int a, int r, int k, int x) -> double {   // H(x_a row r, y_k component x)
@@ -726,6 +890,8 @@ __global__ __launch_bounds__(256) void k_vi_lin(ViArgs V, int wbase) {
       }
     for (int c = (sa == sb ? r : 0); c < 6; ++c) S[kBS * b + 6 * r + c] -= acc[c];
   }
+  if (XL)
+    for (int e = tid; e < 9 * N * ncol; e += blockDim.x) Xg[e] = sXd[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -782,7 +948,21 @@ hipError_t launch_vi_preint(int n_factors, const int32_t* sample_begin, const do
 void launch_vi_lin(const ViArgs& V, int wbase, int nwin, hipStream_t st) {
   if (nwin <= 0 || V.max_factors <= 0) return;
   hipLaunchKernelGGL(k_vi_fac, dim3(V.max_factors, nwin), dim3(64), 0, st, V, wbase);
-  hipLaunchKernelGGL(k_vi_lin, dim3(nwin), dim3(256), 0, st, V, wbase);
+  // X (9N x (6 n_free + 1) doubles, n_free <= N) in LDS beside the static
+  // arrays when the CU's 160 KB hold both
+  constexpr size_t kStatic = sizeof(double) * (size_t)(kViMaxStates * (81 + 81 + 9 + 9) + (kViMaxStates - 1) * (81 + 216)) +
+                             sizeof(int) * (kViMaxStates + 1);
+  const int N = V.max_factors + 1;
+  const size_t xb = sizeof(double) * 9 * (size_t)N * (6 * (size_t)N + 1);
+  static bool attr = false;
+  if (!attr) {
+    attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vi_lin<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)kStatic - 256) == hipSuccess;
+  }
+  if (attr && kStatic + xb + 256 <= 160 * 1024)
+    hipLaunchKernelGGL(k_vi_lin<true>, dim3(nwin), dim3(kViLinThreads), xb, st, V, wbase);
+  else
+    hipLaunchKernelGGL(k_vi_lin<false>, dim3(nwin), dim3(kViLinThreads), 0, st, V, wbase);
 }
 
 void launch_vi_cand(const ViArgs& V, int wbase, int nwin, hipStream_t st) {
