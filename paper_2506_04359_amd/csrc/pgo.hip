@@ -436,14 +436,30 @@ __device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, i
       const int q0 = G.chunk_ptr[b], q1 = G.chunk_ptr[b + 1];
       if (q0 == q1) continue;
       double v = W.L[36 * (long long)b + e];
-      for (int q = q0; q < q1; ++q) v -= W.part[36 * (long long)q + e];
+      int q = q0;
+      for (; q + 4 <= q1; q += 4) {   // four reads in flight, subtracted in order
+        double p[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = W.part[36 * (long long)(q + k) + e];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v -= p[k];
+      }
+      for (; q < q1; ++q) v -= W.part[36 * (long long)q + e];
       W.L[36 * (long long)b + e] = v;
     } else {
       const int c = c0 + (t - nb) / 6, a = (t - nb) % 6;
       const int q0 = G.fchunk_ptr[c], q1 = G.fchunk_ptr[c + 1];
       if (q0 == q1) continue;
       double v = W.y[6 * c + a];
-      for (int q = q0; q < q1; ++q) v -= fpart[6 * (long long)q + a];
+      int q = q0;
+      for (; q + 4 <= q1; q += 4) {
+        double p[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = fpart[6 * (long long)(q + k) + a];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v -= p[k];
+      }
+      for (; q < q1; ++q) v -= fpart[6 * (long long)q + a];
       W.y[6 * c + a] = v;
     }
   }
@@ -467,7 +483,20 @@ __device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, i
 #pragma unroll
     for (int a = 0; a < 6; ++a) yc[a] = W.y[6 * c + a];
     if constexpr (SUM) {
-      for (int q = G.chunk_ptr[bd]; q < G.chunk_ptr[bd + 1]; ++q)
+      // two chunks' partials read before either is subtracted (in order)
+      const int q1 = G.chunk_ptr[bd + 1];
+      int q = G.chunk_ptr[bd];
+      for (; q + 2 <= q1; q += 2) {
+        double p0[36], p1[36];
+#pragma unroll
+        for (int k = 0; k < 36; ++k) {
+          p0[k] = W.part[36 * (long long)q + k];
+          p1[k] = W.part[36 * (long long)(q + 1) + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 36; ++k) m[k] = (m[k] - p0[k]) - p1[k];
+      }
+      for (; q < q1; ++q)
 #pragma unroll
         for (int k = 0; k < 36; ++k) m[k] -= W.part[36 * (long long)q + k];
       for (int q = G.fchunk_ptr[c]; q < G.fchunk_ptr[c + 1]; ++q)
@@ -513,10 +542,24 @@ __device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, i
       double x[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) x[k] = row[k];
-      if constexpr (SUM)
-        for (int q = G.chunk_ptr[b]; q < G.chunk_ptr[b + 1]; ++q)
+      if constexpr (SUM) {
+        const int q1 = G.chunk_ptr[b + 1];
+        int q = G.chunk_ptr[b];
+        for (; q + 4 <= q1; q += 4) {   // four chunks' rows in flight, in order
+          double p[4][6];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) p[j][k] = W.part[36 * (long long)(q + j) + 6 * a + k];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) x[k] -= p[j][k];
+        }
+        for (; q < q1; ++q)
 #pragma unroll
           for (int k = 0; k < 6; ++k) x[k] -= W.part[36 * (long long)q + 6 * a + k];
+      }
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         double v = x[k];
