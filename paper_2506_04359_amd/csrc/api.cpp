@@ -864,7 +864,8 @@ ba_status ba_graph_create(int32_t n_poses, int32_t n_edges, const int32_t* edge_
                o_ap = blob.add(P.asm_ptr), o_ae = blob.add(P.asm_edge), o_rp = blob.add(P.rhs_ptr),
                o_re = blob.add(P.rhs_edge), o_ei = blob.add(P.edge_i), o_ej = blob.add(P.edge_j),
                o_bc = blob.add(P.blk_col), o_cp = blob.add(P.chunk_ptr), o_cb = blob.add(P.chunk_blk),
-               o_fcp = blob.add(P.fchunk_ptr), o_fcc = blob.add(P.fchunk_col);
+               o_fcp = blob.add(P.fchunk_ptr), o_fcc = blob.add(P.fchunk_col),
+               o_cab = blob.add(P.chunk_ab), o_fbc = blob.add(P.fchunk_bc);
   hipError_t e = hipGetDevice(&g->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   e = hipMalloc(&g->mem, blob.size);
@@ -907,6 +908,8 @@ ba_status ba_graph_create(int32_t n_poses, int32_t n_edges, const int32_t* edge_
   D.chunk_blk = at(o_cb);
   D.fchunk_ptr = at(o_fcp);
   D.fchunk_col = at(o_fcc);
+  D.chunk_ab = at(o_cab);
+  D.fchunk_bc = at(o_fbc);
   D.n_chunks = (int)P.chunk_blk.size();
   D.n_fchunks = (int)P.fchunk_col.size();
   D.n_wide = P.n_wide;

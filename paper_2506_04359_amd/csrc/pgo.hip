@@ -367,48 +367,46 @@ __device__ __forceinline__ void pgo_phase1_range(const PgoDev& G, const PgoWork&
   for (int t = t0; t < nq + (f1 - f0) * 6; t += stride) {
     if (t < nq) {
       const int q = q0 + t / 36, e = t % 36, a = e / 6, c = e % 6;
-      const int b = G.chunk_blk[q];
-      const int u0 = G.upd_ptr[b] + kPgoChunk * (q - G.chunk_ptr[b]);
-      const int u1 = min(u0 + kPgoChunk, G.upd_ptr[b + 1]);
+      // the chunk's block pairs in one read (-1 past the list's end; those
+      // entries read the first pair and add nothing)
+      const int32_t* ab = G.chunk_ab + 2 * kPgoChunk * (long long)q;
       int ia[kPgoChunk], ib[kPgoChunk];
 #pragma unroll
       for (int k = 0; k < kPgoChunk; ++k) {
-        const int u = u0 + k < u1 ? u0 + k : u0;
-        ia[k] = G.upd_a[u];
-        ib[k] = G.upd_b[u];
+        ia[k] = ab[k];
+        ib[k] = ab[kPgoChunk + k];
       }
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < kPgoChunk; ++k) {
-        const double* La = W.L + 36 * (long long)ia[k] + 6 * a;
-        const double* Lb = W.L + 36 * (long long)ib[k] + 6 * c;
+        const bool on = ia[k] >= 0;
+        const double* La = W.L + 36 * (long long)(on ? ia[k] : ia[0]) + 6 * a;
+        const double* Lb = W.L + 36 * (long long)(on ? ib[k] : ib[0]) + 6 * c;
         double s = 0.0;
 #pragma unroll
         for (int m = 0; m < 6; ++m) s += La[m] * Lb[m];
-        acc += (u0 + k < u1) ? s : 0.0;
+        acc += on ? s : 0.0;
       }
       W.part[36 * (long long)q + e] = acc;
     } else {
       const int fq = f0 + (t - nq) / 6, a = (t - nq) % 6;
-      const int c = G.fchunk_col[fq];
-      const int g0 = G.fwd_ptr[c] + kPgoChunk * (fq - G.fchunk_ptr[c]);
-      const int g1 = min(g0 + kPgoChunk, G.fwd_ptr[c + 1]);
+      const int32_t* bc = G.fchunk_bc + 2 * kPgoChunk * (long long)fq;
       int ib[kPgoChunk], ik[kPgoChunk];
 #pragma unroll
       for (int k = 0; k < kPgoChunk; ++k) {
-        const int f = g0 + k < g1 ? g0 + k : g0;
-        ib[k] = G.fwd_blk[f];
-        ik[k] = G.fwd_col[f];
+        ib[k] = bc[k];
+        ik[k] = bc[kPgoChunk + k];
       }
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < kPgoChunk; ++k) {
-        const double* Lf = W.L + 36 * (long long)ib[k] + 6 * a;
-        const double* yk = W.y + 6 * ik[k];
+        const bool on = ib[k] >= 0;
+        const double* Lf = W.L + 36 * (long long)(on ? ib[k] : ib[0]) + 6 * a;
+        const double* yk = W.y + 6 * (on ? ik[k] : ik[0]);
         double s = 0.0;
 #pragma unroll
         for (int m = 0; m < 6; ++m) s += Lf[m] * yk[m];
-        acc += (g0 + k < g1) ? s : 0.0;
+        acc += on ? s : 0.0;
       }
       fpart[6 * (long long)fq + a] = acc;
     }

@@ -18,6 +18,7 @@ struct PgoDev {
   const int32_t *upd_ptr, *upd_a, *upd_b, *fwd_ptr, *fwd_blk, *fwd_col;
   const int32_t *asm_ptr, *asm_edge, *rhs_ptr, *rhs_edge, *edge_i, *edge_j;
   const int32_t *blk_col, *chunk_ptr, *chunk_blk, *fchunk_ptr, *fchunk_col;
+  const int32_t *chunk_ab, *fchunk_bc;
   int n_chunks, n_fchunks;
   int n_wide;
 };

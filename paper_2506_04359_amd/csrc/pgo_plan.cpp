@@ -290,6 +290,26 @@ std::string build_pgo_plan(int32_t n_poses, int32_t n_edges, const int32_t* edge
     P.fchunk_ptr[c + 1] = P.fchunk_ptr[c] + (n + kPgoChunk - 1) / kPgoChunk;
     for (int q = P.fchunk_ptr[c]; q < P.fchunk_ptr[c + 1]; ++q) P.fchunk_col.push_back(c);
   }
+  P.chunk_ab.assign(P.chunk_blk.size() * 2 * kPgoChunk, -1);
+  for (int b = 0; b < nb; ++b)
+    for (int q = P.chunk_ptr[b]; q < P.chunk_ptr[b + 1]; ++q) {
+      const int u0 = P.upd_ptr[b] + kPgoChunk * (q - P.chunk_ptr[b]);
+      const int u1 = std::min(u0 + kPgoChunk, P.upd_ptr[b + 1]);
+      for (int k = 0; u0 + k < u1; ++k) {
+        P.chunk_ab[(size_t)2 * kPgoChunk * q + k] = P.upd_a[u0 + k];
+        P.chunk_ab[(size_t)2 * kPgoChunk * q + kPgoChunk + k] = P.upd_b[u0 + k];
+      }
+    }
+  P.fchunk_bc.assign(P.fchunk_col.size() * 2 * kPgoChunk, -1);
+  for (int c = 0; c < nf; ++c)
+    for (int q = P.fchunk_ptr[c]; q < P.fchunk_ptr[c + 1]; ++q) {
+      const int g0 = P.fwd_ptr[c] + kPgoChunk * (q - P.fchunk_ptr[c]);
+      const int g1 = std::min(g0 + kPgoChunk, P.fwd_ptr[c + 1]);
+      for (int k = 0; g0 + k < g1; ++k) {
+        P.fchunk_bc[(size_t)2 * kPgoChunk * q + k] = P.fwd_blk[g0 + k];
+        P.fchunk_bc[(size_t)2 * kPgoChunk * q + kPgoChunk + k] = P.fwd_col[g0 + k];
+      }
+    }
   // leading levels whose update phase has at least 4096 tasks run as
   // launches over the whole GPU
   for (int l = 0; l < P.n_levels; ++l) {

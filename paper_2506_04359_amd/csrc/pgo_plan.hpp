@@ -40,6 +40,10 @@ struct PgoPlan {
   int n_wide = 0;
   std::vector<int32_t> wide_tasks;
   std::vector<int32_t> chunk_ptr, chunk_blk, fchunk_ptr, fchunk_col;
+  // per chunk its kPgoChunk block pairs (L_rk ids, then L_ck ids) and per
+  // forward chunk its (block, column) pairs, -1 past the list's end: a
+  // chunk's thread reads its whole list at once
+  std::vector<int32_t> chunk_ab, fchunk_bc;
   int n_blocks() const { return (int)blk_row.size(); }
 };
 
