@@ -413,19 +413,34 @@ __device__ __forceinline__ void pgo_phase1_range(const PgoDev& G, const PgoWork&
   }
 }
 
-// Phase (1) of level l (all its columns' chunks).
-__device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
-  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
-  pgo_phase1_range(G, W, G.chunk_ptr[b0], G.chunk_ptr[b1], G.fchunk_ptr[c0], G.fchunk_ptr[c1], t0, stride);
+// Index ranges of level l: columns, blocks, update chunks, forward chunks.
+struct PgoLevel {
+  int c0, c1, b0, b1, q0, q1, f0, f1;
+};
+__device__ __forceinline__ PgoLevel pgo_level(const PgoDev& G, int l) {
+  PgoLevel v;
+  v.c0 = G.lev_ptr[l];
+  v.c1 = G.lev_ptr[l + 1];
+  v.b0 = G.blk_ptr[v.c0];
+  v.b1 = G.blk_ptr[v.c1];
+  v.q0 = G.chunk_ptr[v.b0];
+  v.q1 = G.chunk_ptr[v.b1];
+  v.f0 = G.fchunk_ptr[v.c0];
+  v.f1 = G.fchunk_ptr[v.c1];
+  return v;
+}
+
+// Phase (1) of a level (all its columns' chunks).
+__device__ __forceinline__ void pgo_phase1(const PgoDev& G, const PgoWork& W, const PgoLevel& v, int t0, int stride) {
+  pgo_phase1_range(G, W, v.q0, v.q1, v.f0, v.f1, t0, stride);
 }
 
 // The level's partials subtracted from its blocks and right-hand sides, one
 // entry per thread, in chunk order (the narrow levels' variant of the sums
 // that phases 2 and 3 otherwise do per column / row).
-__device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, int l, int t0, int stride) {
-  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
-  const int b0 = G.blk_ptr[c0], b1 = G.blk_ptr[c1];
+__device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, const PgoLevel& v, int t0,
+                                            int stride) {
+  const int c0 = v.c0, c1 = v.c1, b0 = v.b0, b1 = v.b1;
   const double* fpart = W.part + 36 * (long long)G.n_chunks;
   const int nb = (b1 - b0) * 36;
   for (int t = t0; t < nb + (c1 - c0) * 6; t += stride) {
@@ -468,9 +483,8 @@ __device__ __forceinline__ void pgo_phase1b(const PgoDev& G, const PgoWork& W, i
 // finishes the forward step, then the lanes solve the column's panel rows.
 // With SUM the chunk partials are subtracted here (the wide levels).
 template <bool SUM>
-__device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, int l, int w0, int nw, int lane,
-                                            int* sfail = nullptr) {
-  const int c0 = G.lev_ptr[l], c1 = G.lev_ptr[l + 1];
+__device__ __forceinline__ void pgo_phase23(const PgoDev& G, const PgoWork& W, int c0, int c1, int w0, int nw,
+                                            int lane, int* sfail = nullptr) {
   const double* fpart = W.part + 36 * (long long)G.n_chunks;
   for (int c = c0 + w0; c < c1; c += nw) {
     const int bd = G.blk_ptr[c];
@@ -588,7 +602,8 @@ __global__ __launch_bounds__(kPgoEdgeThreads) void k_pgo_wide(PgoArgs A, int l) 
   pgo_phase1_range(G, A.W, G.chunk_ptr[bA], G.chunk_ptr[bB], G.fchunk_ptr[c], G.fchunk_ptr[c + 1], threadIdx.x,
                    kPgoEdgeThreads);
   __syncthreads();
-  if (threadIdx.x < 64) pgo_phase23<true>(G, A.W, l, blockIdx.x, gridDim.x, threadIdx.x);
+  if (threadIdx.x < 64)
+    pgo_phase23<true>(G, A.W, G.lev_ptr[l], G.lev_ptr[l + 1], blockIdx.x, gridDim.x, threadIdx.x);
 }
 
 // Levels [l0, n_levels) in one workgroup, then the back substitution.
@@ -599,15 +614,24 @@ __global__ __launch_bounds__(kPgoStepThreads) void k_pgo_factor(PgoArgs A, int l
   // a failed pivot of the wide levels (earlier launches) or of this one,
   // mirrored in LDS so that the level loop reads no flag from memory
   __shared__ int sFail;
+  // the narrow levels' index ranges, read once (level by level in parallel)
+  // instead of by every phase of every level
+  constexpr int kLevCache = 128;
+  __shared__ PgoLevel sLv[kLevCache];
+  const int nlv = G.n_levels - l0;
+  const bool cached = nlv <= kLevCache;
   if (tid == 0) sFail = W.istate[4];
+  if (cached)
+    for (int i = tid; i < nlv; i += kPgoStepThreads) sLv[i] = pgo_level(G, l0 + i);
   __syncthreads();
   for (int l = l0; l < G.n_levels; ++l) {
     if (sFail) break;
-    pgo_phase1(G, W, l, tid, kPgoStepThreads);
+    const PgoLevel lv = cached ? sLv[l - l0] : pgo_level(G, l);
+    pgo_phase1(G, W, lv, tid, kPgoStepThreads);
     __syncthreads();
-    pgo_phase1b(G, W, l, tid, kPgoStepThreads);
+    pgo_phase1b(G, W, lv, tid, kPgoStepThreads);
     __syncthreads();
-    pgo_phase23<false>(G, W, l, tid >> 6, kPgoStepThreads / 64, tid & 63, &sFail);
+    pgo_phase23<false>(G, W, lv.c0, lv.c1, tid >> 6, kPgoStepThreads / 64, tid & 63, &sFail);
     __syncthreads();
   }
   if (sFail) {
