@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "device.hpp"
 #include "geometry.hpp"
@@ -954,11 +955,14 @@ void launch_vi_lin(const ViArgs& V, int wbase, int nwin, hipStream_t st) {
                              sizeof(int) * (kViMaxStates + 1);
   const int N = V.max_factors + 1;
   const size_t xb = sizeof(double) * 9 * (size_t)N * (6 * (size_t)N + 1);
+  // the dynamic LDS limit of the LDS variant is raised once per process (as
+  // for the other kernels); if that fails, X stays in the workspace
+  static std::once_flag once;
   static bool attr = false;
-  if (!attr) {
+  std::call_once(once, [] {
     attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vi_lin<true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)kStatic - 256) == hipSuccess;
-  }
+  });
   if (attr && kStatic + xb + 256 <= 160 * 1024)
     hipLaunchKernelGGL(k_vi_lin<true>, dim3(nwin), dim3(kViLinThreads), xb, st, V, wbase);
   else
