@@ -258,7 +258,7 @@ ba_status ba_adjoint(ba_window w, ba_batch b, const ba_settings* s, const double
                      double* grad_w, void* workspace, size_t ws_bytes, ba_report* reports,
                      void* stream);
 
-/* Launch shape of a plan's batched solve (the a11 schedule: one launch per
+/* Launch shape of a plan's batched solve (one launch per
  * stage and size class).  Defaults: chunk_obs from the plan's size,
  * tile_pairs 0, every class_chunk_mult 1, class_streams 1. */
 typedef struct {

@@ -1,4 +1,4 @@
-"""Launch shapes of the batched solve (the a11 schedule): the shape is read
+"""Launch shapes of the batched solve (one launch per stage and size class): the shape is read
 back as set, invalid shapes are refused without changing the plan, every shape
 solves to the mixed-precision bar against the oracle, running the size
 classes on one stream instead of as concurrent chains changes nothing (bit for
