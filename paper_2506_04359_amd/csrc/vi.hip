@@ -950,20 +950,26 @@ void launch_vi_lin(const ViArgs& V, int wbase, int nwin, hipStream_t st) {
   if (nwin <= 0 || V.max_factors <= 0) return;
   hipLaunchKernelGGL(k_vi_fac, dim3(V.max_factors, nwin), dim3(64), 0, st, V, wbase);
   // X (9N x (6 n_free + 1) doubles, n_free <= N) in LDS beside the static
-  // arrays when the CU's 160 KB hold both
-  constexpr size_t kStatic = sizeof(double) * (size_t)(kViMaxStates * (81 + 81 + 9 + 9) + (kViMaxStates - 1) * (81 + 216)) +
-                             sizeof(int) * (kViMaxStates + 1);
+  // arrays when the CU's 160 KB hold both.  The static size is the compiled
+  // kernel's own (asked once per process, when its dynamic LDS limit is
+  // raised, as for the other kernels); if either call fails, X stays in the
+  // workspace.
+  constexpr size_t kLds = 160 * 1024;
   const int N = V.max_factors + 1;
   const size_t xb = sizeof(double) * 9 * (size_t)N * (6 * (size_t)N + 1);
-  // the dynamic LDS limit of the LDS variant is raised once per process (as
-  // for the other kernels); if that fails, X stays in the workspace
   static std::once_flag once;
   static bool attr = false;
+  static size_t kStatic = kLds;
   std::call_once(once, [] {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_vi_lin<true>)) != hipSuccess ||
+        fa.sharedSizeBytes >= kLds)
+      return;
+    kStatic = fa.sharedSizeBytes;
     attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vi_lin<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)kStatic - 256) == hipSuccess;
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLds - kStatic)) == hipSuccess;
   });
-  if (attr && kStatic + xb + 256 <= 160 * 1024)
+  if (attr && kStatic + xb <= kLds)
     hipLaunchKernelGGL(k_vi_lin<true>, dim3(nwin), dim3(kViLinThreads), xb, st, V, wbase);
   else
     hipLaunchKernelGGL(k_vi_lin<false>, dim3(nwin), dim3(kViLinThreads), 0, st, V, wbase);
