@@ -121,6 +121,18 @@ def test_plan_is_landmark_major_permutation():
     assert info["schur_blocks"] == int(np.sum(nfree * (nfree + 1) // 2))
 
 
+def test_single_window_plans_spread_work_items():
+    # a plan of one window has nothing to run beside it: its work items aim at
+    # n_obs / 256 observations (at least 128, at most 8192), whole tiles each
+    for cfg in (1, 2, 4):
+        w = bagen.make_window(cfg)
+        i = _mk(w).info()
+        co = max(128, min(8192, w.n_obs // 256))
+        want = max(1, (w.n_obs + co // 2) // co)
+        assert i["n_chunks"] == min(want, i["n_tiles"]), (cfg, i)
+        assert i["n_chunks"] > 1
+
+
 def test_host_only_window_cannot_be_solved():
     import paper_2506_04359_amd as ba
     w = bagen.tiny_window(seed=4)
